@@ -19,9 +19,10 @@ Quantum-Classical Dual Kernel"):
   ``closed_form``;
 * an exact path-sum transfer chain over computational-basis histories, for
   any qubit count and up to three layers -- ``pathsum``;
-* the MPS simulation: per-sample TEBD build with QR canonicalisation and
-  SVD bond truncation, and the pairwise transfer-matrix overlap sweep with
-  power-of-two rescaling -- ``mps``;
+* the MPS simulation: per-sample TEBD build (entangler chains swept in
+  alternating directions, SVD bond truncation at the orthogonality centre),
+  and the pairwise transfer-matrix overlap sweep with power-of-two
+  rescaling -- ``mps``;
 * the RBF kernel of Eq. (3) and the linear mix of Eq. (11) --
   ``classical``;
 * kernel invariants and the tolerance gates used by the parity tests --

@@ -3,22 +3,27 @@
 Site tensors use the index order (left bond, physical, right bond); bond 0
 and bond n have dimension 1.
 
-Build (per sample, FP64), following the time-evolving-block-decimation
-scheme the tensor-network route of Section II-C relies on: for each of the L
-layers,
+Build (per sample, FP64), a time-evolving-block-decimation replay of the
+circuit (the paper contracts the overlap network exactly, Section II-C; the
+MPS route reaches the same K_q and makes the work linear in the sample
+count). Start from the product state |0...0>, every bond 1. For layer
+l = 1..L:
 
-1. apply G_k = RZ(2 x_k) H to the physical index of every site (a unitary
-   on that index keeps any canonical form);
-2. right-canonicalise: for k = n-1 .. 1, factor the site matrix
-   A_k[(l), (s r)] = R Q with Q row-orthonormal (via a reduced QR of its
-   conjugate transpose), keep Q as site k and push R into site k-1, so the
-   orthogonality centre ends at site 0;
-3. left to right, k = 0 .. n-2: merge the centre with its right neighbour,
-   Theta[(l s), (t r)] = sum_b A_k[l,s,b] A_{k+1}[b,t,r], multiply the
-   diagonal RZZ phase exp(-i theta_k/2 sigma_s sigma_t), take its SVD
-   U S V^dagger, keep the singular values s_j > cutoff * s_0 (at most
-   chi_max, largest first), renormalise the kept values to unit norm, and
-   set A_k = U (left-canonical), A_{k+1} = S V^dagger (the new centre).
+1. apply G_k = RZ(2 x_k) H to the physical index of every site (a unitary on
+   that index keeps any canonical form and the orthogonality centre);
+2. apply the RZZ chain as two-site steps along the chain, left to right on
+   odd layers (k = 0..n-2) and right to left on even layers (k = n-2..0), so
+   the orthogonality centre is always one of the two sites merged:
+   Theta[(l s), (t r)] = sum_b A_k[l,s,b] A_{k+1}[b,t,r] times the diagonal
+   phase exp(-i theta_k/2 sigma_s sigma_t); SVD Theta = U S V^dagger; keep
+   the singular values s_j > cutoff * s_0 (at most chi_max, largest first);
+   renormalise the kept values to unit norm; then
+   left-to-right:  A_k = U (left-canonical),  A_{k+1} = S V^dagger (centre);
+   right-to-left:  A_k = U S (centre),        A_{k+1} = V^dagger.
+
+The entanglers of one layer commute, so the sweep direction changes nothing
+when no bond is truncated; alternating directions removes the separate
+canonicalisation pass a fixed direction would need.
 
 Truncation is per sample, so every sample stays a normalised state and the
 Gram matrix of the truncated states is still a Gram matrix (PSD, unit
@@ -55,23 +60,17 @@ def build_mps(x, n_layers: int, chi_max: int, cutoff: float = 1e-10,
         A.append(t)
     theta = rzz_angles(x) if (entangle and n > 1) else np.zeros(max(n - 1, 0))
     discarded = 0.0
-    for _ in range(n_layers):
+    for layer in range(n_layers):
         # 1. single-qubit layer
         for k in range(n):
             g = rz(2.0 * x[k]) @ HADAMARD
             A[k] = np.einsum("st,atb->asb", g, A[k])
         if n == 1:
             continue
-        # 2. right-canonicalise, centre -> site 0
-        for k in range(n - 1, 0, -1):
-            chl, _, chr_ = A[k].shape
-            m = A[k].reshape(chl, 2 * chr_)
-            q, r = np.linalg.qr(m.conj().T)          # m^dagger = q r
-            rk = q.shape[1]
-            A[k] = q.conj().T.reshape(rk, 2, chr_)    # m = r^dagger q^dagger
-            A[k - 1] = np.tensordot(A[k - 1], r.conj().T, axes=([2], [0]))
-        # 3. left-to-right entangler pass with SVD truncation
-        for k in range(n - 1):
+        # 2. entangler chain, direction alternating with the layer
+        left_to_right = (layer % 2 == 0)
+        order = range(n - 1) if left_to_right else range(n - 2, -1, -1)
+        for k in order:
             chl = A[k].shape[0]
             chr_ = A[k + 1].shape[2]
             th = np.tensordot(A[k], A[k + 1], axes=([2], [0]))  # (l, s, t, r)
@@ -84,8 +83,12 @@ def build_mps(x, n_layers: int, chi_max: int, cutoff: float = 1e-10,
             discarded += float(np.sum(s[keep:] ** 2) / np.sum(s ** 2))
             u, s, vh = u[:, :keep], s[:keep], vh[:keep]
             s = s / np.linalg.norm(s)
-            A[k] = u.reshape(chl, 2, keep)
-            A[k + 1] = (s[:, None] * vh).reshape(keep, 2, chr_)
+            if left_to_right:
+                A[k] = u.reshape(chl, 2, keep)
+                A[k + 1] = (s[:, None] * vh).reshape(keep, 2, chr_)
+            else:
+                A[k] = (u * s[None, :]).reshape(chl, 2, keep)
+                A[k + 1] = vh.reshape(keep, 2, chr_)
     chis = [1] + [A[k].shape[2] for k in range(n)]
     if return_discarded:
         return A, chis, discarded
