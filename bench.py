@@ -1,0 +1,232 @@
+#!/usr/bin/env python
+"""Benchmark of the dual-kernel hot path on one MI355X.
+
+Workload (one step = one pass of the whole hot path): 784-qubit synthetic
+28x28 "images" (10 classes, seeded smooth field per class + pixel noise,
+scaled to [0, pi]), 4000 training + 1000 test samples, 2 layers, chi_max 64,
+cutoff 1e-10. A step builds the MPS of all 5000 samples on the device
+(TEBD, FP64), packs them, and runs ONE persistent sweep launch over the
+train x train upper triangle (diagonal included) and the test x train
+rectangle with the fused epilogue (ln K_q, K_q, K_c with gamma = 1/d, and
+K = 0.5 K_q + 0.5 K_c, all FP64). Inputs are resident in HBM before timing.
+
+value = unique pairs per second = (4000*4001/2 + 1000*4000) / seconds per step.
+
+The plain complex-FP64 sweep runs the same step as the comparator; the CPU
+oracle is timed on a bounded sample on the host cores (cpu_baseline).
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {  # published MI355X figures, TFLOP/s
+    "fp64": ("alu", 78.6), "fp32": ("alu", 157.3), "fp32_mfma": ("mfma", 157.3),
+    "bf16x2": ("mfma", 2500.0), "bf16x3": ("mfma", 2500.0),
+}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp32_mfma": "f32", "bf16x2": "bf16", "bf16x3": "bf16"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(chi_rows, chi_cols, symmetric):
+    """Sum over pairs of sum_k 16 (cA_k cB_k cB_{k+1} + cA_{k+1} cA_k cB_{k+1})
+    on realized bond dimensions (8 real FLOP per complex MAC)."""
+    import numpy as np
+    A = chi_rows.astype(np.float64)
+    B = chi_cols.astype(np.float64)
+    # per-sample site features
+    a0, a1 = A[:, :-1], A[:, 1:]
+    b0, b1 = B[:, :-1], B[:, 1:]
+    # term1: cA_k * (cB_k cB_{k+1}); term2: (cA_{k+1} cA_k) * cB_{k+1}
+    t1 = a0.sum(0) * (b0 * b1).sum(0)
+    t2 = (a1 * a0).sum(0) * b1.sum(0)
+    total = 16.0 * float((t1 + t2).sum())
+    if symmetric:
+        # upper triangle with diagonal: (full + diagonal) / 2
+        diag = 16.0 * float(((a0 * b0 * b1) + (a1 * a0 * b1)).sum())
+        total = 0.5 * (total + diag)
+    return total
+
+
+def cpu_baseline(x_tr, seconds_target=15.0):
+    """Time the FP64 oracle on a bounded sample with a process pool."""
+    import multiprocessing as mp
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    n_build, n_pairs = 4, 1536
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores, initializer=_pool_init) as pool:
+        res = pool.map(_oracle_chunk, [(x_tr[(4 * w) % (len(x_tr) - 4):][:n_build], n_pairs)
+                                       for w in range(cores)])
+    wall = time.perf_counter() - t0
+    build_s = max(r[0] for r in res)
+    sweep_s = max(r[1] for r in res)
+    build_rate = cores * n_build / build_s        # samples / s
+    sweep_rate = cores * n_pairs / sweep_s        # pairs / s
+    pairs = 4000 * 4001 // 2 + 1000 * 4000
+    job_s = 5000 / build_rate + pairs / sweep_rate
+    return {"value": pairs / job_s, "unit": "entries/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{cores} processes x ({n_build} TEBD builds + {n_pairs} FP64 pair "
+                       f"sweeps) at d=784, L=2; wall {wall:.1f}s; whole-job rate "
+                       f"extrapolated to 5000 builds + {pairs} pairs")}
+
+
+def _pool_init():
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+
+
+def _oracle_chunk(args):
+    import numpy as np
+    from oracle import mps
+    xs, n_pairs = args
+    t0 = time.perf_counter()
+    M = mps.build_batch(xs, 2, 64)
+    t1 = time.perf_counter()
+    P = mps.pad_batch(M)
+    rng = np.random.default_rng(0)
+    pairs = rng.integers(len(xs), size=(n_pairs, 2))
+    mps.ln_kernel_pairs(P, P, pairs)
+    t2 = time.perf_counter()
+    return t1 - t0, t2 - t1
+
+
+def run(args):
+    import numpy as np
+    import torch
+
+    import paper_2602_01330_amd.qk as qk
+    from synthdata import config_inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("bench: generating inputs")
+    x_tr, x_te, _ = config_inputs("C3")
+    d = x_tr.shape[1]
+    xtr = torch.as_tensor(x_tr, device=dev)
+    xte = torch.as_tensor(x_te, device=dev)
+    ntr, nte = xtr.shape[0], xte.shape[0]
+    pairs = ntr * (ntr + 1) // 2 + nte * ntr
+    f64 = dict(dtype=torch.float64, device=dev)
+    out = {k: torch.empty((ntr, ntr), **f64) for k in ("kq", "ln", "kc", "k")}
+    out_te = {k: torch.empty((nte, ntr), **f64) for k in ("kq", "ln", "kc", "k")}
+    stream = torch.cuda.current_stream()
+
+    def one_step(prec, timing=None):
+        store = qk.QK_STORE_FP64 if prec == "fp64" else qk.QK_STORE_FP32
+        btr = qk.qk_mps_build(xtr, 2, 64, 1e-10, store=store)
+        bte = qk.qk_mps_build(xte, 2, 64, 1e-10, store=store)
+        tasks = [
+            {"rows": btr, "cols": btr, "symmetric": True, "kq": out["kq"], "lnkq": out["ln"],
+             "fuse": {"x_rows": xtr, "x_cols": xtr, "gamma": 1.0 / d, "w": 0.5,
+                      "kc": out["kc"], "k": out["k"]}},
+            {"rows": bte, "cols": btr, "symmetric": False, "kq": out_te["kq"],
+             "lnkq": out_te["ln"],
+             "fuse": {"x_rows": xte, "x_cols": xtr, "gamma": 1.0 / d, "w": 0.5,
+                      "kc": out_te["kc"], "k": out_te["k"]}},
+        ]
+        if timing is not None:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        qk.qk_overlap_gram_multi(tasks, prec)
+        if timing is not None:
+            e1.record(stream)
+            timing.append((e0, e1))
+        return btr, bte
+
+    def measure(prec, steps, warmup):
+        for w in range(warmup):
+            b = one_step(prec)
+            torch.cuda.synchronize()
+            del b
+            log(f"bench: {prec} warmup {w + 1}/{warmup} done")
+        timing = []
+        keep = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            keep.append(one_step(prec, timing))
+            if len(keep) > 1:
+                keep.pop(0)  # release the previous step's batches
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sweep_ms = [a.elapsed_time(b) for a, b in timing]
+        btr, bte = keep[-1]
+        chi_tr = qk.qk_mps_chi(btr)
+        chi_te = qk.qk_mps_chi(bte)
+        info = qk.qk_mps_info(btr)
+        flops = (algorithmic_flops(chi_tr, chi_tr, True)
+                 + algorithmic_flops(chi_te, chi_tr, False))
+        ms = (t1 - t0) * 1e3 / steps
+        log(f"bench: {prec}: {ms:.1f} ms/step, sweep {np.mean(sweep_ms):.1f} ms")
+        return {"ms_per_step": ms, "sweep_ms": float(np.mean(sweep_ms)), "flops": flops,
+                "chi_max_realized": info["chi_realized_max"], "chi_pad": info["chi_pad"]}
+
+    chosen = args.prec
+    if chosen == "auto":
+        x1 = xtr[:2]
+        b = qk.qk_mps_build(x1, 2, 64)
+        chosen = qk.qk_resolve_precision(b, b)
+        b.close()
+    res = measure(chosen, args.steps, args.warmup)
+    value = pairs / (res["ms_per_step"] / 1e3)
+    bound, peak = PEAKS[chosen]
+    achieved = res["flops"] / (res["sweep_ms"] / 1e3) / 1e12
+    line = {
+        "metric": "Gram kernel entries/sec at 784 qubits chi_max=64 (chosen vs plain FP64)",
+        "value": value, "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[chosen],
+        "data": "synthetic (seeded 28x28 smooth-field images, 10 classes)",
+        "config": {"workload": "784-qubit images, 4000 train + 1000 test, L=2, chi_max=64, "
+                               "cutoff 1e-10, fused RBF (gamma=1/d) + mix w=0.5",
+                   "n_train": ntr, "n_test": nte, "d": d, "n_layers": 2, "chi_max": 64,
+                   "chi_realized_max": res["chi_max_realized"], "chi_pad": res["chi_pad"],
+                   "unique_pairs": pairs, "sweep_form": chosen},
+        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "sweep (one persistent launch per step)",
+                     "kernel_ms": res["sweep_ms"], "algorithmic_flop": res["flops"]},
+    }
+    if not args.no_plain and chosen != "fp64":
+        p = measure("fp64", max(1, args.steps // 2), 1)
+        line["plain_fp64"] = {"value": pairs / (p["ms_per_step"] / 1e3),
+                              "ms_per_step": p["ms_per_step"], "sweep_ms": p["sweep_ms"]}
+        line["speedup_vs_plain_fp64"] = value / line["plain_fp64"]["value"]
+    if not args.no_cpu:
+        log("bench: timing the CPU oracle sample")
+        line["cpu_baseline"] = cpu_baseline(x_tr, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="auto",
+                    choices=["auto", "fp64", "fp32", "fp32_mfma", "bf16x2", "bf16x3"])
+    ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparator")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the Gram tiles shard across GPUs without "
+              "communication in the sweep (see DESIGN.md), but multi-GPU runs are not part "
+              "of this build; use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    run(args)
+
+
+if __name__ == "__main__":
+    main()

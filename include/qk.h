@@ -1,0 +1,243 @@
+/*
+ * qk.h -- C ABI of libqk: MPS quantum kernels, the RBF kernel and their
+ * linear mix on one AMD Instinct MI355X (gfx950).
+ *
+ * Operations (paper: "Scalable Tensor Network Simulation for
+ * Quantum-Classical Dual Kernel"):
+ *   - encode every sample as a matrix-product state of the feature state
+ *     |psi(x)> = U(x)|0...0> (Eq. (6), Section II-C);
+ *   - fill Gram matrices of the quantum kernel K_q = |<psi(x)|psi(y)>|^2
+ *     (Eq. (7); equivalently |<0|U^dagger(y)U(x)|0>|^2, Eqs. (8)-(10)),
+ *     block by block (Section II-D, blockwise construction);
+ *   - the classical RBF kernel K_c = exp(-gamma ||x - y||^2) (Eq. (3));
+ *   - the dual kernel K = w K_q + (1 - w) K_c (Eq. (11); the paper's alpha).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns a qk_status; no C++ exception crosses the ABI.
+ *     On failure qk_last_error() returns a thread-local message.
+ *   - Pointers named *_dev are device pointers (HIP device memory of the
+ *     current device); *_host are host pointers. Caller-owned buffers stay
+ *     owned by the caller and must stay alive until the stream has finished
+ *     the enqueued work. The library never frees or retains them.
+ *   - Matrices are row-major with an explicit leading dimension in elements.
+ *   - hip_stream is a hipStream_t (NULL = the default stream). Work is
+ *     enqueued on it and the call returns; argument checks are synchronous
+ *     and a rejected call enqueues nothing.
+ *   - Errors found on the device (non-finite input, a bond dimension above
+ *     the bound) are latched in the batch and reported by qk_mps_info().
+ *   - Calls on different streams may run concurrently; an MPS batch is
+ *     read-only after qk_mps_build() returns.
+ */
+#ifndef QK_H
+#define QK_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define QK_API __attribute__((visibility("default")))
+#else
+#define QK_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QK_OK = 0,
+  QK_ERR_INVALID_ARG = -1,
+  QK_ERR_OUT_OF_MEMORY = -2,
+  QK_ERR_HIP = -3,
+  QK_ERR_UNSUPPORTED = -4,
+  QK_ERR_BUSY = -5,
+  QK_ERR_CANCELLED = -6,
+  QK_ERR_DEVICE = -7, /* a check latched on the device failed */
+  QK_ERR_NOT_FOUND = -8
+} qk_status;
+
+/* Number format / engine of the overlap sweep. */
+typedef enum {
+  QK_PREC_FP64 = 0,      /* complex FP64 on VALU: the plain comparator     */
+  QK_PREC_FP32 = 1,      /* complex FP32 on VALU                           */
+  QK_PREC_BF16X2 = 2,    /* split BF16 (hi+lo, 3 products) on MFMA, FP32 acc */
+  QK_PREC_BF16X3 = 3,    /* split BF16 (3 pieces, 6 products) on MFMA       */
+  QK_PREC_AUTO = 4,      /* fastest form that meets the stated tolerance    */
+  QK_PREC_FP32_MFMA = 5  /* complex FP32 on v_mfma_f32_16x16x4f32           */
+} qk_precision;
+
+/* Which packed forms a batch keeps after qk_mps_build (bit mask). */
+enum {
+  QK_STORE_FP64 = 1, /* complex FP64 site tensors (needed by QK_PREC_FP64) */
+  QK_STORE_FP32 = 2, /* complex FP32 site tensors (all other forms)        */
+  QK_STORE_ALL = 3
+};
+
+/*
+ * Encoding circuit (the benchmark instance of the block-structured feature
+ * map of Section II-C, Fig. 1(B)); per layer:
+ *   H on every qubit, RZ(2 x_k) on qubit k, then RZZ(theta_k) on (k, k+1),
+ *   k = 0..n-2, theta_k = 2 (pi - x_k)(pi - x_{k+1}); repeated n_layers
+ *   times with the same x. RZ(p) = exp(-i p Z/2), RZZ(t) = exp(-i t ZZ/2).
+ */
+typedef struct {
+  int32_t n_qubits;   /* = number of features d, >= 1                      */
+  int32_t n_layers;   /* L >= 1                                             */
+  int32_t chi_max;    /* bond-dimension cap, >= 1                           */
+  int32_t entangle;   /* 1: RZZ chain as above; 0: all theta_k = 0          */
+  double cutoff_rel;  /* keep singular values s_j > cutoff_rel * s_0, >= 0  */
+} qk_circuit_desc;
+
+typedef struct qk_mps_batch qk_mps_batch; /* opaque, device-resident, library-owned */
+
+/*
+ * qk_mps_build -- one MPS per sample (Eq. (6)).
+ * Time-evolving block decimation in FP64 on the device, one wavefront per
+ * sample: per layer, the single-qubit gates, then the RZZ chain as two-site
+ * steps (merge, phase, one-sided Jacobi SVD, truncate at s_j > cutoff*s_0 and
+ * chi_max, renormalise), sweeping left to right on odd and right to left on
+ * even layers. Then the tensors are packed for the overlap sweep.
+ *   c        circuit; the library bounds every bond by chi_ws =
+ *            min(chi_max, 2^min(n_layers, floor(n_qubits/2))) (1 when
+ *            entangle = 0), the exact bond bound of this circuit family;
+ *            tensors are padded to chi_pad = the power of two >= chi_ws;
+ *            chi_ws <= 16 is supported.
+ *   x_dev    n_samples x n_qubits FP64 features, row-major, leading dim ld_x.
+ *            Must be finite (checked on the device, reported by qk_mps_info).
+ *   store    QK_STORE_* mask of packed forms to keep.
+ *   out      receives a new batch; release it with qk_mps_release.
+ * Errors: INVALID_ARG (bad desc, null pointers, ld_x < n_qubits),
+ *         UNSUPPORTED (chi_ws > 16), OUT_OF_MEMORY, HIP.
+ */
+QK_API qk_status qk_mps_build(const qk_circuit_desc* c, const double* x_dev,
+                       int64_t n_samples, int64_t ld_x, uint32_t store,
+                       void* hip_stream, qk_mps_batch** out);
+
+/*
+ * qk_mps_import -- test hook: upload MPS built elsewhere (e.g. on the host).
+ *   chi_host     n_samples x (n_qubits+1) bond dimensions (chi_0 = chi_n = 1).
+ *   tensors_host complex FP64 (re, im interleaved), layout
+ *                [site k][sample i][s][a][b], a, b < chi_pad, zero outside
+ *                the realized (chi_k, chi_{k+1}) block; chi_pad a power of 2.
+ * The copy is synchronous. Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.
+ */
+QK_API qk_status qk_mps_import(const qk_circuit_desc* c, int64_t n_samples,
+                        int32_t chi_pad, const int32_t* chi_host,
+                        const double* tensors_host, uint32_t store,
+                        void* hip_stream, qk_mps_batch** out);
+
+/*
+ * qk_mps_info -- synchronises the batch's build stream, then reports the
+ * sample count, qubit count, padded and largest realized bond dimension and
+ * the device bytes held. Returns QK_ERR_DEVICE if the build latched an error
+ * (non-finite input or a bond above chi_ws); qk_last_error() says which.
+ * Any output pointer may be NULL.
+ */
+QK_API qk_status qk_mps_info(const qk_mps_batch* b, int64_t* n_samples,
+                      int32_t* n_qubits, int32_t* chi_pad,
+                      int32_t* chi_realized_max, int64_t* device_bytes);
+
+/* Copies the realized bond table (n_samples x (n_qubits+1) int32) to host. */
+QK_API qk_status qk_mps_chi(const qk_mps_batch* b, int32_t* chi_host);
+
+/* Frees the batch after waiting for all work on the device (sweeps on any
+ * stream may read it). NULL is accepted. */
+QK_API qk_status qk_mps_release(qk_mps_batch* b);
+
+/*
+ * Optional fusion of the RBF kernel (Eq. (3)) and the mix (Eq. (11)) into
+ * the epilogue of the overlap sweep. x_rows_dev / x_cols_dev are the FP64
+ * features the batches were built from (row-major, leading dims ld_xr,
+ * ld_xc, d = n_qubits columns). kc_dev and k_dev are FP64 outputs laid out
+ * like kq (either may be NULL to skip it).
+ */
+typedef struct {
+  const double* x_rows_dev;
+  int64_t ld_xr;
+  const double* x_cols_dev;
+  int64_t ld_xc;
+  double gamma;
+  double w;
+  double* kc_dev;
+  int64_t ld_kc;
+  double* k_dev;
+  int64_t ld_k;
+} qk_fuse_desc;
+
+/*
+ * qk_overlap_gram -- K_q for every pair (row sample i, column sample j)
+ * (Eq. (7)) by the transfer-matrix sweep E_{k+1} = sum_s A_k^{s dagger} E_k
+ * B_k^s, E_0 = 1, with an exact power-of-two rescale of E after every site
+ * and an int32 exponent; ln K_q = 2 (ln|E_n| + e ln 2) in FP64 and
+ * K_q = exp(ln K_q) (0 once below the FP64 range).
+ *   rows, cols   batches with the same qubit count and chi_pad.
+ *   symmetric    1: rows == cols; only j >= i is contracted and both
+ *                triangles are written (train x train); 0: full rectangle.
+ *   prec         QK_PREC_*; QK_PREC_FP64 needs QK_STORE_FP64 in both batches.
+ *   kq_dev       FP64 rows->n_samples x cols->n_samples output, ld_kq (may be
+ *                NULL if lnkq_dev is given).
+ *   lnkq_dev     FP64 ln K_q output, ld_ln (NULL to skip).
+ *   fuse         NULL, or RBF + mix outputs as above.
+ * Errors: INVALID_ARG, UNSUPPORTED (chi_pad not supported by prec), HIP.
+ */
+QK_API qk_status qk_overlap_gram(const qk_mps_batch* rows, const qk_mps_batch* cols,
+                          int32_t symmetric, qk_precision prec, double* kq_dev,
+                          int64_t ld_kq, double* lnkq_dev, int64_t ld_ln,
+                          const qk_fuse_desc* fuse, void* hip_stream);
+
+/*
+ * One Gram block in a ragged multi-task launch: uneven qubit counts and
+ * bond dimensions share one persistent launch. Fields as in
+ * qk_overlap_gram.
+ */
+typedef struct {
+  const qk_mps_batch* rows;
+  const qk_mps_batch* cols;
+  int32_t symmetric;
+  double* kq_dev;
+  int64_t ld_kq;
+  double* lnkq_dev;
+  int64_t ld_ln;
+  qk_fuse_desc fuse;   /* used when use_fuse != 0 */
+  int32_t use_fuse;
+} qk_gram_task;
+
+/*
+ * qk_overlap_gram_multi -- all tasks in one persistent launch; tiles of all
+ * tasks form one list in longest-processing-time order (cost n * chi^3).
+ * At most 16 tasks. Errors as qk_overlap_gram.
+ */
+QK_API qk_status qk_overlap_gram_multi(const qk_gram_task* tasks, int32_t n_tasks,
+                                qk_precision prec, void* hip_stream);
+
+/*
+ * qk_rbf_gram -- K_c[i][j] = exp(-gamma sum_t (x_it - y_jt)^2) (Eq. (3)),
+ * FP64, direct differences. x_dev: m x d (ld_x), y_dev: n x d (ld_y),
+ * kc_dev: m x n (ld_kc). Errors: INVALID_ARG, HIP.
+ */
+QK_API qk_status qk_rbf_gram(const double* x_dev, int64_t m, int64_t ld_x,
+                      const double* y_dev, int64_t n, int64_t ld_y, int32_t d,
+                      double gamma, double* kc_dev, int64_t ld_kc,
+                      void* hip_stream);
+
+/*
+ * qk_dual_mix -- K = w K_q + (1 - w) K_c elementwise (Eq. (11)), FP64,
+ * m x n with separate leading dimensions; k_dev may alias kq_dev or kc_dev
+ * when the leading dimensions agree. Errors: INVALID_ARG, HIP.
+ */
+QK_API qk_status qk_dual_mix(const double* kq_dev, int64_t ld_kq, const double* kc_dev,
+                      int64_t ld_kc, int64_t m, int64_t n, double w,
+                      double* k_dev, int64_t ld_k, void* hip_stream);
+
+/* Resolves QK_PREC_AUTO for a batch pair: writes the form the library
+ * would run (from the tuning table, else the built-in default). */
+QK_API qk_status qk_resolve_precision(const qk_mps_batch* rows,
+                               const qk_mps_batch* cols, qk_precision* out);
+
+QK_API const char* qk_status_string(qk_status s);
+QK_API const char* qk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QK_H */

@@ -1,0 +1,346 @@
+// MPS build on the device: time-evolving block decimation of the encoding
+// circuit of Eq. (6), FP64, one 64-lane wavefront per sample.
+//
+// Per layer: the single-qubit gates G_k = RZ(2 x_k) H on every site, then the
+// RZZ(theta_k) chain as two-site steps, left to right on odd layers and right
+// to left on even layers (the entanglers of one layer commute, and the
+// orthogonality centre always sits on the merged pair). A step merges the two
+// sites into Theta (2 chi_l x 2 chi_r), multiplies the diagonal RZZ phase,
+// factors Theta = U S V^dagger with a one-sided (Hestenes) Jacobi SVD, keeps
+// s_j > cutoff * s_0 (at most chi_max), renormalises the kept values and
+// splits back. The site tensors live in the packed sweep layout
+// [site][sample][s][a][b] (padded to T x T, zero outside the realized block),
+// so the FP64 sweep reads the build's output directly.
+#include <hip/hip_runtime.h>
+
+#include "qk_internal.h"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct cplx {
+  double re, im;
+};
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ inline double2 cadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ inline double2 cscale(double2 a, double s) {
+  return make_double2(a.x * s, a.y * s);
+}
+
+// One-sided Jacobi on the columns of X (R rows x C columns, column-major in
+// LDS with leading dimension LD), accumulating V (C x C, column-major, LD).
+// On return the columns of X are mutually orthogonal and X_in V = X_out.
+// C must be even (a padded zero column is skipped). A pair is rotated while
+// |x_p^H x_q| > 1e-14 |x_p| |x_q|; columns with |x|^2 <= floor2 are rounding
+// noise of a rank-deficient X and are left alone. Returns false if the sweep
+// limit was reached.
+template <int LD>
+__device__ bool jacobi_columns(double2* X, double2* V, int R, int C, double floor2) {
+  const int lane = threadIdx.x;
+  const int npairs = C >> 1;
+  int g = 64 / npairs;  // lanes per pair, a power of two
+  g = g >= 32 ? 32 : (g >= 16 ? 16 : (g >= 8 ? 8 : (g >= 4 ? 4 : (g >= 2 ? 2 : 1))));
+  const int pair = lane / g;
+  const int sub = lane % g;
+  const bool active = pair < npairs;
+  const int players = C - 1;
+  const double tol = 1e-14;
+
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rotated = 0;
+    for (int r = 0; r < players; ++r) {
+      int p = 0, q = 0;
+      if (active) {
+        if (pair == 0) {
+          p = 0;
+          q = 1 + (r % players);
+        } else {
+          p = 1 + (r + pair) % players;
+          q = 1 + (r - pair + players) % players;
+        }
+      }
+      double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+      if (active) {
+        for (int row = sub; row < R; row += g) {
+          double2 xp = X[p * LD + row];
+          double2 xq = X[q * LD + row];
+          al += xp.x * xp.x + xp.y * xp.y;
+          be += xq.x * xq.x + xq.y * xq.y;
+          gr += xp.x * xq.x + xp.y * xq.y;  // conj(xp) * xq
+          gi += xp.x * xq.y - xp.y * xq.x;
+        }
+      }
+      for (int off = 1; off < g; off <<= 1) {
+        al += __shfl_xor(al, off, 64);
+        be += __shfl_xor(be, off, 64);
+        gr += __shfl_xor(gr, off, 64);
+        gi += __shfl_xor(gi, off, 64);
+      }
+      const double gabs = sqrt(gr * gr + gi * gi);
+      const bool do_rot =
+          active && al > floor2 && be > floor2 && gabs > tol * sqrt(al * be);
+      if (do_rot) {
+        const double zeta = (be - al) / (2.0 * gabs);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t);
+        const double s = c * t;
+        // e^{-i phi} = conj(gamma) / |gamma|
+        const double2 ph = make_double2(gr / gabs, -gi / gabs);
+        for (int row = sub; row < R; row += g) {
+          double2 xp = X[p * LD + row];
+          double2 xq = cmul(ph, X[q * LD + row]);
+          X[p * LD + row] = make_double2(c * xp.x - s * xq.x, c * xp.y - s * xq.y);
+          X[q * LD + row] = make_double2(s * xp.x + c * xq.x, s * xp.y + c * xq.y);
+        }
+        for (int row = sub; row < C; row += g) {
+          double2 vp = V[p * LD + row];
+          double2 vq = cmul(ph, V[q * LD + row]);
+          V[p * LD + row] = make_double2(c * vp.x - s * vq.x, c * vp.y - s * vq.y);
+          V[q * LD + row] = make_double2(s * vp.x + c * vq.x, s * vp.y + c * vq.y);
+        }
+      }
+      rotated |= do_rot ? 1 : 0;
+      __syncthreads();
+    }
+    if (!__any(rotated)) return true;
+  }
+  return false;
+}
+
+// LDS layout per workgroup, D = 2 * W (largest Theta dimension).
+template <int W>
+struct BuildSmem {
+  static constexpr int D = 2 * W;
+  double2 X[D * D];
+  double2 V[D * D];
+  double2 sa[2 * W * W];  // site k copy   [s][a][b], padded to W x W
+  double2 sb[2 * W * W];  // site k+1 copy
+  double S[D];
+  int perm[D];
+};
+
+template <int W>
+__global__ __launch_bounds__(64) void mps_build_kernel(
+    const double* __restrict__ x, int64_t ld_x, int64_t N, int nq, int n_layers,
+    int chi_max, int entangle, double cutoff, int T, double2* __restrict__ t64,
+    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status) {
+  constexpr int D = 2 * W;
+  __shared__ BuildSmem<W> sm;
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int TT = T * T;
+  const int slot = 2 * TT;
+  const double* xi = x + i * ld_x;
+  int32_t* chi = chi_tab + i * (int64_t)(nq + 1);
+  auto site = [&](int k) -> double2* { return t64 + ((int64_t)k * N + i) * slot; };
+
+  // product state |0...0>, every bond 1; reject non-finite features
+  int bad = 0;
+  for (int k = lane; k < nq; k += 64) bad |= !isfinite(xi[k]);
+  if (__any(bad) && lane == 0) atomicOr(status, QK_FLAG_NONFINITE);
+  for (int64_t e = lane; e < (int64_t)nq * slot; e += 64) {
+    int k = (int)(e / slot), r = (int)(e % slot);
+    site(k)[r] = make_double2(r == 0 ? 1.0 : 0.0, 0.0);
+  }
+  for (int b = lane; b <= nq; b += 64) chi[b] = 1;
+  __syncthreads();
+
+  const double inv_sqrt2 = 0.70710678118654752440;
+  int chi_seen = 1;
+  for (int layer = 0; layer < n_layers; ++layer) {
+    // 1. single-qubit layer: A'[0] = e^{-ix}(A0 + A1)/sqrt2, A'[1] = e^{ix}(A0 - A1)/sqrt2
+    for (int64_t e = lane; e < (int64_t)nq * TT; e += 64) {
+      int k = (int)(e / TT), r = (int)(e % TT);
+      double sn, cs;
+      sincos(xi[k], &sn, &cs);
+      double2* A = site(k);
+      double2 a0 = A[r], a1 = A[TT + r];
+      double2 u = cscale(cadd(a0, a1), inv_sqrt2);
+      double2 v = cscale(make_double2(a0.x - a1.x, a0.y - a1.y), inv_sqrt2);
+      A[r] = cmul(make_double2(cs, -sn), u);
+      A[TT + r] = cmul(make_double2(cs, sn), v);
+    }
+    __syncthreads();
+    if (nq == 1) continue;
+
+    // 2. entangler chain
+    const bool l2r = (layer % 2) == 0;
+    for (int step = 0; step < nq - 1; ++step) {
+      const int k = l2r ? step : (nq - 2 - step);
+      const int cl = chi[k], cm = chi[k + 1], cr = chi[k + 2];
+      double theta = 0.0;
+      if (entangle) theta = 2.0 * (kPi - xi[k]) * (kPi - xi[k + 1]);
+      // stage the two sites (realized blocks) in LDS, W x W padded
+      for (int e = lane; e < 2 * W * W; e += 64) {
+        int s = e / (W * W), r = e % (W * W), a = r / W, b = r % W;
+        sm.sa[e] = (a < T && b < T) ? site(k)[s * TT + a * T + b] : make_double2(0, 0);
+        sm.sb[e] = (a < T && b < T) ? site(k + 1)[s * TT + a * T + b] : make_double2(0, 0);
+      }
+      __syncthreads();
+      // Theta[(s,a)][(t,c)], rows s*cl + a, cols t*cr + c
+      const int R = 2 * cl, C = 2 * cr;
+      const bool transpose = C > R;  // factor Theta^dagger when it is wide
+      const int XR = transpose ? C : R, XC = transpose ? R : C;
+      double sh, ch;
+      sincos(0.5 * theta, &sh, &ch);
+      double fro = 0.0;
+      for (int e = lane; e < R * C; e += 64) {
+        int row = e % R, col = e / R;
+        int s = row / cl, a = row % cl, t = col / cr, c = col % cr;
+        double2 acc = make_double2(0, 0);
+        for (int b = 0; b < cm; ++b)
+          acc = cadd(acc, cmul(sm.sa[s * W * W + a * W + b], sm.sb[t * W * W + b * W + c]));
+        // exp(-i theta/2 sigma_s sigma_t)
+        double2 ph = (s == t) ? make_double2(ch, -sh) : make_double2(ch, sh);
+        acc = cmul(ph, acc);
+        fro += acc.x * acc.x + acc.y * acc.y;
+        if (!transpose) sm.X[col * D + row] = acc;
+        else sm.X[row * D + col] = make_double2(acc.x, -acc.y);
+      }
+      const int XCe = XC + (XC & 1);  // even column count
+      for (int e = lane; e < D * D; e += 64) {
+        int col = e / D, row = e % D;
+        if (col >= XC && col < XCe) sm.X[e] = make_double2(0, 0);
+        sm.V[e] = make_double2((col == row && col < XCe) ? 1.0 : 0.0, 0.0);
+      }
+      __syncthreads();
+      for (int off = 1; off < 64; off <<= 1) fro += __shfl_xor(fro, off, 64);
+      bool conv = jacobi_columns<D>(sm.X, sm.V, XR, XCe, 1e-30 * fro);
+      if (!conv && lane == 0) atomicOr(status, QK_FLAG_NOCONV);
+      // singular values = column norms; rank them (descending, stable)
+      if (lane < XCe) {
+        double s2 = 0.0;
+        for (int row = 0; row < XR; ++row) {
+          double2 v = sm.X[lane * D + row];
+          s2 += v.x * v.x + v.y * v.y;
+        }
+        sm.S[lane] = sqrt(s2);
+      }
+      __syncthreads();
+      if (lane < XCe) {
+        double mine = sm.S[lane];
+        int rank = 0;
+        for (int j = 0; j < XCe; ++j) {
+          double o = sm.S[j];
+          rank += (o > mine) || (o == mine && j < lane);
+        }
+        sm.perm[rank] = lane;
+      }
+      __syncthreads();
+      const double s0 = sm.S[sm.perm[0]];
+      int keep = 0;
+      double norm2 = 0.0;
+      const int kmax = XC < chi_max ? XC : chi_max;
+      for (int j = 0; j < kmax; ++j) {
+        double sj = sm.S[sm.perm[j]];
+        if (j == 0 || sj > cutoff * s0) {
+          ++keep;
+          norm2 += sj * sj;
+        } else {
+          break;
+        }
+      }
+      if (keep > W) {
+        if (lane == 0) atomicOr(status, QK_FLAG_CHI_OVER);
+        keep = W;
+        norm2 = 0.0;
+        for (int j = 0; j < keep; ++j) norm2 += sm.S[sm.perm[j]] * sm.S[sm.perm[j]];
+      }
+      const double inv_norm = norm2 > 0.0 ? 1.0 / sqrt(norm2) : 0.0;
+      if (keep > chi_seen) chi_seen = keep;
+      // Left factor Lf (R x keep) and right factor Rf (keep x C) of Theta:
+      //   no transpose: Lf[:,j] = X[:,pj]/S_pj, Rf[j,:] = conj(V[:,pj])
+      //   transpose   : Lf[:,j] = V[:,pj],     Rf[j,:] = conj(X[:,pj])/S_pj
+      // with S absorbed right (l2r) or left (r2l), renormalised.
+      for (int e = lane; e < 2 * TT; e += 64) {
+        int s = e / TT, r = e % TT, a = r / T, j = r % T;
+        double2 v = make_double2(0, 0);
+        if (a < cl && j < keep) {
+          int pj = sm.perm[j], row = s * cl + a;
+          double Sj = sm.S[pj];
+          double2 u;
+          if (!transpose) u = Sj > 0.0 ? cscale(sm.X[pj * D + row], 1.0 / Sj) : make_double2(0, 0);
+          else u = sm.V[pj * D + row];
+          v = l2r ? u : cscale(u, Sj * inv_norm);
+        }
+        site(k)[e] = v;
+      }
+      for (int e = lane; e < 2 * TT; e += 64) {
+        int t = e / TT, r = e % TT, j = r / T, c = r % T;
+        double2 v = make_double2(0, 0);
+        if (j < keep && c < cr) {
+          int pj = sm.perm[j], col = t * cr + c;
+          double Sj = sm.S[pj];
+          double2 h;
+          if (!transpose) {
+            double2 q = sm.V[pj * D + col];
+            h = make_double2(q.x, -q.y);
+          } else {
+            double2 q = sm.X[pj * D + col];
+            h = Sj > 0.0 ? make_double2(q.x / Sj, -q.y / Sj) : make_double2(0, 0);
+          }
+          v = l2r ? cscale(h, Sj * inv_norm) : h;
+        }
+        site(k + 1)[e] = v;
+      }
+      if (lane == 0) chi[k + 1] = keep;
+      __syncthreads();
+    }
+  }
+  if (lane == 0) atomicMax(status + 1, chi_seen);
+}
+
+__global__ void pack32_kernel(const double2* __restrict__ a, float2* __restrict__ b,
+                              int64_t count) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) {
+    double2 v = a[i];
+    b[i] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+}  // namespace
+
+hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
+                           int n_layers, int chi_max, int entangle,
+                           double cutoff, int chi_ws, int T, double2* t64,
+                           int32_t* chi, int32_t* status, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  dim3 grid((unsigned)n), block(64);
+#define QK_BUILD_CASE(WV)                                                     \
+  case WV:                                                                    \
+    hipLaunchKernelGGL(mps_build_kernel<WV>, grid, block, 0, s, x, ld_x, n,   \
+                       nq, n_layers, chi_max, entangle, cutoff, T, t64, chi,  \
+                       status);                                               \
+    break;
+  switch (T) {
+    QK_BUILD_CASE(1)
+    QK_BUILD_CASE(2)
+    QK_BUILD_CASE(4)
+    QK_BUILD_CASE(8)
+    QK_BUILD_CASE(16)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef QK_BUILD_CASE
+  return hipGetLastError();
+}
+
+hipError_t qk_launch_pack32(const double2* t64, float2* t32, int64_t count,
+                            hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(pack32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, t64, t32, count);
+  return hipGetLastError();
+}

@@ -1,0 +1,464 @@
+// Host side of the libqk C ABI: argument checks, batch ownership, task
+// tables and launch configuration. Every step of the computation runs in the
+// HIP kernels of this library; nothing here touches sample data.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "qk_internal.h"
+#include "qk_tune.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qk_status fail(qk_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+qk_status hip_fail(hipError_t e, const char* what) {
+  return fail(QK_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define QK_HIP(call, what)                      \
+  do {                                          \
+    hipError_t e__ = (call);                    \
+    if (e__ != hipSuccess) return hip_fail(e__, what); \
+  } while (0)
+
+int pow2_ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+int device_cus() {
+  static int cus = 0;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  });
+  return cus;
+}
+
+qk_status check_desc(const qk_circuit_desc* c) {
+  if (!c) return fail(QK_ERR_INVALID_ARG, "circuit descriptor is NULL");
+  if (c->n_qubits < 1) return fail(QK_ERR_INVALID_ARG, "n_qubits must be >= 1");
+  if (c->n_layers < 1) return fail(QK_ERR_INVALID_ARG, "n_layers must be >= 1");
+  if (c->chi_max < 1) return fail(QK_ERR_INVALID_ARG, "chi_max must be >= 1");
+  if (c->entangle != 0 && c->entangle != 1)
+    return fail(QK_ERR_INVALID_ARG, "entangle must be 0 or 1");
+  if (!(c->cutoff_rel >= 0.0) || !std::isfinite(c->cutoff_rel))
+    return fail(QK_ERR_INVALID_ARG, "cutoff_rel must be finite and >= 0");
+  return QK_OK;
+}
+
+// Exact bond bound of this circuit family: each layer's RZZ chain multiplies
+// the Schmidt rank across a cut by at most 2, and no cut of n qubits has
+// rank above 2^floor(n/2).
+int chi_bound(const qk_circuit_desc* c) {
+  if (!c->entangle || c->n_qubits == 1) return 1;
+  const int e = std::min(c->n_layers, c->n_qubits / 2);
+  int64_t b = 1;
+  for (int l = 0; l < e && b < c->chi_max; ++l) b *= 2;
+  return (int)std::min<int64_t>(b, c->chi_max);
+}
+
+qk_status alloc_batch(const qk_circuit_desc* c, int64_t n, int T, uint32_t store,
+                      hipStream_t s, qk_mps_batch** out) {
+  auto* b = new qk_mps_batch();
+  (void)hipGetDevice(&b->device);
+  b->n = n;
+  b->nq = c->n_qubits;
+  b->n_layers = c->n_layers;
+  b->T = T;
+  b->stream = s;
+  const int64_t elems = (int64_t)c->n_qubits * n * 2 * T * T;
+  auto cleanup = [&](qk_status st, const char* what) {
+    (void)hipFree(b->t64);
+    (void)hipFree(b->t32);
+    (void)hipFree(b->chi);
+    (void)hipFree(b->status);
+    delete b;
+    return fail(st, what);
+  };
+  // the FP64 form is the build's workspace, so it is always allocated
+  if (hipMalloc(&b->t64, std::max<int64_t>(elems, 1) * sizeof(double2)) != hipSuccess)
+    return cleanup(QK_ERR_OUT_OF_MEMORY, "device allocation of FP64 site tensors failed");
+  if ((store & QK_STORE_FP32) &&
+      hipMalloc(&b->t32, std::max<int64_t>(elems, 1) * sizeof(float2)) != hipSuccess)
+    return cleanup(QK_ERR_OUT_OF_MEMORY, "device allocation of FP32 site tensors failed");
+  if (hipMalloc(&b->chi, std::max<int64_t>(n * (c->n_qubits + 1), 1) * sizeof(int32_t)) != hipSuccess)
+    return cleanup(QK_ERR_OUT_OF_MEMORY, "device allocation of the bond table failed");
+  if (hipMalloc(&b->status, 2 * sizeof(int32_t)) != hipSuccess)
+    return cleanup(QK_ERR_OUT_OF_MEMORY, "device allocation of the status word failed");
+  if (hipMemsetAsync(b->status, 0, 2 * sizeof(int32_t), s) != hipSuccess)
+    return cleanup(QK_ERR_HIP, "status reset failed");
+  if (hipEventCreateWithFlags(&b->ready, hipEventDisableTiming) != hipSuccess)
+    return cleanup(QK_ERR_HIP, "event creation failed");
+  b->bytes = elems * (int64_t)sizeof(double2) +
+             ((store & QK_STORE_FP32) ? elems * (int64_t)sizeof(float2) : 0) +
+             n * (c->n_qubits + 1) * (int64_t)sizeof(int32_t);
+  *out = b;
+  return QK_OK;
+}
+
+// Drops the FP64 form after packing when the caller did not ask to keep it.
+qk_status finish_batch(qk_mps_batch* b, uint32_t store) {
+  const int64_t elems = (int64_t)b->nq * b->n * 2 * b->T * b->T;
+  if (b->t32) QK_HIP(qk_launch_pack32(b->t64, b->t32, elems, b->stream), "pack to FP32");
+  QK_HIP(hipEventRecord(b->ready, b->stream), "event record");
+  if (!(store & QK_STORE_FP64)) {
+    QK_HIP(hipEventSynchronize(b->ready), "build synchronisation");
+    (void)hipFree(b->t64);
+    b->t64 = nullptr;
+    b->bytes -= elems * (int64_t)sizeof(double2);
+  }
+  return QK_OK;
+}
+
+qk_status fill_task(QkTask& t, const qk_mps_batch* rows, const qk_mps_batch* cols,
+                    int32_t symmetric, bool fp64, double* kq, int64_t ld_kq,
+                    double* lnkq, int64_t ld_ln, const qk_fuse_desc* fuse, int tile) {
+  if (!rows || !cols) return fail(QK_ERR_INVALID_ARG, "batch is NULL");
+  if (rows->nq != cols->nq) return fail(QK_ERR_INVALID_ARG, "qubit counts differ");
+  if (rows->T != cols->T)
+    return fail(QK_ERR_UNSUPPORTED, "row and column batches have different chi_pad");
+  if (symmetric && rows != cols)
+    return fail(QK_ERR_INVALID_ARG, "symmetric mode needs rows == cols");
+  const bool work = rows->n > 0 && cols->n > 0;
+  if (work && !kq && !lnkq && !(fuse && (fuse->kc_dev || fuse->k_dev)))
+    return fail(QK_ERR_INVALID_ARG, "no output requested");
+  if (kq && ld_kq < cols->n) return fail(QK_ERR_INVALID_ARG, "ld_kq < number of columns");
+  if (lnkq && ld_ln < cols->n) return fail(QK_ERR_INVALID_ARG, "ld_ln < number of columns");
+  if (fp64 && (!rows->t64 || !cols->t64))
+    return fail(QK_ERR_INVALID_ARG, "FP64 sweep needs batches built with QK_STORE_FP64");
+  if (!fp64 && (!rows->t32 || !cols->t32))
+    return fail(QK_ERR_INVALID_ARG, "this sweep needs batches built with QK_STORE_FP32");
+  memset(&t, 0, sizeof(t));
+  t.ta = fp64 ? (const void*)rows->t64 : (const void*)rows->t32;
+  t.tb = fp64 ? (const void*)cols->t64 : (const void*)cols->t32;
+  t.na = rows->n;
+  t.nb = cols->n;
+  t.nq = rows->nq;
+  t.T = rows->T;
+  t.symmetric = symmetric ? 1 : 0;
+  const int64_t tr = (rows->n + tile - 1) / tile, tc = (cols->n + tile - 1) / tile;
+  t.tiles_c = (int32_t)tc;
+  t.n_tiles = symmetric ? tr * (tr + 1) / 2 : tr * tc;
+  t.kq = kq;
+  t.ld_kq = ld_kq;
+  t.lnkq = lnkq;
+  t.ld_ln = ld_ln;
+  if (fuse && work) {
+    if (!fuse->x_rows_dev || !fuse->x_cols_dev)
+      return fail(QK_ERR_INVALID_ARG, "fusion needs the feature matrices");
+    if (fuse->ld_xr < rows->nq || fuse->ld_xc < cols->nq)
+      return fail(QK_ERR_INVALID_ARG, "feature leading dimension < qubit count");
+    if (!(fuse->w >= 0.0 && fuse->w <= 1.0)) return fail(QK_ERR_INVALID_ARG, "w must be in [0, 1]");
+    if (!(fuse->gamma >= 0.0) || !std::isfinite(fuse->gamma))
+      return fail(QK_ERR_INVALID_ARG, "gamma must be finite and >= 0");
+    if (fuse->kc_dev && fuse->ld_kc < cols->n) return fail(QK_ERR_INVALID_ARG, "ld_kc too small");
+    if (fuse->k_dev && fuse->ld_k < cols->n) return fail(QK_ERR_INVALID_ARG, "ld_k too small");
+    t.fuse = 1;
+    t.xr = fuse->x_rows_dev;
+    t.ld_xr = fuse->ld_xr;
+    t.xc = fuse->x_cols_dev;
+    t.ld_xc = fuse->ld_xc;
+    t.gamma = fuse->gamma;
+    t.w = fuse->w;
+    t.kc = fuse->kc_dev;
+    t.ld_kc = fuse->ld_kc;
+    t.k = fuse->k_dev;
+    t.ld_k = fuse->ld_k;
+  }
+  return QK_OK;
+}
+
+bool supported_T(qk_precision p, int T) {
+  switch (p) {
+    case QK_PREC_FP64:
+    case QK_PREC_FP32:
+      return T == 1 || T == 2 || T == 4;
+    default:
+      return qk_mfma_supports(p, T);
+  }
+}
+
+qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, hipStream_t s) {
+  // longest-processing-time order: per-tile cost ~ nq * T^3
+  std::stable_sort(tasks.begin(), tasks.end(), [](const QkTask& a, const QkTask& b) {
+    return (double)a.nq * a.T * a.T * a.T > (double)b.nq * b.T * b.T * b.T;
+  });
+  QkTaskTable tt;
+  memset(&tt, 0, sizeof(tt));
+  int64_t acc = 0;
+  for (size_t k = 0; k < tasks.size(); ++k) {
+    tasks[k].tile_begin = acc;
+    acc += tasks[k].n_tiles;
+    tt.t[k] = tasks[k];
+  }
+  tt.n_tasks = (int32_t)tasks.size();
+  tt.total_tiles = acc;
+  if (acc == 0) return QK_OK;
+  hipError_t e;
+  if (prec == QK_PREC_FP64 || prec == QK_PREC_FP32) {
+    const int per_cu = prec == QK_PREC_FP64 ? 2 : 3;
+    int grid = (int)std::min<int64_t>(acc, (int64_t)device_cus() * per_cu);
+    e = prec == QK_PREC_FP64 ? qk_launch_sweep_fp64(tt, grid, s)
+                             : qk_launch_sweep_fp32(tt, grid, s);
+  } else {
+    e = qk_launch_sweep_mfma(tt, prec, device_cus(), s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "sweep launch");
+  return QK_OK;
+}
+
+int tile_for(qk_precision p) {
+  return (p == QK_PREC_FP64 || p == QK_PREC_FP32) ? qk_sweep_valu_tile() : qk_mfma_tile(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qk_status_string(qk_status s) {
+  switch (s) {
+    case QK_OK: return "ok";
+    case QK_ERR_INVALID_ARG: return "invalid argument";
+    case QK_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case QK_ERR_HIP: return "HIP runtime error";
+    case QK_ERR_UNSUPPORTED: return "unsupported configuration";
+    case QK_ERR_BUSY: return "busy";
+    case QK_ERR_CANCELLED: return "cancelled";
+    case QK_ERR_DEVICE: return "device-side check failed";
+    case QK_ERR_NOT_FOUND: return "not found";
+  }
+  return "unknown status";
+}
+
+const char* qk_last_error(void) { return g_last_error.c_str(); }
+
+qk_status qk_mps_build(const qk_circuit_desc* c, const double* x_dev,
+                       int64_t n_samples, int64_t ld_x, uint32_t store,
+                       void* hip_stream, qk_mps_batch** out) {
+  qk_status st = check_desc(c);
+  if (st != QK_OK) return st;
+  if (!out) return fail(QK_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_samples < 0) return fail(QK_ERR_INVALID_ARG, "n_samples < 0");
+  if (n_samples > 0 && !x_dev) return fail(QK_ERR_INVALID_ARG, "x_dev is NULL");
+  if (ld_x < c->n_qubits) return fail(QK_ERR_INVALID_ARG, "ld_x < n_qubits");
+  if (store == 0 || (store & ~(uint32_t)QK_STORE_ALL))
+    return fail(QK_ERR_INVALID_ARG, "store must be a non-empty QK_STORE_* mask");
+  const int ws = chi_bound(c);
+  const int T = pow2_ceil(ws);
+  if (T > 16) return fail(QK_ERR_UNSUPPORTED, "bond bound above 16 is not supported by the build");
+  hipStream_t s = (hipStream_t)hip_stream;
+  qk_mps_batch* b = nullptr;
+  st = alloc_batch(c, n_samples, T, store, s, &b);
+  if (st != QK_OK) return st;
+  b->chi_ws = ws;
+  hipError_t e = qk_launch_build(x_dev, ld_x, n_samples, c->n_qubits, c->n_layers,
+                                 c->chi_max, c->entangle, c->cutoff_rel, ws, T,
+                                 b->t64, b->chi, b->status, s);
+  if (e != hipSuccess) {
+    qk_mps_release(b);
+    return hip_fail(e, "build launch");
+  }
+  st = finish_batch(b, store);
+  if (st != QK_OK) {
+    qk_mps_release(b);
+    return st;
+  }
+  *out = b;
+  return QK_OK;
+}
+
+qk_status qk_mps_import(const qk_circuit_desc* c, int64_t n_samples,
+                        int32_t chi_pad, const int32_t* chi_host,
+                        const double* tensors_host, uint32_t store,
+                        void* hip_stream, qk_mps_batch** out) {
+  qk_status st = check_desc(c);
+  if (st != QK_OK) return st;
+  if (!out) return fail(QK_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_samples < 0) return fail(QK_ERR_INVALID_ARG, "n_samples < 0");
+  if (chi_pad < 1 || chi_pad > 16 || (chi_pad & (chi_pad - 1)))
+    return fail(QK_ERR_INVALID_ARG, "chi_pad must be a power of two <= 16");
+  if (n_samples > 0 && (!chi_host || !tensors_host))
+    return fail(QK_ERR_INVALID_ARG, "host arrays are NULL");
+  if (store == 0 || (store & ~(uint32_t)QK_STORE_ALL))
+    return fail(QK_ERR_INVALID_ARG, "store must be a non-empty QK_STORE_* mask");
+  int mx = 1;
+  for (int64_t i = 0; i < n_samples * (c->n_qubits + 1); ++i) {
+    if (chi_host[i] < 1 || chi_host[i] > chi_pad)
+      return fail(QK_ERR_INVALID_ARG, "bond dimension outside [1, chi_pad]");
+    mx = std::max(mx, chi_host[i]);
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  qk_mps_batch* b = nullptr;
+  st = alloc_batch(c, n_samples, chi_pad, store, s, &b);
+  if (st != QK_OK) return st;
+  b->chi_ws = chi_pad;
+  const int64_t elems = (int64_t)c->n_qubits * n_samples * 2 * chi_pad * chi_pad;
+  const int32_t stat[2] = {0, mx};
+  hipError_t e = hipMemcpy(b->t64, tensors_host, elems * sizeof(double2), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->chi, chi_host, n_samples * (c->n_qubits + 1) * sizeof(int32_t),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpy(b->status, stat, sizeof(stat), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    qk_mps_release(b);
+    return hip_fail(e, "import copy");
+  }
+  st = finish_batch(b, store);
+  if (st != QK_OK) {
+    qk_mps_release(b);
+    return st;
+  }
+  *out = b;
+  return QK_OK;
+}
+
+qk_status qk_mps_info(const qk_mps_batch* b, int64_t* n_samples, int32_t* n_qubits,
+                      int32_t* chi_pad, int32_t* chi_realized_max, int64_t* device_bytes) {
+  if (!b) return fail(QK_ERR_INVALID_ARG, "batch is NULL");
+  QK_HIP(hipEventSynchronize(b->ready), "batch synchronisation");
+  int32_t st[2] = {0, 0};
+  QK_HIP(hipMemcpy(st, b->status, sizeof(st), hipMemcpyDeviceToHost), "status read");
+  if (n_samples) *n_samples = b->n;
+  if (n_qubits) *n_qubits = b->nq;
+  if (chi_pad) *chi_pad = b->T;
+  if (chi_realized_max) *chi_realized_max = st[1];
+  if (device_bytes) *device_bytes = b->bytes;
+  if (st[0]) {
+    std::string m = "build latched:";
+    if (st[0] & QK_FLAG_NONFINITE) m += " non-finite feature;";
+    if (st[0] & QK_FLAG_CHI_OVER) m += " bond above the padded bound;";
+    if (st[0] & QK_FLAG_NOCONV) m += " Jacobi SVD sweep limit reached;";
+    return fail(QK_ERR_DEVICE, m);
+  }
+  return QK_OK;
+}
+
+qk_status qk_mps_chi(const qk_mps_batch* b, int32_t* chi_host) {
+  if (!b || !chi_host) return fail(QK_ERR_INVALID_ARG, "NULL argument");
+  QK_HIP(hipEventSynchronize(b->ready), "batch synchronisation");
+  QK_HIP(hipMemcpy(chi_host, b->chi, b->n * (b->nq + 1) * sizeof(int32_t),
+                   hipMemcpyDeviceToHost),
+         "bond table read");
+  return QK_OK;
+}
+
+qk_status qk_mps_release(qk_mps_batch* b) {
+  if (!b) return QK_OK;
+  // sweeps on any stream may still read the batch: drain the device first
+  (void)hipDeviceSynchronize();
+  (void)hipFree(b->t64);
+  (void)hipFree(b->t32);
+  (void)hipFree(b->chi);
+  (void)hipFree(b->status);
+  if (b->ready) (void)hipEventDestroy(b->ready);
+  delete b;
+  return QK_OK;
+}
+
+qk_status qk_overlap_gram(const qk_mps_batch* rows, const qk_mps_batch* cols,
+                          int32_t symmetric, qk_precision prec, double* kq_dev,
+                          int64_t ld_kq, double* lnkq_dev, int64_t ld_ln,
+                          const qk_fuse_desc* fuse, void* hip_stream) {
+  qk_gram_task task;
+  memset(&task, 0, sizeof(task));
+  task.rows = rows;
+  task.cols = cols;
+  task.symmetric = symmetric;
+  task.kq_dev = kq_dev;
+  task.ld_kq = ld_kq;
+  task.lnkq_dev = lnkq_dev;
+  task.ld_ln = ld_ln;
+  if (fuse) {
+    task.fuse = *fuse;
+    task.use_fuse = 1;
+  }
+  return qk_overlap_gram_multi(&task, 1, prec, hip_stream);
+}
+
+qk_status qk_overlap_gram_multi(const qk_gram_task* tasks, int32_t n_tasks,
+                                qk_precision prec, void* hip_stream) {
+  if (!tasks || n_tasks < 1 || n_tasks > QK_MAX_TASKS)
+    return fail(QK_ERR_INVALID_ARG, "need 1..16 tasks");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (prec == QK_PREC_AUTO) {
+    qk_status st = qk_resolve_precision(tasks[0].rows, tasks[0].cols, &prec);
+    if (st != QK_OK) return st;
+  }
+  if (prec < QK_PREC_FP64 || prec > QK_PREC_FP32_MFMA)
+    return fail(QK_ERR_INVALID_ARG, "unknown precision");
+  std::vector<QkTask> tv(n_tasks);
+  const int tile = tile_for(prec);
+  for (int k = 0; k < n_tasks; ++k) {
+    const qk_gram_task& g = tasks[k];
+    qk_status st = fill_task(tv[k], g.rows, g.cols, g.symmetric, prec == QK_PREC_FP64,
+                             g.kq_dev, g.ld_kq, g.lnkq_dev, g.ld_ln,
+                             g.use_fuse ? &g.fuse : nullptr, tile);
+    if (st != QK_OK) return st;
+    if (!supported_T(prec, tv[k].T))
+      return fail(QK_ERR_UNSUPPORTED, "chi_pad " + std::to_string(tv[k].T) +
+                                          " is not supported by this sweep form");
+  }
+  // the sweep reads the batches: order it after their builds
+  for (int k = 0; k < n_tasks; ++k) {
+    QK_HIP(hipStreamWaitEvent(s, tasks[k].rows->ready, 0), "wait for row batch");
+    QK_HIP(hipStreamWaitEvent(s, tasks[k].cols->ready, 0), "wait for column batch");
+  }
+  return run_tasks(tv, prec, s);
+}
+
+qk_status qk_rbf_gram(const double* x_dev, int64_t m, int64_t ld_x, const double* y_dev,
+                      int64_t n, int64_t ld_y, int32_t d, double gamma, double* kc_dev,
+                      int64_t ld_kc, void* hip_stream) {
+  if (m < 0 || n < 0 || d < 1) return fail(QK_ERR_INVALID_ARG, "bad sizes");
+  if ((m > 0 && !x_dev) || (n > 0 && !y_dev) || (m > 0 && n > 0 && !kc_dev))
+    return fail(QK_ERR_INVALID_ARG, "NULL pointer");
+  if (ld_x < d || ld_y < d || ld_kc < n) return fail(QK_ERR_INVALID_ARG, "leading dimension too small");
+  if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(QK_ERR_INVALID_ARG, "gamma must be finite and >= 0");
+  hipError_t e = qk_launch_rbf(x_dev, m, ld_x, y_dev, n, ld_y, d, gamma, kc_dev, ld_kc,
+                               (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "rbf launch");
+  return QK_OK;
+}
+
+qk_status qk_dual_mix(const double* kq_dev, int64_t ld_kq, const double* kc_dev,
+                      int64_t ld_kc, int64_t m, int64_t n, double w, double* k_dev,
+                      int64_t ld_k, void* hip_stream) {
+  if (m < 0 || n < 0) return fail(QK_ERR_INVALID_ARG, "bad sizes");
+  if (m > 0 && n > 0 && (!kq_dev || !kc_dev || !k_dev)) return fail(QK_ERR_INVALID_ARG, "NULL pointer");
+  if (ld_kq < n || ld_kc < n || ld_k < n) return fail(QK_ERR_INVALID_ARG, "leading dimension too small");
+  if (!(w >= 0.0 && w <= 1.0)) return fail(QK_ERR_INVALID_ARG, "w must be in [0, 1]");
+  hipError_t e = qk_launch_mix(kq_dev, ld_kq, kc_dev, ld_kc, m, n, w, k_dev, ld_k,
+                               (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "mix launch");
+  return QK_OK;
+}
+
+qk_status qk_resolve_precision(const qk_mps_batch* rows, const qk_mps_batch* cols,
+                               qk_precision* out) {
+  if (!rows || !cols || !out) return fail(QK_ERR_INVALID_ARG, "NULL argument");
+  *out = qk_tune_choose(rows->T, rows->nq, rows->t32 != nullptr, rows->t64 != nullptr);
+  return QK_OK;
+}
+
+}  // extern "C"

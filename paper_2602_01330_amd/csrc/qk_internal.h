@@ -1,0 +1,80 @@
+// Internal declarations shared by the host side of libqk and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/qk.h"
+
+// Device status word bits latched by the build kernel.
+enum : int32_t {
+  QK_FLAG_NONFINITE = 1,   // a feature was NaN or Inf
+  QK_FLAG_CHI_OVER = 2,    // a kept bond exceeded the bound chi_ws
+  QK_FLAG_NOCONV = 4       // a Jacobi SVD hit its sweep limit
+};
+
+struct qk_mps_batch {
+  int device = 0;
+  int64_t n = 0;          // samples
+  int32_t nq = 0;         // qubits (sites)
+  int32_t n_layers = 0;
+  int32_t chi_ws = 1;     // bond bound used by the build
+  int32_t T = 1;          // padded bond dimension of the packed tensors
+  double2* t64 = nullptr; // [nq][n][2][T][T] complex FP64
+  float2* t32 = nullptr;  // [nq][n][2][T][T] complex FP32
+  int32_t* chi = nullptr; // [n][nq+1] realized bond dimensions
+  int32_t* status = nullptr;  // [0] flag bits, [1] max realized chi
+  hipStream_t stream = nullptr;
+  hipEvent_t ready = nullptr;
+  int64_t bytes = 0;
+};
+
+// Kernel launchers (build.hip).
+hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
+                           int n_layers, int chi_max, int entangle,
+                           double cutoff, int chi_ws, int T, double2* t64,
+                           int32_t* chi, int32_t* status, hipStream_t s);
+hipError_t qk_launch_pack32(const double2* t64, float2* t32, int64_t count,
+                            hipStream_t s);
+
+// One Gram block of a (possibly multi-task) sweep launch (sweep kernels).
+struct QkTask {
+  const void* ta;        // row tensors (double2* or float2*), [nq][na][2][T][T]
+  const void* tb;        // column tensors
+  int64_t na, nb;        // sample counts
+  int32_t nq, T;
+  int32_t symmetric;
+  int32_t tiles_c;       // column tiles
+  int64_t tile_begin;    // first global tile index of this task
+  int64_t n_tiles;
+  double* kq; int64_t ld_kq;
+  double* lnkq; int64_t ld_ln;
+  const double* xr; int64_t ld_xr;
+  const double* xc; int64_t ld_xc;
+  double gamma, w;
+  double* kc; int64_t ld_kc;
+  double* k; int64_t ld_k;
+  int32_t fuse;
+};
+
+constexpr int QK_MAX_TASKS = 16;
+
+struct QkTaskTable {
+  QkTask t[QK_MAX_TASKS];
+  int32_t n_tasks;
+  int64_t total_tiles;
+};
+
+// Sweep launchers (sweep_valu.hip / sweep_mfma.hip). Tiles are 16 x 16
+// pairs for the VALU kernels and tile_r x tile_c for MFMA.
+hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, hipStream_t s);
+hipError_t qk_launch_sweep_fp32(const QkTaskTable& tt, int grid, hipStream_t s);
+int qk_sweep_valu_tile();
+
+hipError_t qk_launch_rbf(const double* x, int64_t m, int64_t ld_x,
+                         const double* y, int64_t n, int64_t ld_y, int d,
+                         double gamma, double* kc, int64_t ld_kc, hipStream_t s);
+hipError_t qk_launch_mix(const double* kq, int64_t ld_kq, const double* kc,
+                         int64_t ld_kc, int64_t m, int64_t n, double w,
+                         double* k, int64_t ld_k, hipStream_t s);

@@ -1,0 +1,288 @@
+// Transfer-matrix overlap sweep on the vector ALUs: one pair per lane.
+//
+// For a pair (row sample i, column sample j) with site tensors A_k^s (row) and
+// B_k^s (column), both chi x chi after padding to T:
+//   E_0 = 1 (top-left entry),  E_{k+1} = sum_s A_k^{s dagger} E_k B_k^s,
+// then <psi_i|psi_j> = E_n[0][0] and K_q = |E_n|^2 (Eq. (7)). After every site
+// E is multiplied by 2^-e (e = frexp exponent of max|Re|,|Im|), which is exact,
+// and e is added to an int32 exponent; ln K_q = 2 (ln|E_n| + e ln 2) in FP64.
+//
+// A workgroup of 256 lanes owns a 16 x 16 tile of pairs. The 16 row and 16
+// column site tensors of the current site are staged in LDS (double-buffered:
+// the next site's global loads are in flight while the current site is
+// computed). Tiles of all tasks of a launch form one list walked with a static
+// grid stride (persistent workgroups). The same template serves complex FP64
+// (the plain comparator) and complex FP32.
+#include <hip/hip_runtime.h>
+
+#include "qk_internal.h"
+
+namespace {
+
+constexpr int kTile = 16;
+constexpr int kThreads = kTile * kTile;
+
+template <typename R>
+struct Cx;
+template <>
+struct Cx<double> {
+  using V = double2;
+};
+template <>
+struct Cx<float> {
+  using V = float2;
+};
+
+// Exponent e with m = f * 2^e, f in [0.5, 1); m > 0 and normal.
+__device__ inline int frexp_exp(double m) {
+  return (int)((__double_as_longlong(m) >> 52) & 0x7ff) - 1022;
+}
+__device__ inline int frexp_exp(float m) {
+  return (int)((__float_as_uint(m) >> 23) & 0xff) - 126;
+}
+__device__ inline double pow2(double, int e) {  // 2^e for -1022 <= e <= 1023
+  return __longlong_as_double((long long)(e + 1023) << 52);
+}
+__device__ inline float pow2(float, int e) {  // 2^e for -126 <= e <= 127
+  return __uint_as_float((unsigned)(e + 127) << 23);
+}
+
+// Maps a task-local tile index to (tile row, tile col).
+__device__ inline void tile_coords(const QkTask& t, int64_t lt, int& ti, int& tj) {
+  if (!t.symmetric) {
+    ti = (int)(lt / t.tiles_c);
+    tj = (int)(lt % t.tiles_c);
+    return;
+  }
+  // upper triangle (tj >= ti) of an n x n tile grid, row-major
+  const int64_t n = t.tiles_c;
+  double b = 2.0 * n + 1.0;
+  int64_t r = (int64_t)((b - sqrt(b * b - 8.0 * (double)lt)) * 0.5);
+  if (r < 0) r = 0;
+  if (r > n - 1) r = n - 1;
+  auto start = [&](int64_t q) { return q * n - q * (q - 1) / 2; };
+  while (r > 0 && start(r) > lt) --r;
+  while (r + 1 < n && start(r + 1) <= lt) ++r;
+  ti = (int)r;
+  tj = (int)(r + (lt - start(r)));
+}
+
+template <typename R, int T>
+struct SweepSmem {
+  using C = typename Cx<R>::V;
+  static constexpr int kSlot = 2 * T * T;       // complex per sample-site
+  static constexpr int kStride = kSlot + 1;     // padded against bank conflicts
+  C a[2][kTile * kStride];
+  C b[2][kTile * kStride];
+};
+
+template <typename R, int T>
+__device__ void run_tile(const QkTask& t, int ti, int tj, SweepSmem<R, T>& sm) {
+  using C = typename Cx<R>::V;
+  constexpr int kSlot = SweepSmem<R, T>::kSlot;
+  constexpr int kStride = SweepSmem<R, T>::kStride;
+  const int tid = threadIdx.x;
+  const int r = tid / kTile, c = tid % kTile;
+  const int64_t i0 = (int64_t)ti * kTile, j0 = (int64_t)tj * kTile;
+  const int64_t i = i0 + r, j = j0 + c;
+  const C* ta = static_cast<const C*>(t.ta);
+  const C* tb = static_cast<const C*>(t.tb);
+  const int nq = t.nq;
+
+  // global -> register staging of one site for the whole tile
+  constexpr int kPer = (2 * kTile * kSlot + kThreads - 1) / kThreads;
+  C stage[kPer];
+  auto load_site = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      int e = tid + q * kThreads;
+      C v;
+      v.x = 0;
+      v.y = 0;
+      if (e < 2 * kTile * kSlot) {
+        int side = e / (kTile * kSlot);
+        int rem = e % (kTile * kSlot);
+        int smp = rem / kSlot;
+        if (side == 0) {
+          if (i0 + smp < t.na) v = ta[((int64_t)k * t.na + i0) * kSlot + rem];
+        } else {
+          if (j0 + smp < t.nb) v = tb[((int64_t)k * t.nb + j0) * kSlot + rem];
+        }
+      }
+      stage[q] = v;
+    }
+  };
+  auto store_site = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      int e = tid + q * kThreads;
+      if (e < 2 * kTile * kSlot) {
+        int side = e / (kTile * kSlot);
+        int rem = e % (kTile * kSlot);
+        int smp = rem / kSlot, o = rem % kSlot;
+        if (side == 0) sm.a[buf][smp * kStride + o] = stage[q];
+        else sm.b[buf][smp * kStride + o] = stage[q];
+      }
+    }
+  };
+
+  R er[T][T], ei[T][T];
+#pragma unroll
+  for (int a = 0; a < T; ++a)
+#pragma unroll
+    for (int b = 0; b < T; ++b) {
+      er[a][b] = (a == 0 && b == 0) ? R(1) : R(0);
+      ei[a][b] = R(0);
+    }
+  int expo = 0;
+
+  load_site(0);
+  store_site(0);
+  __syncthreads();
+  for (int k = 0; k < nq; ++k) {
+    const int buf = k & 1;
+    if (k + 1 < nq) load_site(k + 1);
+    const C* As = &sm.a[buf][r * kStride];
+    const C* Bs = &sm.b[buf][c * kStride];
+    R nr[T][T], ni[T][T];
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+      for (int b = 0; b < T; ++b) {
+        nr[a][b] = R(0);
+        ni[a][b] = R(0);
+      }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      // G = E B^s (T x T), then E' += A^{s dagger} G
+      R gr[T][T], gi[T][T];
+#pragma unroll
+      for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int bb = 0; bb < T; ++bb) {
+          gr[a][bb] = R(0);
+          gi[a][bb] = R(0);
+        }
+#pragma unroll
+      for (int b = 0; b < T; ++b)
+#pragma unroll
+        for (int bb = 0; bb < T; ++bb) {
+          C bv = Bs[s * T * T + b * T + bb];
+#pragma unroll
+          for (int a = 0; a < T; ++a) {
+            gr[a][bb] += er[a][b] * bv.x - ei[a][b] * bv.y;
+            gi[a][bb] += er[a][b] * bv.y + ei[a][b] * bv.x;
+          }
+        }
+#pragma unroll
+      for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int aa = 0; aa < T; ++aa) {
+          C av = As[s * T * T + a * T + aa];  // A^s[a][aa]; dagger -> conj
+#pragma unroll
+          for (int bb = 0; bb < T; ++bb) {
+            nr[aa][bb] += av.x * gr[a][bb] + av.y * gi[a][bb];
+            ni[aa][bb] += av.x * gi[a][bb] - av.y * gr[a][bb];
+          }
+        }
+    }
+    // exact power-of-two rescale
+    R m = R(0);
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+      for (int b = 0; b < T; ++b) m = fmax(m, fmax(fabs(nr[a][b]), fabs(ni[a][b])));
+    int e = m > R(0) ? frexp_exp(m) : 0;
+    R sc = pow2(R(0), -e);
+    expo += e;
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+      for (int b = 0; b < T; ++b) {
+        er[a][b] = nr[a][b] * sc;
+        ei[a][b] = ni[a][b] * sc;
+      }
+    if (k + 1 < nq) store_site(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: ln K_q, K_q, optional RBF and mix; FP64
+  const bool valid = i < t.na && j < t.nb && (!t.symmetric || j >= i);
+  if (!valid) return;
+  const double re = (double)er[0][0], im = (double)ei[0][0];
+  const double mag2 = re * re + im * im;
+  const double lnk = mag2 > 0.0 ? log(mag2) + 2.0 * (double)expo * 0.69314718055994530942
+                                : -INFINITY;
+  const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
+  auto put = [&](double* p, int64_t ld, double v) {
+    if (!p) return;
+    p[i * ld + j] = v;
+    if (t.symmetric && j != i) p[j * ld + i] = v;
+  };
+  put(t.kq, t.ld_kq, kq);
+  put(t.lnkq, t.ld_ln, lnk);
+  if (t.fuse) {
+    const double* xr = t.xr + i * t.ld_xr;
+    const double* xc = t.xc + j * t.ld_xc;
+    double d2 = 0.0;
+    for (int f = 0; f < nq; ++f) {
+      double df = xr[f] - xc[f];
+      d2 += df * df;
+    }
+    const double kc = exp(-t.gamma * d2);
+    put(t.kc, t.ld_kc, kc);
+    put(t.k, t.ld_k, t.w * kq + (1.0 - t.w) * kc);
+  }
+}
+
+// Largest T the persistent kernel instantiates for each real type.
+template <typename R>
+struct MaxT;
+template <>
+struct MaxT<double> {
+  static constexpr int v = 4;
+};
+template <>
+struct MaxT<float> {
+  static constexpr int v = 4;
+};
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void sweep_valu_kernel(QkTaskTable tt) {
+  __shared__ SweepSmem<R, MaxT<R>::v> sm4;
+  for (int64_t q = blockIdx.x; q < tt.total_tiles; q += gridDim.x) {
+    int ti_task = 0;
+    while (ti_task + 1 < tt.n_tasks && tt.t[ti_task + 1].tile_begin <= q) ++ti_task;
+    const QkTask& t = tt.t[ti_task];
+    int ti, tj;
+    tile_coords(t, q - t.tile_begin, ti, tj);
+    switch (t.T) {
+      case 1:
+        run_tile<R, 1>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 1>*>(&sm4));
+        break;
+      case 2:
+        run_tile<R, 2>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 2>*>(&sm4));
+        break;
+      default:
+        run_tile<R, 4>(t, ti, tj, sm4);
+        break;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+int qk_sweep_valu_tile() { return kTile; }
+
+hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, hipStream_t s) {
+  if (tt.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(sweep_valu_kernel<double>, dim3(grid), dim3(kThreads), 0, s, tt);
+  return hipGetLastError();
+}
+
+hipError_t qk_launch_sweep_fp32(const QkTaskTable& tt, int grid, hipStream_t s) {
+  if (tt.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(sweep_valu_kernel<float>, dim3(grid), dim3(kThreads), 0, s, tt);
+  return hipGetLastError();
+}

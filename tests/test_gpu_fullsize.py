@@ -1,0 +1,65 @@
+"""Full-size parity: the 784-qubit image workload (4000 train + 1000 test,
+L = 2, chi_max 64) in the launch configuration the benchmark times (one
+persistent multi-task sweep with the fused epilogue), checked on the seeded
+200-pair subset stored by tests/golden/make_golden.py (exact path-sum
+values) and by properties that hold at any size."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import checks  # noqa: E402
+from synthdata import config_inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.mark.parametrize("prec", ["auto", "fp64"])
+def test_c3_full_gram_sampled(prec):
+    import paper_2602_01330_amd.qk as qk
+    g = json.load(open(os.path.join(GOLDEN, "c3_pathsum_200.json")))
+    x_tr, x_te, _ = config_inputs("C3")
+    print(f"[C3 full {prec}] 4000+1000 d=784", flush=True)
+    dev = torch.device("cuda")
+    xtr = torch.as_tensor(x_tr, device=dev)
+    xte = torch.as_tensor(x_te, device=dev)
+    store = qk.QK_STORE_FP64 if prec == "fp64" else qk.QK_STORE_ALL
+    btr = qk.qk_mps_build(xtr, 2, 64, 1e-10, store=store)
+    bte = qk.qk_mps_build(xte, 2, 64, 1e-10, store=store)
+    f64 = dict(dtype=torch.float64, device=dev)
+    A = {k: torch.full((4000, 4000), float("nan"), **f64) for k in ("kq", "ln", "kc", "k")}
+    B = {k: torch.full((1000, 4000), float("nan"), **f64) for k in ("kq", "ln", "kc", "k")}
+    tasks = [
+        {"rows": btr, "cols": btr, "symmetric": True, "kq": A["kq"], "lnkq": A["ln"],
+         "fuse": {"x_rows": xtr, "x_cols": xtr, "gamma": 1 / 784, "w": 0.5, "kc": A["kc"],
+                  "k": A["k"]}},
+        {"rows": bte, "cols": btr, "symmetric": False, "kq": B["kq"], "lnkq": B["ln"],
+         "fuse": {"x_rows": xte, "x_cols": xtr, "gamma": 1 / 784, "w": 0.5, "kc": B["kc"],
+                  "k": B["k"]}},
+    ]
+    qk.qk_overlap_gram_multi(tasks, prec)
+    torch.cuda.synchronize()
+    info = qk.qk_mps_info(btr)
+    qk.qk_mps_info(bte)
+    assert info["chi_realized_max"] == 4 and info["chi_pad"] == 4
+    pick = lambda M, rs: (A if rs == 0 else B)[M]
+    got = {k: np.array([pick(k, rs)[i, j].item() for rs, i, j in g["pairs"]])
+           for k in ("kq", "ln", "kc", "k")}
+    ok_b, lmax = checks.gate_b(got["ln"], np.array(g["lnkq"]))
+    assert ok_b, lmax
+    for key, ref in (("kq", "kq"), ("kc", "kc"), ("k", "k_w0.5")):
+        ok, dmax, rel = checks.gate_a(got[key], np.array(g[ref]))
+        assert ok, (key, dmax, rel)
+    # properties at full size
+    kq = A["kq"].cpu().numpy()
+    assert np.all(np.isfinite(kq)) and np.all(np.isfinite(B["kq"].cpu().numpy()))
+    assert np.max(np.abs(np.diag(kq) - 1.0)) <= 1e-5
+    assert np.array_equal(kq, kq.T)
+    assert kq.min() >= 0.0 and kq.max() <= 1.0 + 1e-5
+    kc = A["kc"].cpu().numpy()
+    assert np.array_equal(np.diag(kc), np.ones(4000))
