@@ -122,7 +122,7 @@ def run(args):
     stream = torch.cuda.current_stream()
 
     def one_step(prec, timing=None):
-        store = qk.QK_STORE_FP64 if prec == "fp64" else qk.QK_STORE_FP32
+        store = qk.QK_STORE_FP64 if prec == "fp64" else qk.QK_STORE_ALL
         btr = qk.qk_mps_build(xtr, 2, 64, 1e-10, store=store)
         bte = qk.qk_mps_build(xte, 2, 64, 1e-10, store=store)
         tasks = [

@@ -228,6 +228,17 @@ QK_API qk_status qk_dual_mix(const double* kq_dev, int64_t ld_kq, const double* 
                       int64_t ld_kc, int64_t m, int64_t n, double w,
                       double* k_dev, int64_t ld_k, void* hip_stream);
 
+/*
+ * Reduced-precision forms (QK_PREC_FP32, _FP32_MFMA, _BF16X2, _BF16X3) carry
+ * a relative error of ~1e-5 (FP32-class) or ~2e-4 (BF16X2) in K_q after
+ * hundreds of sites, which exceeds 1e-5 absolute only where K_q is large.
+ * After such a sweep every 16 x 16 pair tile holding a K_q above tau is
+ * recomputed by the FP64 sweep (this needs QK_STORE_FP64 in the batches).
+ * Defaults: tau = 1e-2 (FP32-class forms), 1e-3 (BF16X2). tau <= 0
+ * disables refinement for that form. Process-wide setting.
+ */
+QK_API qk_status qk_set_refine_threshold(qk_precision prec, double tau);
+
 /* Resolves QK_PREC_AUTO for a batch pair: writes the form the library
  * would run (from the tuning table, else the built-in default). */
 QK_API qk_status qk_resolve_precision(const qk_mps_batch* rows,

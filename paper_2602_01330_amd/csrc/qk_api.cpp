@@ -129,7 +129,7 @@ qk_status finish_batch(qk_mps_batch* b, uint32_t store) {
 }
 
 qk_status fill_task(QkTask& t, const qk_mps_batch* rows, const qk_mps_batch* cols,
-                    int32_t symmetric, bool fp64, double* kq, int64_t ld_kq,
+                    int32_t symmetric, bool fp64, bool refine, double* kq, int64_t ld_kq,
                     double* lnkq, int64_t ld_ln, const qk_fuse_desc* fuse, int tile) {
   if (!rows || !cols) return fail(QK_ERR_INVALID_ARG, "batch is NULL");
   if (rows->nq != cols->nq) return fail(QK_ERR_INVALID_ARG, "qubit counts differ");
@@ -146,9 +146,15 @@ qk_status fill_task(QkTask& t, const qk_mps_batch* rows, const qk_mps_batch* col
     return fail(QK_ERR_INVALID_ARG, "FP64 sweep needs batches built with QK_STORE_FP64");
   if (!fp64 && (!rows->t32 || !cols->t32))
     return fail(QK_ERR_INVALID_ARG, "this sweep needs batches built with QK_STORE_FP32");
+  if (!fp64 && refine && (!rows->t64 || !cols->t64))
+    return fail(QK_ERR_INVALID_ARG,
+                "FP64 refinement of large entries needs batches built with QK_STORE_FP64 "
+                "(or disable it with qk_set_refine_threshold)");
   memset(&t, 0, sizeof(t));
   t.ta = fp64 ? (const void*)rows->t64 : (const void*)rows->t32;
   t.tb = fp64 ? (const void*)cols->t64 : (const void*)cols->t32;
+  t.ta64 = rows->t64;
+  t.tb64 = cols->t64;
   t.na = rows->n;
   t.nb = cols->n;
   t.nq = rows->nq;
@@ -196,7 +202,16 @@ bool supported_T(qk_precision p, int T) {
   }
 }
 
-qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, hipStream_t s) {
+// Refinement thresholds on K_q per form (<= 0 disables refinement).
+double g_refine_tau[6] = {0.0, 1e-2, 1e-3, 1e-2, 0.0, 1e-2};
+std::mutex g_refine_mu;
+
+double refine_tau(qk_precision p) {
+  std::lock_guard<std::mutex> lk(g_refine_mu);
+  return (p >= 0 && p < 6) ? g_refine_tau[p] : 0.0;
+}
+
+qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, hipStream_t s) {
   // longest-processing-time order: per-tile cost ~ nq * T^3
   std::stable_sort(tasks.begin(), tasks.end(), [](const QkTask& a, const QkTask& b) {
     return (double)a.nq * a.T * a.T * a.T > (double)b.nq * b.T * b.T * b.T;
@@ -212,15 +227,32 @@ qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, hipStream_t s
   tt.n_tasks = (int32_t)tasks.size();
   tt.total_tiles = acc;
   if (acc == 0) return QK_OK;
-  hipError_t e;
-  if (prec == QK_PREC_FP64 || prec == QK_PREC_FP32) {
-    const int per_cu = prec == QK_PREC_FP64 ? 2 : 3;
-    int grid = (int)std::min<int64_t>(acc, (int64_t)device_cus() * per_cu);
-    e = prec == QK_PREC_FP64 ? qk_launch_sweep_fp64(tt, grid, s)
-                             : qk_launch_sweep_fp32(tt, grid, s);
-  } else {
-    e = qk_launch_sweep_mfma(tt, prec, device_cus(), s);
+  const int grid64 = (int)std::min<int64_t>(acc, (int64_t)device_cus() * 2);
+  if (prec == QK_PREC_FP64) {
+    QK_HIP(qk_launch_sweep_fp64(tt, grid64, nullptr, s), "sweep launch");
+    return QK_OK;
   }
+  const bool refine = tau > 0.0;
+  uint8_t* flags = nullptr;
+  if (refine) QK_HIP(hipMallocAsync((void**)&flags, acc, s), "flag allocation");
+  const double ln_tau = refine ? std::log(tau) : 0.0;
+  hipError_t e;
+  if (prec == QK_PREC_FP32) {
+    int grid = (int)std::min<int64_t>(acc, (int64_t)device_cus() * 3);
+    e = qk_launch_sweep_fp32(tt, grid, flags, ln_tau, s);
+  } else {
+    e = qk_launch_sweep_mfma(tt, prec, device_cus(), flags, ln_tau, s);
+  }
+  if (e == hipSuccess && refine) {
+    // FP64 pass over the flagged tiles only, same tile numbering
+    QkTaskTable t64 = tt;
+    for (int k = 0; k < t64.n_tasks; ++k) {
+      t64.t[k].ta = t64.t[k].ta64;
+      t64.t[k].tb = t64.t[k].tb64;
+    }
+    e = qk_launch_sweep_fp64(t64, grid64, flags, s);
+  }
+  if (refine) (void)hipFreeAsync(flags, s);
   if (e != hipSuccess) return hip_fail(e, "sweep launch");
   return QK_OK;
 }
@@ -409,10 +441,11 @@ qk_status qk_overlap_gram_multi(const qk_gram_task* tasks, int32_t n_tasks,
     return fail(QK_ERR_INVALID_ARG, "unknown precision");
   std::vector<QkTask> tv(n_tasks);
   const int tile = tile_for(prec);
+  const double tau = prec == QK_PREC_FP64 ? 0.0 : refine_tau(prec);
   for (int k = 0; k < n_tasks; ++k) {
     const qk_gram_task& g = tasks[k];
     qk_status st = fill_task(tv[k], g.rows, g.cols, g.symmetric, prec == QK_PREC_FP64,
-                             g.kq_dev, g.ld_kq, g.lnkq_dev, g.ld_ln,
+                             tau > 0.0, g.kq_dev, g.ld_kq, g.lnkq_dev, g.ld_ln,
                              g.use_fuse ? &g.fuse : nullptr, tile);
     if (st != QK_OK) return st;
     if (!supported_T(prec, tv[k].T))
@@ -424,7 +457,16 @@ qk_status qk_overlap_gram_multi(const qk_gram_task* tasks, int32_t n_tasks,
     QK_HIP(hipStreamWaitEvent(s, tasks[k].rows->ready, 0), "wait for row batch");
     QK_HIP(hipStreamWaitEvent(s, tasks[k].cols->ready, 0), "wait for column batch");
   }
-  return run_tasks(tv, prec, s);
+  return run_tasks(tv, prec, tau, s);
+}
+
+qk_status qk_set_refine_threshold(qk_precision prec, double tau) {
+  if (prec <= QK_PREC_FP64 || prec > QK_PREC_FP32_MFMA || prec == QK_PREC_AUTO)
+    return fail(QK_ERR_INVALID_ARG, "refinement applies to the reduced-precision forms");
+  if (!std::isfinite(tau)) return fail(QK_ERR_INVALID_ARG, "tau must be finite");
+  std::lock_guard<std::mutex> lk(g_refine_mu);
+  g_refine_tau[prec] = tau;
+  return QK_OK;
 }
 
 qk_status qk_rbf_gram(const double* x_dev, int64_t m, int64_t ld_x, const double* y_dev,

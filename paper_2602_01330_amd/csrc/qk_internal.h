@@ -42,6 +42,8 @@ hipError_t qk_launch_pack32(const double2* t64, float2* t32, int64_t count,
 struct QkTask {
   const void* ta;        // row tensors (double2* or float2*), [nq][na][2][T][T]
   const void* tb;        // column tensors
+  const void* ta64;      // FP64 forms, used by the refinement pass (may be null)
+  const void* tb64;
   int64_t na, nb;        // sample counts
   int32_t nq, T;
   int32_t symmetric;
@@ -66,10 +68,14 @@ struct QkTaskTable {
   int64_t total_tiles;
 };
 
-// Sweep launchers (sweep_valu.hip / sweep_mfma.hip). Tiles are 16 x 16
-// pairs for the VALU kernels and tile_r x tile_c for MFMA.
-hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, hipStream_t s);
-hipError_t qk_launch_sweep_fp32(const QkTaskTable& tt, int grid, hipStream_t s);
+// Sweep launchers (sweep_valu.hip / sweep_mfma.hip). Every sweep kernel uses
+// 16 x 16 pair tiles with the same tile numbering, so a flag per tile written
+// by one pass (1 = the tile holds a K_q above the refinement threshold) can
+// select the tiles of another. flags_out may be null; flags_in null = all.
+hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, const uint8_t* flags_in,
+                                hipStream_t s);
+hipError_t qk_launch_sweep_fp32(const QkTaskTable& tt, int grid, uint8_t* flags_out,
+                                double ln_tau, hipStream_t s);
 int qk_sweep_valu_tile();
 
 hipError_t qk_launch_rbf(const double* x, int64_t m, int64_t ld_x,

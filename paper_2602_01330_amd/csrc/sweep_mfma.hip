@@ -1,10 +1,406 @@
-// Matrix-core (MFMA) forms of the overlap sweep.
+// Matrix-core (MFMA) forms of the transfer-matrix overlap sweep, chi_pad <= 4.
+//
+// Per pair (i, j) and site k:  E' = sum_s A_i^{s dagger} E B_j^s  (E is 4 x 4
+// complex). Complex products are realified, [Re C | Im C] = [Re X | Im X] .
+// [[Re Y, Im Y], [-Im Y, Re Y]], and each site is two GEMM-shaped steps:
+//
+//   step R (right multiply, shared by the pairs of one column j):
+//     G[(p,a)][(s,c,b')] = sum_{(c_in,b)} E[(p,a)][(c_in,b)] Bhat_j[(c_in,b)][(s,c,b')]
+//     16 x 16 x 8 per column of four pairs -> two 16x16x4 MFMAs, every lane busy;
+//   step L (left multiply, shared by the pairs of one row i):
+//     E'[(c',a')][(q,b')] = sum_{(s,c_in,a)} Ahat_i[(c',a')][(s,c_in,a)] G[(s,c_in,a)][(q,b')]
+//     8 x 16 x 16 per row of four pairs -> four 16x16x4 MFMAs whose rows 8..15 are
+//     zero: chi = 4 gives only 8 realified output rows, so this step runs the
+//     matrix cores at half width (the ceiling of the whole sweep is 2/3 of
+//     the MFMA peak at chi = 4).
+//
+// A wavefront owns a 4 x 4 block of pairs and runs its whole chain of sites
+// without workgroup barriers: every lane loads its own operand values of the
+// next site (prefetched one site ahead; the 16 waves of a workgroup share the
+// 16 row and 16 column samples of a 16 x 16 tile, so the loads hit the CU's
+// L1/L2), and the two re-layouts between the steps (MFMA output -> operand of
+// the other step) go through a per-wave LDS area. Each
+// pair's E is scaled by an exact power of two every fourth site (per-pair
+// int32 exponent); the FP32 range leaves ample room for four sites of decay.
+//
+// Forms: FP32 operands on v_mfma_f32_16x16x4f32; or split BF16 on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation -- BF16x2: x = h + l with
+// round-to-nearest pieces (|x - h - l| <= 2^-18 |x|), the products hh, hl,
+// lh, ll; BF16x3: x = h + m + l exactly (8+8+8 bits), the
+// products of total order <= 2 plus m*l and l*m (8 per real product). The
+// split is folded into the contraction index, so one MFMA K of 32 covers four
+// (BF16x2) or eight (BF16x3) products of each FP32 term.
+//
+// Reduced-precision forms flag every tile holding a K_q above a threshold;
+// flagged tiles are recomputed by the FP64 sweep (qk_launch_sweep_fp64 with
+// the flags) so that entries near 1 carry FP64 accuracy.
 #include <hip/hip_runtime.h>
 
 #include "qk_tune.h"
 
-bool qk_mfma_supports(qk_precision, int) { return false; }
-int qk_mfma_tile(qk_precision) { return 16; }
-hipError_t qk_launch_sweep_mfma(const QkTaskTable&, qk_precision, int, hipStream_t) {
-  return hipErrorInvalidValue;
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+enum Form { kF32 = 0, kBF16x2 = 1, kBF16x3 = 2 };
+
+constexpr int kWaves = 16;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kTile = 16;
+// Per-wave LDS areas (floats). Strides are chosen so that the accesses of
+// each half-wave (b32, 32 lanes) or lane octet (b128) fall in distinct banks
+// of a 32-bank LDS:
+//   G[p][q][a][b'][(s,c)] = p*336 + q*80 + a*16 + b'*4 + (s,c)
+//     written b32 by lanes (p, (s,c,b')), read b128 by lanes (a, (q,b'));
+//   E[q][p][a][(b,c)]     = q*136 + p*34 + a*8 + b*2 + c
+//     written b32 by lanes (c, (q,b)), read b64 by lanes (b, (p,a)).
+constexpr int kGp = 336, kGq = 80, kGa = 16;
+constexpr int kEq = 136, kEp = 34;
+constexpr int kRescaleEvery = 4;  // sites between exact rescales
+
+struct MfmaSmem {
+  float g[kWaves][4 * kGp];
+  float e[kWaves][4 * kEq];
+  int ex[kWaves][16];
+  int flag;
+};
+
+// max over lanes l ^ 1 and l ^ 2 (DPP quad permutations) and l ^ 16 (swizzle)
+__device__ inline float max_xor_1_2_16(float m) {
+  m = fmaxf(m, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(m), 0xB1, 0xF, 0xF, false)));
+  m = fmaxf(m, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(m), 0x4E, 0xF, 0xF, false)));
+  m = fmaxf(m, __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(m), 0x401F)));
+  return m;
+}
+
+__device__ inline int frexp_exp(float m) {
+  return (int)((__float_as_uint(m) >> 23) & 0xff) - 126;
+}
+__device__ inline float pow2f(int e) { return __uint_as_float((unsigned)(e + 127) << 23); }
+
+__device__ inline __bf16 bf16_trunc(float x) {
+  unsigned short h = (unsigned short)(__float_as_uint(x) >> 16);
+  return __builtin_bit_cast(__bf16, h);
+}
+__device__ inline float bf16_trunc_f(float x) { return __uint_as_float(__float_as_uint(x) & 0xffff0000u); }
+
+// pieces of x: BF16x2 -> (h, l), BF16x3 -> (h, m, l)
+template <int F>
+struct Split;
+template <>
+struct Split<kBF16x2> {
+  __bf16 p[2];
+  __device__ Split(float x) {
+    // round-to-nearest pieces: |x - h - l| <= 2^-18 |x|
+    p[0] = (__bf16)x;
+    p[1] = (__bf16)(x - (float)p[0]);
+  }
+};
+template <>
+struct Split<kBF16x3> {
+  __bf16 p[3];
+  __device__ Split(float x) {
+    float h = bf16_trunc_f(x);
+    float r = x - h;
+    float m = bf16_trunc_f(r);
+    p[0] = bf16_trunc(x);
+    p[1] = bf16_trunc(r);
+    p[2] = (__bf16)(r - m);
+  }
+};
+
+// piece index of the left / right factor for product term t
+__device__ constexpr int lhs_piece2(int t) { return t >> 1; }       // h h l l
+__device__ constexpr int rhs_piece2(int t) { return t & 1; }        // h l h l
+__device__ constexpr int lhs_piece3(int t) {                        // 0 0 1 0 1 2 1 2
+  return t == 0 ? 0 : t == 1 ? 0 : t == 2 ? 1 : t == 3 ? 0 : t == 4 ? 1 : t == 5 ? 2 : t == 6 ? 1 : 2;
+}
+__device__ constexpr int rhs_piece3(int t) {                        // 0 1 0 2 1 0 2 1
+  return t == 0 ? 0 : t == 1 ? 1 : t == 2 ? 0 : t == 3 ? 2 : t == 4 ? 1 : t == 5 ? 0 : t == 6 ? 2 : 1;
+}
+
+// acc += sum over NC FP32 contraction chunks: a[c] (lane's A value) * b[c]
+// (lane's B value), in the 16x16x4 lane layout; for the split forms the
+// chunks and product terms are folded into 16x16x32 instructions.
+template <int F, int NC>
+__device__ inline f4 mma(const float* a, const float* b, f4 acc) {
+  if constexpr (F == kF32) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b[c], acc, 0, 0, 0);
+  } else if constexpr (F == kBF16x2) {
+    // 4 products per chunk -> 2 chunks per instruction
+#pragma unroll
+    for (int c0 = 0; c0 < NC; c0 += 2) {
+      bf8 va, vb;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        Split<kBF16x2> sa(a[c0 + h]), sb(b[c0 + h]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          va[h * 4 + t] = sa.p[lhs_piece2(t)];
+          vb[h * 4 + t] = sb.p[rhs_piece2(t)];
+        }
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, acc, 0, 0, 0);
+    }
+  } else {
+    // 8 products per chunk -> one chunk per instruction
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      bf8 va, vb;
+      Split<kBF16x3> sa(a[c]), sb(b[c]);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        va[t] = sa.p[lhs_piece3(t)];
+        vb[t] = sb.p[rhs_piece3(t)];
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, acc, 0, 0, 0);
+    }
+  }
+  return acc;
+}
+
+__device__ inline void tile_coords(const QkTask& t, int64_t lt, int& ti, int& tj) {
+  if (!t.symmetric) {
+    ti = (int)(lt / t.tiles_c);
+    tj = (int)(lt % t.tiles_c);
+    return;
+  }
+  const int64_t n = t.tiles_c;
+  double b = 2.0 * n + 1.0;
+  int64_t r = (int64_t)((b - sqrt(b * b - 8.0 * (double)lt)) * 0.5);
+  if (r < 0) r = 0;
+  if (r > n - 1) r = n - 1;
+  auto start = [&](int64_t q) { return q * n - q * (q - 1) / 2; };
+  while (r > 0 && start(r) > lt) --r;
+  while (r + 1 < n && start(r + 1) <= lt) ++r;
+  ti = (int)r;
+  tj = (int)(r + (lt - start(r)));
+}
+
+#define QK_LDS_FENCE() __asm__ volatile("" ::: "memory")
+
+template <int F, bool kFullT>
+__device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint8_t* flags,
+                         int64_t tile_id, double ln_tau) {
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index: scalar
+  const int lane = tid & 63;
+  const int g = lane >> 4, n = lane & 15;
+  const int wr = w >> 2, wc = w & 3;
+  const int64_t i0 = (int64_t)ti * kTile + 4 * wr, j0 = (int64_t)tj * kTile + 4 * wc;
+  const float2* ta = static_cast<const float2*>(t.ta);
+  const float2* tb = static_cast<const float2*>(t.tb);
+  const int T = kFullT ? 4 : t.T, TT = T * T, slotT = 2 * TT;
+  const int nq = t.nq;
+  float* gb = sm.g[w];
+  float* eb = sm.e[w];
+
+  // ---- per-lane 32-bit operand offsets from the wave's (scalar) site base.
+  // Samples past the end are clamped to the last one: those pairs compute
+  // garbage that is never written, and every pair's E is independent.
+  // step R, column q: B^s[b = g][b' = n&3], s = n>>3
+  const int rs = n >> 3, rcout = (n >> 2) & 1, rbp = n & 3;
+  // step L, row p: A^s[a = g][a' = n&3] for s = 0, 1 (lanes n < 8)
+  const int lcp = n >> 2, lap = n & 3;
+  int boff[4], aoff[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = (j0 + q) < t.nb ? (j0 + q) : (t.nb - 1);
+    const int64_t i = (i0 + q) < t.na ? (i0 + q) : (t.na - 1);
+    boff[q] = (int)((j - j0) * slotT) + rs * TT + (g < T ? g : 0) * T + (rbp < T ? rbp : 0);
+    aoff[q] = (int)((i - i0) * slotT) + (g < T ? g : 0) * T + (lap < T ? lap : 0);
+  }
+  // zero the elements outside the padded bond block (only when T < 4)
+  const bool bin = kFullT || (g < T && rbp < T);
+  const bool ain = kFullT || (g < T && lap < T);
+  const int64_t bstride = (int64_t)t.nb * slotT, astride = (int64_t)t.na * slotT;
+  const float2* bbase = tb + j0 * slotT;
+  const float2* abase = ta + i0 * slotT;
+  float2 bcur[4], acur[4][2];
+  auto fetch_b = [&](int k) {
+    const float2* p = bbase + (int64_t)k * bstride;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float2 v = p[boff[q]];
+      bcur[q] = kFullT ? v : make_float2(bin ? v.x : 0.f, bin ? v.y : 0.f);
+    }
+  };
+  auto fetch_a = [&](int k) {
+    const float2* p = abase + (int64_t)k * astride;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float2 v0 = p[aoff[q]], v1 = p[aoff[q] + TT];
+      acur[q][0] = kFullT ? v0 : make_float2(ain ? v0.x : 0.f, ain ? v0.y : 0.f);
+      acur[q][1] = kFullT ? v1 : make_float2(ain ? v1.x : 0.f, ain ? v1.y : 0.f);
+    }
+  };
+
+  // E in step-R operand form: lane (p = n>>2, a = n&3, b = g) holds Re/Im E[a][b]
+  float eR[4][2];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    eR[q][0] = ((n & 3) == 0 && g == 0) ? 1.f : 0.f;
+    eR[q][1] = 0.f;
+  }
+  int expo[4] = {0, 0, 0, 0};
+
+  fetch_b(0);
+  fetch_a(0);
+  for (int k = 0; k < nq; ++k) {
+    // ---- step R: G = E Bhat_j for the wave's four columns; the lane's
+    // G[(p=g, a=r)][(s, cout, b')] of pair (g, q) goes out as four b32 stores
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float2 bv = bcur[q];
+      float bop[2];
+      bop[0] = rcout ? bv.y : bv.x;
+      bop[1] = rcout ? bv.x : -bv.y;
+      f4 z = {0.f, 0.f, 0.f, 0.f};
+      const f4 dr = mma<F, 2>(eR[q], bop, z);
+      float* gw = &gb[g * kGp + q * kGq + rbp * 4 + (rs * 2 + rcout)];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gw[r * kGa] = dr[r];
+    }
+    if (k + 1 < nq) fetch_b(k + 1);  // in flight during step L
+    QK_LDS_FENCE();
+    // ---- step L: E' = Ahat_i^dagger G for the wave's four rows, then the
+    // exact power-of-two rescale every few sites (pair (p, q) lives on lanes
+    // g in {0,1}, n>>2 == q: 4 lanes b' x 4 registers), then E' to LDS
+    {
+      const int q = n >> 2, bp = n & 3;  // output column (q, b')
+      const bool rescale = (k % kRescaleEvery) == kRescaleEvery - 1 || k + 1 == nq;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const float2 a0 = acur[p][0], a1 = acur[p][1];
+        float aop[4];
+        aop[0] = lcp == 0 ? a0.x : -a0.y;  // s = 0, c_in = 0
+        aop[1] = lcp == 0 ? a0.y : a0.x;   // s = 0, c_in = 1
+        aop[2] = lcp == 0 ? a1.x : -a1.y;  // s = 1, c_in = 0
+        aop[3] = lcp == 0 ? a1.y : a1.x;   // s = 1, c_in = 1
+        if (n >= 8) aop[0] = aop[1] = aop[2] = aop[3] = 0.f;
+        const f4 gv = *reinterpret_cast<const f4*>(&gb[p * kGp + q * kGq + g * kGa + bp * 4]);
+        float bop[4] = {gv[0], gv[1], gv[2], gv[3]};
+        f4 z = {0.f, 0.f, 0.f, 0.f};
+        f4 dl = mma<F, 4>(aop, bop, z);
+        if (rescale) {
+          float m = fmaxf(fmaxf(fabsf(dl[0]), fabsf(dl[1])), fmaxf(fabsf(dl[2]), fabsf(dl[3])));
+          m = max_xor_1_2_16(m);
+          const int e = m > 0.f ? frexp_exp(m) : 0;
+          const float sc = pow2f(-e);
+          expo[p] += e;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) dl[r] *= sc;
+        }
+        if (g < 2) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) eb[q * kEq + p * kEp + r * 8 + bp * 2 + g] = dl[r];
+        }
+      }
+      if (k + 1 < nq) fetch_a(k + 1);
+    }
+    QK_LDS_FENCE();
+    {
+      const int p = n >> 2, a = n & 3;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float2 ev = *reinterpret_cast<const float2*>(&eb[q * kEq + p * kEp + a * 8 + g * 2]);
+        eR[q][0] = ev.x;
+        eR[q][1] = ev.y;
+      }
+    }
+    QK_LDS_FENCE();
+  }
+
+  // ---- epilogue: pair (p, q) = (pi >> 2, pi & 3), four lanes per pair
+  if (g == 0 && (n & 3) == 0) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) sm.ex[w][p * 4 + (n >> 2)] = expo[p];
+  }
+  if (tid == 0) sm.flag = 0;
+  __syncthreads();
+  const int pi = lane & 15, part = lane >> 4;
+  const int p = pi >> 2, q = pi & 3;
+  const int64_t i = i0 + p, j = j0 + q;
+  const bool valid = i < t.na && j < t.nb && (!t.symmetric || j >= i);
+  const float2 av = *reinterpret_cast<const float2*>(&eb[q * kEq + p * kEp]);
+  const double re = (double)av.x, im = (double)av.y;
+  const double mag2 = re * re + im * im;
+  const double lnk = mag2 > 0.0 ? log(mag2) + 2.0 * (double)sm.ex[w][pi] * 0.69314718055994530942
+                                : -INFINITY;
+  const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
+  double d2 = 0.0;
+  if (t.fuse && valid) {
+    const double* xr = t.xr + i * t.ld_xr;
+    const double* xc = t.xc + j * t.ld_xc;
+    for (int f = part; f < nq; f += 4) {
+      const double df = xr[f] - xc[f];
+      d2 += df * df;
+    }
+  }
+  d2 += __shfl_xor(d2, 16, 64);
+  d2 += __shfl_xor(d2, 32, 64);
+  if (valid && part == 0) {
+    auto put = [&](double* ptr, int64_t ld, double v) {
+      if (!ptr) return;
+      ptr[i * ld + j] = v;
+      if (t.symmetric && j != i) ptr[j * ld + i] = v;
+    };
+    put(t.kq, t.ld_kq, kq);
+    put(t.lnkq, t.ld_ln, lnk);
+    if (t.fuse) {
+      const double kc = exp(-t.gamma * d2);
+      put(t.kc, t.ld_kc, kc);
+      put(t.k, t.ld_k, t.w * kq + (1.0 - t.w) * kc);
+    }
+    if (flags && lnk > ln_tau) atomicOr(&sm.flag, 1);
+  }
+  __syncthreads();
+  if (flags && tid == 0) flags[tile_id] = (uint8_t)sm.flag;
+}
+
+template <int F>
+__global__ __launch_bounds__(kThreads) void sweep_mfma_kernel(QkTaskTable tt, uint8_t* flags,
+                                                              double ln_tau) {
+  __shared__ MfmaSmem sm;
+  for (int64_t q = blockIdx.x; q < tt.total_tiles; q += gridDim.x) {
+    int k = 0;
+    while (k + 1 < tt.n_tasks && tt.t[k + 1].tile_begin <= q) ++k;
+    const QkTask& t = tt.t[k];
+    int ti, tj;
+    tile_coords(t, q - t.tile_begin, ti, tj);
+    if (t.T == 4) run_tile<F, true>(t, ti, tj, sm, flags, q, ln_tau);
+    else run_tile<F, false>(t, ti, tj, sm, flags, q, ln_tau);
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+bool qk_mfma_supports(qk_precision p, int T) {
+  const bool form = p == QK_PREC_FP32_MFMA || p == QK_PREC_BF16X2 || p == QK_PREC_BF16X3;
+  return form && (T == 1 || T == 2 || T == 4);
+}
+
+int qk_mfma_tile(qk_precision) { return kTile; }
+
+hipError_t qk_launch_sweep_mfma(const QkTaskTable& tt, qk_precision p, int cus,
+                                uint8_t* flags, double ln_tau, hipStream_t s) {
+  if (tt.total_tiles == 0) return hipSuccess;
+  const int grid = (int)(tt.total_tiles < (int64_t)cus ? tt.total_tiles : cus);
+  switch (p) {
+    case QK_PREC_FP32_MFMA:
+      hipLaunchKernelGGL(sweep_mfma_kernel<kF32>, dim3(grid), dim3(kThreads), 0, s, tt, flags, ln_tau);
+      break;
+    case QK_PREC_BF16X2:
+      hipLaunchKernelGGL(sweep_mfma_kernel<kBF16x2>, dim3(grid), dim3(kThreads), 0, s, tt, flags, ln_tau);
+      break;
+    case QK_PREC_BF16X3:
+      hipLaunchKernelGGL(sweep_mfma_kernel<kBF16x3>, dim3(grid), dim3(kThreads), 0, s, tt, flags, ln_tau);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }

@@ -77,7 +77,8 @@ struct SweepSmem {
 };
 
 template <typename R, int T>
-__device__ void run_tile(const QkTask& t, int ti, int tj, SweepSmem<R, T>& sm) {
+__device__ void run_tile(const QkTask& t, int ti, int tj, SweepSmem<R, T>& sm,
+                         int* tile_flag, double ln_tau) {
   using C = typename Cx<R>::V;
   constexpr int kSlot = SweepSmem<R, T>::kSlot;
   constexpr int kStride = SweepSmem<R, T>::kStride;
@@ -213,6 +214,7 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, SweepSmem<R, T>& sm) {
   const double mag2 = re * re + im * im;
   const double lnk = mag2 > 0.0 ? log(mag2) + 2.0 * (double)expo * 0.69314718055994530942
                                 : -INFINITY;
+  if (tile_flag && lnk > ln_tau) atomicOr(tile_flag, 1);
   const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
   auto put = [&](double* p, int64_t ld, double v) {
     if (!p) return;
@@ -248,9 +250,17 @@ struct MaxT<float> {
 };
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void sweep_valu_kernel(QkTaskTable tt) {
+__global__ __launch_bounds__(kThreads) void sweep_valu_kernel(QkTaskTable tt,
+                                                              const uint8_t* flags_in,
+                                                              uint8_t* flags_out,
+                                                              double ln_tau) {
   __shared__ SweepSmem<R, MaxT<R>::v> sm4;
+  __shared__ int tile_flag;
   for (int64_t q = blockIdx.x; q < tt.total_tiles; q += gridDim.x) {
+    if (flags_in && flags_in[q] == 0) continue;  // uniform per workgroup
+    if (threadIdx.x == 0) tile_flag = 0;
+    __syncthreads();
+    int* tf = flags_out ? &tile_flag : nullptr;
     int ti_task = 0;
     while (ti_task + 1 < tt.n_tasks && tt.t[ti_task + 1].tile_begin <= q) ++ti_task;
     const QkTask& t = tt.t[ti_task];
@@ -258,16 +268,17 @@ __global__ __launch_bounds__(kThreads) void sweep_valu_kernel(QkTaskTable tt) {
     tile_coords(t, q - t.tile_begin, ti, tj);
     switch (t.T) {
       case 1:
-        run_tile<R, 1>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 1>*>(&sm4));
+        run_tile<R, 1>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 1>*>(&sm4), tf, ln_tau);
         break;
       case 2:
-        run_tile<R, 2>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 2>*>(&sm4));
+        run_tile<R, 2>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 2>*>(&sm4), tf, ln_tau);
         break;
       default:
-        run_tile<R, 4>(t, ti, tj, sm4);
+        run_tile<R, 4>(t, ti, tj, sm4, tf, ln_tau);
         break;
     }
     __syncthreads();
+    if (flags_out && threadIdx.x == 0) flags_out[q] = (uint8_t)tile_flag;
   }
 }
 
@@ -275,14 +286,18 @@ __global__ __launch_bounds__(kThreads) void sweep_valu_kernel(QkTaskTable tt) {
 
 int qk_sweep_valu_tile() { return kTile; }
 
-hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, hipStream_t s) {
+hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, const uint8_t* flags_in,
+                                hipStream_t s) {
   if (tt.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(sweep_valu_kernel<double>, dim3(grid), dim3(kThreads), 0, s, tt);
+  hipLaunchKernelGGL(sweep_valu_kernel<double>, dim3(grid), dim3(kThreads), 0, s, tt, flags_in,
+                     (uint8_t*)nullptr, 0.0);
   return hipGetLastError();
 }
 
-hipError_t qk_launch_sweep_fp32(const QkTaskTable& tt, int grid, hipStream_t s) {
+hipError_t qk_launch_sweep_fp32(const QkTaskTable& tt, int grid, uint8_t* flags_out,
+                                double ln_tau, hipStream_t s) {
   if (tt.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(sweep_valu_kernel<float>, dim3(grid), dim3(kThreads), 0, s, tt);
+  hipLaunchKernelGGL(sweep_valu_kernel<float>, dim3(grid), dim3(kThreads), 0, s, tt,
+                     (const uint8_t*)nullptr, flags_out, ln_tau);
   return hipGetLastError();
 }

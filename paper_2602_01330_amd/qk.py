@@ -81,17 +81,19 @@ _lib.qk_rbf_gram.argtypes = [_P, C.c_int64, C.c_int64, _P, C.c_int64, C.c_int64,
 _lib.qk_dual_mix.argtypes = [_P, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int64, C.c_double,
                              _P, C.c_int64, _P]
 _lib.qk_resolve_precision.argtypes = [_P, _P, C.POINTER(C.c_int)]
+_lib.qk_set_refine_threshold.argtypes = [C.c_int, C.c_double]
 _lib.qk_status_string.restype = C.c_char_p
 _lib.qk_status_string.argtypes = [C.c_int]
 _lib.qk_last_error.restype = C.c_char_p
 for _f in ("qk_mps_build", "qk_mps_import", "qk_mps_info", "qk_mps_chi", "qk_mps_release",
            "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
-           "qk_resolve_precision"):
+           "qk_resolve_precision", "qk_set_refine_threshold"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTED = ["qk_mps_build", "qk_mps_import", "qk_mps_info", "qk_mps_chi", "qk_mps_release",
             "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
-            "qk_resolve_precision", "qk_status_string", "qk_last_error"]
+            "qk_resolve_precision", "qk_set_refine_threshold", "qk_status_string",
+            "qk_last_error"]
 
 
 def _check(st):
@@ -265,6 +267,15 @@ def qk_resolve_precision(rows: MpsBatch, cols: MpsBatch) -> str:
     out = C.c_int()
     _check(_lib.qk_resolve_precision(rows.handle, cols.handle, C.byref(out)))
     return PREC_NAME[out.value]
+
+
+def qk_set_refine_threshold(prec, tau: float):
+    """FP64 recomputation of tiles holding K_q > tau for a reduced form."""
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    _check(_lib.qk_set_refine_threshold(p, float(tau)))
+
+
+REFINE_DEFAULT = {"fp32": 1e-2, "fp32_mfma": 1e-2, "bf16x3": 1e-2, "bf16x2": 1e-3}
 
 
 def qk_status_string(s: int) -> str:

@@ -19,8 +19,12 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-@pytest.mark.parametrize("prec", ["auto", "fp64"])
-def test_c3_full_gram_sampled(prec):
+@pytest.mark.parametrize("prec,ln_tol", [("auto", 1e-3), ("fp64", 1e-3), ("fp32_mfma", 1e-3),
+                                         ("bf16x3", 1e-3), ("bf16x2", 1e-2)])
+def test_c3_full_gram_sampled(prec, ln_tol):
+    """Every form meets gate A (entries near 1 are FP64-refined) and gate B,
+    except BF16x2, whose 2^-17 products leave |d ln K_q| up to ~5e-3 after
+    784 sites: it is held to 1e-2 and is never chosen for such depths."""
     import paper_2602_01330_amd.qk as qk
     g = json.load(open(os.path.join(GOLDEN, "c3_pathsum_200.json")))
     x_tr, x_te, _ = config_inputs("C3")
@@ -50,7 +54,8 @@ def test_c3_full_gram_sampled(prec):
     pick = lambda M, rs: (A if rs == 0 else B)[M]
     got = {k: np.array([pick(k, rs)[i, j].item() for rs, i, j in g["pairs"]])
            for k in ("kq", "ln", "kc", "k")}
-    ok_b, lmax = checks.gate_b(got["ln"], np.array(g["lnkq"]))
+    ok_b, lmax = checks.gate_b(got["ln"], np.array(g["lnkq"]), tol=ln_tol)
+    print(f"[C3 full {prec}] max |d lnK| on the subset = {lmax:.3e}", flush=True)
     assert ok_b, lmax
     for key, ref in (("kq", "kq"), ("kc", "kc"), ("k", "k_w0.5")):
         ok, dmax, rel = checks.gate_a(got[key], np.array(g[ref]))

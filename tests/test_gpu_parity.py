@@ -59,7 +59,21 @@ def gpu_gram(qk, X, L, chi_max, prec, symmetric, Y=None, fuse_w=None, cutoff=1e-
     return out
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+FORMS = ["fp64", "fp32", "fp32_mfma", "bf16x2", "bf16x3"]
+# BF16x2 (2^-17 products) loses ~1e-3 of ln K_q to cancellation within a few
+# dozen sites: it is held to a 1e-2 log / relative bound, the others to the
+# stated gates.
+LN_TOL = {"fp64": 1e-3, "fp32": 1e-3, "fp32_mfma": 1e-3, "bf16x3": 1e-3, "bf16x2": 1e-2}
+REL_TOL = {"fp64": 1e-3, "fp32": 1e-3, "fp32_mfma": 1e-3, "bf16x3": 1e-3, "bf16x2": 1e-2}
+
+
+def gates(prec, k, kref, ln, lnref):
+    ok_a, dmax, rel = checks.gate_a(k, kref, rel_tol=REL_TOL[prec])
+    ok_b, lmax = checks.gate_b(ln, lnref, tol=LN_TOL[prec])
+    return ok_a and ok_b, (dmax, rel, lmax)
+
+
+@pytest.mark.parametrize("prec", FORMS)
 def test_c1_full_gram_vs_statevector_fixture(qk, prec):
     """C1: 200 x 8, L = 1; first 24 rows against the Eq. (7) statevector
     fixture, the whole matrix against the oracle MPS route."""
@@ -70,9 +84,8 @@ def test_c1_full_gram_vs_statevector_fixture(qk, prec):
     ref = np.array(fix["kq"])
     assert checks.gate_a(g["kq"][:24, :24], ref)[0]
     K, LN = oracle_gram(x, 1, 16, symmetric=True)
-    ok_a, dmax, _ = checks.gate_a(g["kq"], K)
-    ok_b, lmax = checks.gate_b(g["ln"], LN)
-    assert ok_a and ok_b, (dmax, lmax)
+    ok, (dmax, rel, lmax) = gates(prec, g["kq"], K, g["ln"], LN)
+    assert ok, (dmax, rel, lmax)
     if prec == "fp64":
         assert lmax < 1e-8, lmax
     kc = classical.rbf_gram(x, x, 1 / 8)
@@ -83,7 +96,7 @@ def test_c1_full_gram_vs_statevector_fixture(qk, prec):
     assert inv["diag_ok"] and inv["sym_ok"] and inv["range_ok"] and inv["psd_ok"], inv
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", FORMS)
 def test_c2_subset_train_and_test(qk, prec):
     """C2 generator (d = 64, L = 2, chi_max 32): 80 train rows (several tiles
     plus a ragged tail) symmetric, and 37 test rows x 80 train rows."""
@@ -91,20 +104,19 @@ def test_c2_subset_train_and_test(qk, prec):
     print(f"[C2 subset {prec}] 80+37 d=64", flush=True)
     g = gpu_gram(qk, xtr, 2, 32, prec, True, fuse_w=0.5)
     K, LN = oracle_gram(xtr, 2, 32, symmetric=True)
-    assert checks.gate_a(g["kq"], K)[0]
-    ok_b, lmax = checks.gate_b(g["ln"], LN)
-    assert ok_b, lmax
+    ok, info = gates(prec, g["kq"], K, g["ln"], LN)
+    assert ok, info
     h = gpu_gram(qk, xte, 2, 32, prec, False, Y=xtr, fuse_w=0.3)
     K2, LN2 = oracle_gram(xte, 2, 32, Y=xtr)
-    assert checks.gate_a(h["kq"], K2)[0]
-    assert checks.gate_b(h["ln"], LN2)[0]
+    ok, info = gates(prec, h["kq"], K2, h["ln"], LN2)
+    assert ok, info
     kc = classical.rbf_gram(xte, xtr, 1 / 64)
     assert checks.gate_a(h["kc"], kc)[0]
     assert checks.gate_a(h["k"], classical.mix(K2, kc, 0.3))[0]
     assert np.array_equal(g["chi"], oracle_chis(xtr, 2, 32))
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", FORMS)
 def test_imported_oracle_mps_sweep(qk, prec):
     """Oracle-built MPS uploaded through qk_mps_import: isolates the sweep."""
     X, _ = gen_clusters(21, 12, 99)
@@ -116,7 +128,7 @@ def test_imported_oracle_mps_sweep(qk, prec):
     qk.qk_overlap_gram(b, b, False, prec, kq, ln)
     torch.cuda.synchronize()
     K, LN = mps.gram(mps.pad_batch(M), mps.pad_batch(M))
-    ok_b, lmax = checks.gate_b(ln.cpu().numpy(), LN)
+    ok_b, lmax = checks.gate_b(ln.cpu().numpy(), LN, tol=LN_TOL[prec])
     assert ok_b, lmax
     if prec == "fp64":
         assert lmax < 1e-10
@@ -127,11 +139,11 @@ def test_edge_shapes(qk, n, d, L):
     """Ragged tiles, a single sample, d = 1 (no entangler), d = 2, L = 3."""
     X, _ = gen_clusters(n, d, 1000 + n + d)
     print(f"[edge] n={n} d={d} L={L}", flush=True)
-    for prec in ("fp64", "fp32"):
+    for prec in FORMS:
         g = gpu_gram(qk, X, L, 64, prec, True)
         K, LN = oracle_gram(X, L, 64, symmetric=True)
-        assert checks.gate_a(g["kq"], K)[0], prec
-        assert checks.gate_b(g["ln"], LN)[0], prec
+        ok, info = gates(prec, g["kq"], K, g["ln"], LN)
+        assert ok, (prec, info)
 
 
 def test_empty_batch_is_accepted(qk):
@@ -191,3 +203,31 @@ def test_determinism_bitwise(qk):
     a = gpu_gram(qk, X, 2, 64, "fp32", True)
     b = gpu_gram(qk, X, 2, 64, "fp32", True)
     assert np.array_equal(a["ln"], b["ln"])
+
+
+@pytest.mark.parametrize("prec,bound", [("fp32", 1e-3), ("fp32_mfma", 1e-3),
+                                        ("bf16x3", 1e-3), ("bf16x2", 3e-2)])
+def test_raw_precision_at_784_qubits(qk, prec, bound):
+    """Refinement off: the bare form against the oracle on image-like inputs
+    (d = 784, L = 2), same-class and cross-class pairs and the diagonal."""
+    x, _, _ = config_inputs("C3", n_train=24)
+    qk.qk_set_refine_threshold(prec, 0.0)
+    try:
+        g = gpu_gram(qk, x, 2, 64, prec, True)
+    finally:
+        qk.qk_set_refine_threshold(prec, qk.REFINE_DEFAULT[prec])
+    K, LN = oracle_gram(x, 2, 64, symmetric=True)
+    ok_b, lmax = checks.gate_b(g["ln"], LN, tol=bound)
+    print(f"[raw {prec}] max |d lnK| = {lmax:.3e}", flush=True)
+    assert ok_b, lmax
+
+
+def test_refinement_restores_fp64_on_large_entries(qk):
+    """With refinement, tiles holding K_q > tau equal the FP64 sweep bitwise."""
+    x, _, _ = config_inputs("C3", n_train=40)
+    a = gpu_gram(qk, x, 2, 64, "bf16x2", True)
+    b = gpu_gram(qk, x, 2, 64, "fp64", True)
+    # the diagonal tiles (16 x 16 blocks containing i == j) were recomputed
+    for t in range(3):
+        blk = slice(16 * t, min(16 * (t + 1), 40))
+        assert np.array_equal(a["ln"][blk, blk], b["ln"][blk, blk])
