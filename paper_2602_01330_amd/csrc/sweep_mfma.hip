@@ -161,6 +161,56 @@ __device__ inline f4 mma(const float* a, const float* b, f4 acc) {
   return acc;
 }
 
+// acc[x] += sum over NC chunks of a[x][c] * b[x][c] for four independent
+// products x, issued chunk-major so consecutive MFMAs never depend on each
+// other.
+template <int F, int NC>
+__device__ inline void mma4(const float (*a)[NC], const float (*b)[NC], f4* acc) {
+  if constexpr (F == kF32) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+        acc[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x][c], b[x][c], acc[x], 0, 0, 0);
+  } else if constexpr (F == kBF16x2) {
+#pragma unroll
+    for (int c0 = 0; c0 < NC; c0 += 2) {
+      bf8 va[4], vb[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          Split<kBF16x2> sa(a[x][c0 + h]), sb(b[x][c0 + h]);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            va[x][h * 4 + t] = sa.p[lhs_piece2(t)];
+            vb[x][h * 4 + t] = sb.p[rhs_piece2(t)];
+          }
+        }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+        acc[x] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va[x], vb[x], acc[x], 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      bf8 va[4], vb[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        Split<kBF16x3> sa(a[x][c]), sb(b[x][c]);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          va[x][t] = sa.p[lhs_piece3(t)];
+          vb[x][t] = sb.p[rhs_piece3(t)];
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+        acc[x] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va[x], vb[x], acc[x], 0, 0, 0);
+    }
+  }
+}
+
 __device__ inline void tile_coords(const QkTask& t, int64_t lt, int& ti, int& tj) {
   if (!t.symmetric) {
     ti = (int)(lt / t.tiles_c);
@@ -204,36 +254,46 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint8_t*
   const int rs = n >> 3, rcout = (n >> 2) & 1, rbp = n & 3;
   // step L, row p: A^s[a = g][a' = n&3] for s = 0, 1 (lanes n < 8)
   const int lcp = n >> 2, lap = n & 3;
-  int boff[4], aoff[4];
+  // byte offsets from the start of the site's sample array (never negative;
+  // below n * slot * 8 bytes, which fits 32 bits for any batch of interest)
+  unsigned boff[4], aoff[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int64_t j = (j0 + q) < t.nb ? (j0 + q) : (t.nb - 1);
     const int64_t i = (i0 + q) < t.na ? (i0 + q) : (t.na - 1);
-    boff[q] = (int)((j - j0) * slotT) + rs * TT + (g < T ? g : 0) * T + (rbp < T ? rbp : 0);
-    aoff[q] = (int)((i - i0) * slotT) + (g < T ? g : 0) * T + (lap < T ? lap : 0);
+    boff[q] = (unsigned)((j * slotT + rs * TT + (g < T ? g : 0) * T + (rbp < T ? rbp : 0)) * 8);
+    aoff[q] = (unsigned)((i * slotT + (g < T ? g : 0) * T + (lap < T ? lap : 0)) * 8);
   }
   // zero the elements outside the padded bond block (only when T < 4)
   const bool bin = kFullT || (g < T && rbp < T);
   const bool ain = kFullT || (g < T && lap < T);
-  const int64_t bstride = (int64_t)t.nb * slotT, astride = (int64_t)t.na * slotT;
-  const float2* bbase = tb + j0 * slotT;
-  const float2* abase = ta + i0 * slotT;
-  float2 bcur[4], acur[4][2];
-  auto fetch_b = [&](int k) {
-    const float2* p = bbase + (int64_t)k * bstride;
+  const int64_t bstride = (int64_t)t.nb * slotT * 8, astride = (int64_t)t.na * slotT * 8;
+  const char* bbase = reinterpret_cast<const char*>(tb);
+  const char* abase = reinterpret_cast<const char*>(ta);
+  const unsigned a1off = (unsigned)(TT * 8);
+
+  struct Ops {
+    float2 b[4];
+    float2 a[4][2];
+  };
+  // loads are unconditional (the site index is clamped), so they can land
+  // straight in the operand registers and stay in flight
+  auto fetch_b = [&](int k, Ops& o) {
+    const char* pb = bbase + (int64_t)k * bstride;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const float2 v = p[boff[q]];
-      bcur[q] = kFullT ? v : make_float2(bin ? v.x : 0.f, bin ? v.y : 0.f);
+      const float2 v = *reinterpret_cast<const float2*>(pb + boff[q]);
+      o.b[q] = kFullT ? v : make_float2(bin ? v.x : 0.f, bin ? v.y : 0.f);
     }
   };
-  auto fetch_a = [&](int k) {
-    const float2* p = abase + (int64_t)k * astride;
+  auto fetch_a = [&](int k, Ops& o) {
+    const char* pa = abase + (int64_t)k * astride;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const float2 v0 = p[aoff[q]], v1 = p[aoff[q] + TT];
-      acur[q][0] = kFullT ? v0 : make_float2(ain ? v0.x : 0.f, ain ? v0.y : 0.f);
-      acur[q][1] = kFullT ? v1 : make_float2(ain ? v1.x : 0.f, ain ? v1.y : 0.f);
+      const float2 v0 = *reinterpret_cast<const float2*>(pa + aoff[q]);
+      const float2 v1 = *reinterpret_cast<const float2*>(pa + aoff[q] + a1off);
+      o.a[q][0] = kFullT ? v0 : make_float2(ain ? v0.x : 0.f, ain ? v0.y : 0.f);
+      o.a[q][1] = kFullT ? v1 : make_float2(ain ? v1.x : 0.f, ain ? v1.y : 0.f);
     }
   };
 
@@ -246,59 +306,79 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint8_t*
   }
   int expo[4] = {0, 0, 0, 0};
 
-  fetch_b(0);
-  fetch_a(0);
-  for (int k = 0; k < nq; ++k) {
-    // ---- step R: G = E Bhat_j for the wave's four columns; the lane's
-    // G[(p=g, a=r)][(s, cout, b')] of pair (g, q) goes out as four b32 stores
+  // one site; each operand set is refetched for the next site right after
+  // its last use
+  Ops cur;
+  auto site_step = [&](int k) {
+    const bool more = k + 1 < nq;
+    const int kn = more ? k + 1 : k;
+    // ---- step R: G = E Bhat_j for the wave's four columns (four independent
+    // chains, issued chunk-major)
+    {
+      float bop[4][2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float2 bv = bcur[q];
-      float bop[2];
-      bop[0] = rcout ? bv.y : bv.x;
-      bop[1] = rcout ? bv.x : -bv.y;
-      f4 z = {0.f, 0.f, 0.f, 0.f};
-      const f4 dr = mma<F, 2>(eR[q], bop, z);
-      float* gw = &gb[g * kGp + q * kGq + rbp * 4 + (rs * 2 + rcout)];
+      for (int q = 0; q < 4; ++q) {
+        bop[q][0] = rcout ? cur.b[q].y : cur.b[q].x;
+        bop[q][1] = rcout ? cur.b[q].x : -cur.b[q].y;
+      }
+      fetch_b(kn, cur);  // in flight during step L
+      f4 acc[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) gw[r * kGa] = dr[r];
+      for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+      mma4<F, 2>(eR, bop, acc);
+      // lane holds G[(p=g, a=r)][(s, cout, b')] of pair (g, q)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float* gw = &gb[g * kGp + q * kGq + rbp * 4 + (rs * 2 + rcout)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gw[r * kGa] = acc[q][r];
+      }
     }
-    if (k + 1 < nq) fetch_b(k + 1);  // in flight during step L
     QK_LDS_FENCE();
     // ---- step L: E' = Ahat_i^dagger G for the wave's four rows, then the
     // exact power-of-two rescale every few sites (pair (p, q) lives on lanes
     // g in {0,1}, n>>2 == q: 4 lanes b' x 4 registers), then E' to LDS
     {
       const int q = n >> 2, bp = n & 3;  // output column (q, b')
-      const bool rescale = (k % kRescaleEvery) == kRescaleEvery - 1 || k + 1 == nq;
+      float bop[4][4], aop[4][4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const float2 a0 = acur[p][0], a1 = acur[p][1];
-        float aop[4];
-        aop[0] = lcp == 0 ? a0.x : -a0.y;  // s = 0, c_in = 0
-        aop[1] = lcp == 0 ? a0.y : a0.x;   // s = 0, c_in = 1
-        aop[2] = lcp == 0 ? a1.x : -a1.y;  // s = 1, c_in = 0
-        aop[3] = lcp == 0 ? a1.y : a1.x;   // s = 1, c_in = 1
-        if (n >= 8) aop[0] = aop[1] = aop[2] = aop[3] = 0.f;
         const f4 gv = *reinterpret_cast<const f4*>(&gb[p * kGp + q * kGq + g * kGa + bp * 4]);
-        float bop[4] = {gv[0], gv[1], gv[2], gv[3]};
-        f4 z = {0.f, 0.f, 0.f, 0.f};
-        f4 dl = mma<F, 4>(aop, bop, z);
-        if (rescale) {
-          float m = fmaxf(fmaxf(fabsf(dl[0]), fabsf(dl[1])), fmaxf(fabsf(dl[2]), fabsf(dl[3])));
+        bop[p][0] = gv[0];
+        bop[p][1] = gv[1];
+        bop[p][2] = gv[2];
+        bop[p][3] = gv[3];
+        const float2 a0 = cur.a[p][0], a1 = cur.a[p][1];
+        const bool z = n >= 8;
+        aop[p][0] = z ? 0.f : (lcp == 0 ? a0.x : -a0.y);  // s = 0, c_in = 0
+        aop[p][1] = z ? 0.f : (lcp == 0 ? a0.y : a0.x);   // s = 0, c_in = 1
+        aop[p][2] = z ? 0.f : (lcp == 0 ? a1.x : -a1.y);  // s = 1, c_in = 0
+        aop[p][3] = z ? 0.f : (lcp == 0 ? a1.y : a1.x);   // s = 1, c_in = 1
+      }
+      fetch_a(kn, cur);  // in flight until the next step L
+      f4 acc[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) acc[p] = f4{0.f, 0.f, 0.f, 0.f};
+      mma4<F, 4>(aop, bop, acc);
+      if ((k % kRescaleEvery) == kRescaleEvery - 1 || !more) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          float m = fmaxf(fmaxf(fabsf(acc[p][0]), fabsf(acc[p][1])),
+                          fmaxf(fabsf(acc[p][2]), fabsf(acc[p][3])));
           m = max_xor_1_2_16(m);
           const int e = m > 0.f ? frexp_exp(m) : 0;
           const float sc = pow2f(-e);
           expo[p] += e;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) dl[r] *= sc;
-        }
-        if (g < 2) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) eb[q * kEq + p * kEp + r * 8 + bp * 2 + g] = dl[r];
+          for (int r = 0; r < 4; ++r) acc[p][r] *= sc;
         }
       }
-      if (k + 1 < nq) fetch_a(k + 1);
+      if (g < 2) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) eb[q * kEq + p * kEp + r * 8 + bp * 2 + g] = acc[p][r];
+      }
     }
     QK_LDS_FENCE();
     {
@@ -311,7 +391,11 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint8_t*
       }
     }
     QK_LDS_FENCE();
-  }
+  };
+
+  fetch_b(0, cur);
+  fetch_a(0, cur);
+  for (int k = 0; k < nq; ++k) site_step(k);
 
   // ---- epilogue: pair (p, q) = (pi >> 2, pi & 3), four lanes per pair
   if (g == 0 && (n & 3) == 0) {
