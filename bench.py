@@ -100,6 +100,85 @@ def _oracle_chunk(args):
     return t1 - t0, t2 - t1
 
 
+def serving(args):
+    """Poisson request stream against resident support sets (5000 samples per
+    d in {16, 64, 256, 784}, L = 2, chi_max 64): 1..64 test rows per request,
+    d and w drawn per request; latency = rows on the host - submission."""
+    import threading
+    import queue
+    import numpy as np
+    import torch
+
+    import paper_2602_01330_amd.qk as qk
+    from synthdata import config_inputs, gen_requests
+    from synthdata.generators import C5_DIMS
+
+    dev = torch.device("cuda:0")
+    srv = qk.qk_server_create(budget_bytes=1 << 30, max_rows_per_iter=512, n_streams=2,
+                              prec="auto")
+    pools = {}
+    for d in C5_DIMS:
+        sup, pool, _ = config_inputs("C5", d=d, n_train=5000, n_test=1024)
+        qk.qk_server_load_support(srv, torch.as_tensor(sup, device=dev), 2, 64)
+        pools[d] = pool
+    log("serve: supports loaded")
+    warm, dur = args.serve_warmup, args.serve_seconds
+    reqs = gen_requests(55, args.serve_rate, warm + dur, dims=C5_DIMS)
+    rng = np.random.default_rng(56)
+    submitted = queue.Queue()
+    t_start = time.perf_counter()
+
+    def submitter():
+        for r in reqs:
+            delay = t_start + r["t"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            d, n = r["d"], r["n_rows"]
+            off = int(rng.integers(0, pools[d].shape[0] - n))
+            rid = qk.qk_server_submit(srv, pools[d][off:off + n], r["w"])
+            submitted.put((rid, r))
+        submitted.put(None)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    out = np.empty((64, 5000))
+    lat, measured_entries, t_first, t_last, sub = [], 0, None, 0.0, []
+    while True:
+        item = submitted.get()
+        if item is None:
+            break
+        rid, r = item
+        st = qk.qk_server_wait(srv, rid, -1)
+        ts, ta, td = qk.qk_server_request_times(srv, rid)
+        qk.qk_server_poll(srv, rid, out)
+        if st != qk.QK_REQ_DONE:
+            raise RuntimeError(f"request {rid} ended in state {st}: {qk.qk_last_error()}")
+        if r["t"] >= warm:
+            sub.append(ts)
+            lat.append(td - ts)
+            measured_entries += r["n_rows"] * 5000
+            t_first = ts if t_first is None else min(t_first, ts)
+            t_last = max(t_last, td)
+    th.join()
+    stats = qk.qk_server_stats(srv)
+    srv.close()
+    lat = np.array(lat) * 1e3
+    meas = [r for r in reqs if r["t"] >= warm]
+    offered = sum(r["n_rows"] for r in meas) * 5000 / dur
+    log(f"serve: {len(lat)} requests, p50 {np.percentile(lat, 50):.1f} ms, "
+        f"p99 {np.percentile(lat, 99):.1f} ms")
+    return {"workload": "Poisson requests (1..64 rows, d in {16,64,256,784}, w ~ U[0,1]) "
+                        "against 5000 resident support MPS per d, L=2, chi_max=64",
+            "rate_per_s": args.serve_rate, "measured_s": dur, "warmup_s": warm,
+            "n_requests": int(len(lat)), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "entries_per_s": measured_entries / (t_last - t_first),
+            "offered_entries_per_s": offered,
+            "submit_span_s": float(max(sub) - min(sub)) if sub else 0.0,
+            "n_iterations": stats["n_iters"],
+            "peak_budget_mb": stats["peak_budget_bytes"] / 2**20}
+
+
 def run(args):
     import numpy as np
     import torch
@@ -203,6 +282,9 @@ def run(args):
         line["plain_fp64"] = {"value": pairs / (p["ms_per_step"] / 1e3),
                               "ms_per_step": p["ms_per_step"], "sweep_ms": p["sweep_ms"]}
         line["speedup_vs_plain_fp64"] = value / line["plain_fp64"]["value"]
+    if args.serve_seconds > 0:
+        log("bench: serving run")
+        line["serving"] = serving(args)
     if not args.no_cpu:
         log("bench: timing the CPU oracle sample")
         line["cpu_baseline"] = cpu_baseline(x_tr, args.cpu_seconds)
@@ -219,6 +301,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="measured seconds of the serving run (0 skips it)")
+    ap.add_argument("--serve-warmup", type=float, default=3.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="requests per second")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the Gram tiles shard across GPUs without "

@@ -148,7 +148,9 @@ QK_API qk_status qk_mps_release(qk_mps_batch* b);
  * the epilogue of the overlap sweep. x_rows_dev / x_cols_dev are the FP64
  * features the batches were built from (row-major, leading dims ld_xr,
  * ld_xc, d = n_qubits columns). kc_dev and k_dev are FP64 outputs laid out
- * like kq (either may be NULL to skip it).
+ * like kq (either may be NULL to skip it). w_rows_dev (may be NULL) holds one
+ * mixing weight per row sample and then overrides w: rows of different
+ * requests batched into one launch keep their own weights.
  */
 typedef struct {
   const double* x_rows_dev;
@@ -157,6 +159,7 @@ typedef struct {
   int64_t ld_xc;
   double gamma;
   double w;
+  const double* w_rows_dev;
   double* kc_dev;
   int64_t ld_kc;
   double* k_dev;
@@ -232,8 +235,10 @@ QK_API qk_status qk_dual_mix(const double* kq_dev, int64_t ld_kq, const double* 
  * Reduced-precision forms (QK_PREC_FP32, _FP32_MFMA, _BF16X2, _BF16X3) carry
  * a relative error of ~1e-5 (FP32-class) or ~2e-4 (BF16X2) in K_q after
  * hundreds of sites, which exceeds 1e-5 absolute only where K_q is large.
- * After such a sweep every 16 x 16 pair tile holding a K_q above tau is
- * recomputed by the FP64 sweep (this needs QK_STORE_FP64 in the batches).
+ * After such a sweep every pair whose K_q exceeds tau is recomputed by the
+ * FP64 sweep (this needs QK_STORE_FP64 in the batches). The decision depends
+ * only on that pair's own value, so a pair's result does not depend on which
+ * other samples share its launch.
  * Defaults: tau = 1e-2 (FP32-class forms), 1e-3 (BF16X2). tau <= 0
  * disables refinement for that form. Process-wide setting.
  */
@@ -246,6 +251,85 @@ QK_API qk_status qk_resolve_precision(const qk_mps_batch* rows,
 
 QK_API const char* qk_status_string(qk_status s);
 QK_API const char* qk_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Serving: kernel rows of test requests against resident support sets.
+ *
+ * The blockwise Gram construction of Section II-D, run as a service: the
+ * support samples of each feature dimension d are encoded once and stay in
+ * device memory; each request carries 1..n test samples and a mixing weight
+ * w and returns its rows of K = w K_q + (1 - w) K_c (Eqs. (3), (7), (11);
+ * gamma = gamma_scale / d) against the support set of its d.
+ *
+ * Continuous batching: a worker thread admits queued requests in arrival
+ * order while the HBM budget allows (per-request state: FP64 build workspace,
+ * packed MPS, feature and output rows) and the row cap of an iteration is not
+ * exceeded. One iteration encodes the admitted rows (one build per d) and
+ * runs ONE persistent sweep launch over all of them (one task per d, per-row
+ * w), then copies each request's rows to pinned host memory. Up to n_streams
+ * iterations are in flight, so requests arriving while others run are
+ * admitted as soon as a stream slot and budget free up. A pair's result does
+ * not depend on the other rows of its iteration (per-pair arithmetic and
+ * per-pair refinement), so a request's rows are identical alone and in a mix.
+ * --------------------------------------------------------------------------- */
+typedef struct qk_server qk_server;
+
+typedef struct {
+  int64_t budget_bytes;       /* device bytes for per-request state; 0 -> 1 GiB     */
+  int32_t max_rows_per_iter;  /* rows admitted into one iteration; 0 -> 512        */
+  int32_t n_streams;          /* iterations in flight, 1..4; 0 -> 2                 */
+  qk_precision prec;          /* sweep form (QK_PREC_AUTO recommended)              */
+  double gamma_scale;         /* gamma = gamma_scale / d; 0 -> 1                    */
+} qk_server_config;
+
+enum { QK_REQ_QUEUED = 0, QK_REQ_RUNNING = 1, QK_REQ_DONE = 2, QK_REQ_FAILED = 3,
+       QK_REQ_CANCELLED = 4 };
+
+/* Starts the worker thread on the current device. Errors: INVALID_ARG, HIP. */
+QK_API qk_status qk_server_create(const qk_server_config* cfg, qk_server** out);
+
+/* Encodes a support set for circuit c (keyed by c->n_qubits; one per d) and
+ * keeps its MPS and a copy of its FP64 features (n x d, device rows x_dev,
+ * leading dim ld_x) until qk_server_destroy. Synchronous. Support memory is
+ * outside the budget. Errors: INVALID_ARG (duplicate d, bad desc), and those
+ * of qk_mps_build. */
+QK_API qk_status qk_server_load_support(qk_server* s, const qk_circuit_desc* c,
+                                        const double* x_dev, int64_t n, int64_t ld_x);
+
+/* Queues a request: n_rows x d FP64 features on the host (copied before the
+ * call returns), mixing weight w in [0, 1]. Never waits for the GPU. Writes
+ * the request id. Errors: NOT_FOUND (no support set for d), INVALID_ARG
+ * (n_rows < 1, w outside [0, 1], non-finite feature). */
+QK_API qk_status qk_server_submit(qk_server* s, const double* x_host, int64_t n_rows,
+                                  int32_t d, double w, int64_t* id);
+
+/* Writes the request state (QK_REQ_*). When DONE and rows_host is not NULL,
+ * copies its n_rows x n_support FP64 rows (leading dim ld_rows >= n_support)
+ * and releases them; a later poll of that id returns NOT_FOUND. FAILED
+ * carries the reason in qk_last_error(). */
+QK_API qk_status qk_server_poll(qk_server* s, int64_t id, double* rows_host,
+                                int64_t ld_rows, int32_t* state);
+
+/* Blocks until the request leaves QUEUED/RUNNING or timeout_ms passes
+ * (< 0: no limit); writes the state. */
+QK_API qk_status qk_server_wait(qk_server* s, int64_t id, int32_t timeout_ms, int32_t* state);
+
+/* Cancels a queued or running request (running work completes on the device
+ * and is discarded). Errors: NOT_FOUND. */
+QK_API qk_status qk_server_cancel(qk_server* s, int64_t id);
+
+/* Times of a request in seconds since qk_server_create: submitted, admitted
+ * into an iteration, rows on the host (-1 if not reached). */
+QK_API qk_status qk_server_request_times(qk_server* s, int64_t id, double* t_submit,
+                                         double* t_admit, double* t_done);
+
+/* Counters: requests done, iterations launched, peak budget bytes in use,
+ * kernel entries (row x support pairs) delivered. Any pointer may be NULL. */
+QK_API qk_status qk_server_stats(qk_server* s, int64_t* n_done, int64_t* n_iters,
+                                 int64_t* peak_budget_bytes, int64_t* entries_done);
+
+/* Stops admitting, drains in-flight iterations, frees everything. */
+QK_API qk_status qk_server_destroy(qk_server* s);
 
 #ifdef __cplusplus
 }

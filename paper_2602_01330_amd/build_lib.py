@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libqk.so")
 
-SOURCES = ["qk_api.cpp", "tune.cpp", "build.hip", "sweep_valu.hip",
+SOURCES = ["qk_api.cpp", "tune.cpp", "server.cpp", "build.hip", "sweep_valu.hip",
            "sweep_mfma.hip", "classical.hip"]
 
 FLAGS = [

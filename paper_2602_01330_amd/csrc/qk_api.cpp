@@ -23,6 +23,17 @@ qk_status fail(qk_status s, const std::string& msg) {
   return s;
 }
 
+void free_batch_memory(qk_mps_batch* b, hipStream_t s) {
+  if (b->t64) (void)hipFreeAsync(b->t64, s);
+  if (b->t32) (void)hipFreeAsync(b->t32, s);
+  if (b->chi) (void)hipFreeAsync(b->chi, s);
+  if (b->status) (void)hipFreeAsync(b->status, s);
+  b->t64 = nullptr;
+  b->t32 = nullptr;
+  b->chi = nullptr;
+  b->status = nullptr;
+}
+
 qk_status hip_fail(hipError_t e, const char* what) {
   return fail(QK_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -86,22 +97,20 @@ qk_status alloc_batch(const qk_circuit_desc* c, int64_t n, int T, uint32_t store
   b->stream = s;
   const int64_t elems = (int64_t)c->n_qubits * n * 2 * T * T;
   auto cleanup = [&](qk_status st, const char* what) {
-    (void)hipFree(b->t64);
-    (void)hipFree(b->t32);
-    (void)hipFree(b->chi);
-    (void)hipFree(b->status);
+    free_batch_memory(b, s);
     delete b;
     return fail(st, what);
   };
-  // the FP64 form is the build's workspace, so it is always allocated
-  if (hipMalloc(&b->t64, std::max<int64_t>(elems, 1) * sizeof(double2)) != hipSuccess)
+  // stream-ordered allocations: no device-wide synchronisation on alloc/free.
+  // The FP64 form is the build's workspace, so it is always allocated.
+  if (hipMallocAsync((void**)&b->t64, std::max<int64_t>(elems, 1) * sizeof(double2), s) != hipSuccess)
     return cleanup(QK_ERR_OUT_OF_MEMORY, "device allocation of FP64 site tensors failed");
   if ((store & QK_STORE_FP32) &&
-      hipMalloc(&b->t32, std::max<int64_t>(elems, 1) * sizeof(float2)) != hipSuccess)
+      hipMallocAsync((void**)&b->t32, std::max<int64_t>(elems, 1) * sizeof(float2), s) != hipSuccess)
     return cleanup(QK_ERR_OUT_OF_MEMORY, "device allocation of FP32 site tensors failed");
-  if (hipMalloc(&b->chi, std::max<int64_t>(n * (c->n_qubits + 1), 1) * sizeof(int32_t)) != hipSuccess)
+  if (hipMallocAsync((void**)&b->chi, std::max<int64_t>(n * (c->n_qubits + 1), 1) * sizeof(int32_t), s) != hipSuccess)
     return cleanup(QK_ERR_OUT_OF_MEMORY, "device allocation of the bond table failed");
-  if (hipMalloc(&b->status, 2 * sizeof(int32_t)) != hipSuccess)
+  if (hipMallocAsync((void**)&b->status, 2 * sizeof(int32_t), s) != hipSuccess)
     return cleanup(QK_ERR_OUT_OF_MEMORY, "device allocation of the status word failed");
   if (hipMemsetAsync(b->status, 0, 2 * sizeof(int32_t), s) != hipSuccess)
     return cleanup(QK_ERR_HIP, "status reset failed");
@@ -120,8 +129,7 @@ qk_status finish_batch(qk_mps_batch* b, uint32_t store) {
   if (b->t32) QK_HIP(qk_launch_pack32(b->t64, b->t32, elems, b->stream), "pack to FP32");
   QK_HIP(hipEventRecord(b->ready, b->stream), "event record");
   if (!(store & QK_STORE_FP64)) {
-    QK_HIP(hipEventSynchronize(b->ready), "build synchronisation");
-    (void)hipFree(b->t64);
+    QK_HIP(hipFreeAsync(b->t64, b->stream), "free of the FP64 workspace");
     b->t64 = nullptr;
     b->bytes -= elems * (int64_t)sizeof(double2);
   }
@@ -184,6 +192,7 @@ qk_status fill_task(QkTask& t, const qk_mps_batch* rows, const qk_mps_batch* col
     t.ld_xc = fuse->ld_xc;
     t.gamma = fuse->gamma;
     t.w = fuse->w;
+    t.w_rows = fuse->w_rows_dev;
     t.kc = fuse->kc_dev;
     t.ld_kc = fuse->ld_kc;
     t.k = fuse->k_dev;
@@ -233,8 +242,10 @@ qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, h
     return QK_OK;
   }
   const bool refine = tau > 0.0;
-  uint8_t* flags = nullptr;
-  if (refine) QK_HIP(hipMallocAsync((void**)&flags, acc, s), "flag allocation");
+  uint32_t* flags = nullptr;
+  if (refine)
+    QK_HIP(hipMallocAsync((void**)&flags, acc * kQkMaskWords * sizeof(uint32_t), s),
+           "refinement mask allocation");
   const double ln_tau = refine ? std::log(tau) : 0.0;
   hipError_t e;
   if (prec == QK_PREC_FP32) {
@@ -262,6 +273,15 @@ int tile_for(qk_precision p) {
 }
 
 }  // namespace
+
+qk_status qk_fail(qk_status s, const std::string& msg) { return fail(s, msg); }
+
+void qk_mps_release_nosync(qk_mps_batch* b, hipStream_t s) {
+  if (!b) return;
+  free_batch_memory(b, s);
+  if (b->ready) (void)hipEventDestroy(b->ready);
+  delete b;
+}
 
 extern "C" {
 
@@ -346,7 +366,8 @@ qk_status qk_mps_import(const qk_circuit_desc* c, int64_t n_samples,
   b->chi_ws = chi_pad;
   const int64_t elems = (int64_t)c->n_qubits * n_samples * 2 * chi_pad * chi_pad;
   const int32_t stat[2] = {0, mx};
-  hipError_t e = hipMemcpy(b->t64, tensors_host, elems * sizeof(double2), hipMemcpyHostToDevice);
+  hipError_t e = hipStreamSynchronize(s);  // the stream-ordered allocations exist
+  if (e == hipSuccess) e = hipMemcpy(b->t64, tensors_host, elems * sizeof(double2), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(b->chi, chi_host, n_samples * (c->n_qubits + 1) * sizeof(int32_t),
                   hipMemcpyHostToDevice);
@@ -399,10 +420,8 @@ qk_status qk_mps_release(qk_mps_batch* b) {
   if (!b) return QK_OK;
   // sweeps on any stream may still read the batch: drain the device first
   (void)hipDeviceSynchronize();
-  (void)hipFree(b->t64);
-  (void)hipFree(b->t32);
-  (void)hipFree(b->chi);
-  (void)hipFree(b->status);
+  free_batch_memory(b, nullptr);
+  (void)hipStreamSynchronize(nullptr);
   if (b->ready) (void)hipEventDestroy(b->ready);
   delete b;
   return QK_OK;

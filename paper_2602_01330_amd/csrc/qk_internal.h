@@ -30,6 +30,13 @@ struct qk_mps_batch {
   int64_t bytes = 0;
 };
 
+// Shared host helpers (qk_api.cpp).
+#include <string>
+qk_status qk_fail(qk_status s, const std::string& msg);
+// Frees a batch without draining the device; the caller guarantees that no
+// enqueued work still reads it. Memory returns to the pool in stream order.
+void qk_mps_release_nosync(qk_mps_batch* b, hipStream_t s);
+
 // Kernel launchers (build.hip).
 hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
                            int n_layers, int chi_max, int entangle,
@@ -55,6 +62,7 @@ struct QkTask {
   const double* xr; int64_t ld_xr;
   const double* xc; int64_t ld_xc;
   double gamma, w;
+  const double* w_rows;  // per-row mixing weight (overrides w) or null
   double* kc; int64_t ld_kc;
   double* k; int64_t ld_k;
   int32_t fuse;
@@ -69,12 +77,14 @@ struct QkTaskTable {
 };
 
 // Sweep launchers (sweep_valu.hip / sweep_mfma.hip). Every sweep kernel uses
-// 16 x 16 pair tiles with the same tile numbering, so a flag per tile written
-// by one pass (1 = the tile holds a K_q above the refinement threshold) can
-// select the tiles of another. flags_out may be null; flags_in null = all.
-hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, const uint8_t* flags_in,
+// 16 x 16 pair tiles with the same tile numbering. A reduced-precision pass
+// writes, per tile, a 256-bit mask (8 words) of the pairs whose K_q exceeds
+// the refinement threshold (bit (i % 16) * 16 + (j % 16)); the FP64 pass then
+// visits only tiles with a set bit and writes only those pairs.
+constexpr int kQkMaskWords = 8;
+hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, const uint32_t* mask_in,
                                 hipStream_t s);
-hipError_t qk_launch_sweep_fp32(const QkTaskTable& tt, int grid, uint8_t* flags_out,
+hipError_t qk_launch_sweep_fp32(const QkTaskTable& tt, int grid, uint32_t* mask_out,
                                 double ln_tau, hipStream_t s);
 int qk_sweep_valu_tile();
 

@@ -31,9 +31,10 @@
 // split is folded into the contraction index, so one MFMA K of 32 covers four
 // (BF16x2) or eight (BF16x3) products of each FP32 term.
 //
-// Reduced-precision forms flag every tile holding a K_q above a threshold;
-// flagged tiles are recomputed by the FP64 sweep (qk_launch_sweep_fp64 with
-// the flags) so that entries near 1 carry FP64 accuracy.
+// Reduced-precision forms mark every pair whose K_q exceeds a threshold;
+// the FP64 sweep (qk_launch_sweep_fp64 with the masks) recomputes the tiles
+// holding marked pairs and writes exactly those pairs, so that entries near
+// 1 carry FP64 accuracy.
 #include <hip/hip_runtime.h>
 
 #include "qk_tune.h"
@@ -63,7 +64,7 @@ struct MfmaSmem {
   float g[kWaves][4 * kGp];
   float e[kWaves][4 * kEq];
   int ex[kWaves][16];
-  int flag;
+  unsigned mask[kQkMaskWords];
 };
 
 // max over lanes l ^ 1 and l ^ 2 (DPP quad permutations) and l ^ 16 (swizzle)
@@ -232,7 +233,7 @@ __device__ inline void tile_coords(const QkTask& t, int64_t lt, int& ti, int& tj
 #define QK_LDS_FENCE() __asm__ volatile("" ::: "memory")
 
 template <int F, bool kFullT>
-__device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint8_t* flags,
+__device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t* mask,
                          int64_t tile_id, double ln_tau) {
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index: scalar
@@ -402,7 +403,7 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint8_t*
 #pragma unroll
     for (int p = 0; p < 4; ++p) sm.ex[w][p * 4 + (n >> 2)] = expo[p];
   }
-  if (tid == 0) sm.flag = 0;
+  if (tid < kQkMaskWords) sm.mask[tid] = 0;
   __syncthreads();
   const int pi = lane & 15, part = lane >> 4;
   const int p = pi >> 2, q = pi & 3;
@@ -435,17 +436,21 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint8_t*
     put(t.lnkq, t.ld_ln, lnk);
     if (t.fuse) {
       const double kc = exp(-t.gamma * d2);
+      const double w = t.w_rows ? t.w_rows[i] : t.w;
       put(t.kc, t.ld_kc, kc);
-      put(t.k, t.ld_k, t.w * kq + (1.0 - t.w) * kc);
+      put(t.k, t.ld_k, w * kq + (1.0 - w) * kc);
     }
-    if (flags && lnk > ln_tau) atomicOr(&sm.flag, 1);
+    if (mask && lnk > ln_tau) {
+      const int bit = (int)(i - (int64_t)ti * kTile) * kTile + (int)(j - (int64_t)tj * kTile);
+      atomicOr(&sm.mask[bit >> 5], 1u << (bit & 31));
+    }
   }
   __syncthreads();
-  if (flags && tid == 0) flags[tile_id] = (uint8_t)sm.flag;
+  if (mask && tid < kQkMaskWords) mask[tile_id * kQkMaskWords + tid] = sm.mask[tid];
 }
 
 template <int F>
-__global__ __launch_bounds__(kThreads) void sweep_mfma_kernel(QkTaskTable tt, uint8_t* flags,
+__global__ __launch_bounds__(kThreads) void sweep_mfma_kernel(QkTaskTable tt, uint32_t* flags,
                                                               double ln_tau) {
   __shared__ MfmaSmem sm;
   for (int64_t q = blockIdx.x; q < tt.total_tiles; q += gridDim.x) {
@@ -470,7 +475,7 @@ bool qk_mfma_supports(qk_precision p, int T) {
 int qk_mfma_tile(qk_precision) { return kTile; }
 
 hipError_t qk_launch_sweep_mfma(const QkTaskTable& tt, qk_precision p, int cus,
-                                uint8_t* flags, double ln_tau, hipStream_t s) {
+                                uint32_t* flags, double ln_tau, hipStream_t s) {
   if (tt.total_tiles == 0) return hipSuccess;
   const int grid = (int)(tt.total_tiles < (int64_t)cus ? tt.total_tiles : cus);
   switch (p) {

@@ -78,7 +78,7 @@ struct SweepSmem {
 
 template <typename R, int T>
 __device__ void run_tile(const QkTask& t, int ti, int tj, SweepSmem<R, T>& sm,
-                         int* tile_flag, double ln_tau) {
+                         unsigned* mask_out, const uint32_t* mask_in, double ln_tau) {
   using C = typename Cx<R>::V;
   constexpr int kSlot = SweepSmem<R, T>::kSlot;
   constexpr int kStride = SweepSmem<R, T>::kStride;
@@ -210,11 +210,14 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, SweepSmem<R, T>& sm,
   // epilogue: ln K_q, K_q, optional RBF and mix; FP64
   const bool valid = i < t.na && j < t.nb && (!t.symmetric || j >= i);
   if (!valid) return;
+  const int bit = r * kTile + c;
+  // refinement pass: write only the pairs the reduced pass marked
+  if (mask_in && !((mask_in[bit >> 5] >> (bit & 31)) & 1u)) return;
   const double re = (double)er[0][0], im = (double)ei[0][0];
   const double mag2 = re * re + im * im;
   const double lnk = mag2 > 0.0 ? log(mag2) + 2.0 * (double)expo * 0.69314718055994530942
                                 : -INFINITY;
-  if (tile_flag && lnk > ln_tau) atomicOr(tile_flag, 1);
+  if (mask_out && lnk > ln_tau) atomicOr(&mask_out[bit >> 5], 1u << (bit & 31));
   const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
   auto put = [&](double* p, int64_t ld, double v) {
     if (!p) return;
@@ -232,8 +235,9 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, SweepSmem<R, T>& sm,
       d2 += df * df;
     }
     const double kc = exp(-t.gamma * d2);
+    const double w = t.w_rows ? t.w_rows[i] : t.w;
     put(t.kc, t.ld_kc, kc);
-    put(t.k, t.ld_k, t.w * kq + (1.0 - t.w) * kc);
+    put(t.k, t.ld_k, w * kq + (1.0 - w) * kc);
   }
 }
 
@@ -251,16 +255,21 @@ struct MaxT<float> {
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void sweep_valu_kernel(QkTaskTable tt,
-                                                              const uint8_t* flags_in,
-                                                              uint8_t* flags_out,
+                                                              const uint32_t* mask_in,
+                                                              uint32_t* mask_out,
                                                               double ln_tau) {
   __shared__ SweepSmem<R, MaxT<R>::v> sm4;
-  __shared__ int tile_flag;
+  __shared__ unsigned tile_mask[kQkMaskWords];
   for (int64_t q = blockIdx.x; q < tt.total_tiles; q += gridDim.x) {
-    if (flags_in && flags_in[q] == 0) continue;  // uniform per workgroup
-    if (threadIdx.x == 0) tile_flag = 0;
+    const uint32_t* mi = mask_in ? mask_in + q * kQkMaskWords : nullptr;
+    if (mi) {  // uniform per workgroup: skip tiles without a marked pair
+      unsigned any = 0;
+      for (int wd = 0; wd < kQkMaskWords; ++wd) any |= mi[wd];
+      if (!any) continue;
+    }
+    if (threadIdx.x < kQkMaskWords) tile_mask[threadIdx.x] = 0;
     __syncthreads();
-    int* tf = flags_out ? &tile_flag : nullptr;
+    unsigned* tf = mask_out ? tile_mask : nullptr;
     int ti_task = 0;
     while (ti_task + 1 < tt.n_tasks && tt.t[ti_task + 1].tile_begin <= q) ++ti_task;
     const QkTask& t = tt.t[ti_task];
@@ -268,17 +277,18 @@ __global__ __launch_bounds__(kThreads) void sweep_valu_kernel(QkTaskTable tt,
     tile_coords(t, q - t.tile_begin, ti, tj);
     switch (t.T) {
       case 1:
-        run_tile<R, 1>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 1>*>(&sm4), tf, ln_tau);
+        run_tile<R, 1>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 1>*>(&sm4), tf, mi, ln_tau);
         break;
       case 2:
-        run_tile<R, 2>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 2>*>(&sm4), tf, ln_tau);
+        run_tile<R, 2>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 2>*>(&sm4), tf, mi, ln_tau);
         break;
       default:
-        run_tile<R, 4>(t, ti, tj, sm4, tf, ln_tau);
+        run_tile<R, 4>(t, ti, tj, sm4, tf, mi, ln_tau);
         break;
     }
     __syncthreads();
-    if (flags_out && threadIdx.x == 0) flags_out[q] = (uint8_t)tile_flag;
+    if (mask_out && threadIdx.x < kQkMaskWords)
+      mask_out[q * kQkMaskWords + threadIdx.x] = tile_mask[threadIdx.x];
   }
 }
 
@@ -286,18 +296,18 @@ __global__ __launch_bounds__(kThreads) void sweep_valu_kernel(QkTaskTable tt,
 
 int qk_sweep_valu_tile() { return kTile; }
 
-hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, const uint8_t* flags_in,
+hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, const uint32_t* mask_in,
                                 hipStream_t s) {
   if (tt.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(sweep_valu_kernel<double>, dim3(grid), dim3(kThreads), 0, s, tt, flags_in,
-                     (uint8_t*)nullptr, 0.0);
+  hipLaunchKernelGGL(sweep_valu_kernel<double>, dim3(grid), dim3(kThreads), 0, s, tt, mask_in,
+                     (uint32_t*)nullptr, 0.0);
   return hipGetLastError();
 }
 
-hipError_t qk_launch_sweep_fp32(const QkTaskTable& tt, int grid, uint8_t* flags_out,
+hipError_t qk_launch_sweep_fp32(const QkTaskTable& tt, int grid, uint32_t* mask_out,
                                 double ln_tau, hipStream_t s) {
   if (tt.total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(sweep_valu_kernel<float>, dim3(grid), dim3(kThreads), 0, s, tt,
-                     (const uint8_t*)nullptr, flags_out, ln_tau);
+                     (const uint32_t*)nullptr, mask_out, ln_tau);
   return hipGetLastError();
 }

@@ -50,7 +50,7 @@ class qk_circuit_desc(C.Structure):
 class qk_fuse_desc(C.Structure):
     _fields_ = [("x_rows_dev", C.c_void_p), ("ld_xr", C.c_int64),
                 ("x_cols_dev", C.c_void_p), ("ld_xc", C.c_int64),
-                ("gamma", C.c_double), ("w", C.c_double),
+                ("gamma", C.c_double), ("w", C.c_double), ("w_rows_dev", C.c_void_p),
                 ("kc_dev", C.c_void_p), ("ld_kc", C.c_int64),
                 ("k_dev", C.c_void_p), ("ld_k", C.c_int64)]
 
@@ -90,7 +90,33 @@ for _f in ("qk_mps_build", "qk_mps_import", "qk_mps_info", "qk_mps_chi", "qk_mps
            "qk_resolve_precision", "qk_set_refine_threshold"):
     getattr(_lib, _f).restype = C.c_int
 
-EXPORTED = ["qk_mps_build", "qk_mps_import", "qk_mps_info", "qk_mps_chi", "qk_mps_release",
+class qk_server_config(C.Structure):
+    _fields_ = [("budget_bytes", C.c_int64), ("max_rows_per_iter", C.c_int32),
+                ("n_streams", C.c_int32), ("prec", C.c_int), ("gamma_scale", C.c_double)]
+
+
+_I64P = C.POINTER(C.c_int64)
+_lib.qk_server_create.argtypes = [C.POINTER(qk_server_config), C.POINTER(_P)]
+_lib.qk_server_load_support.argtypes = [_P, C.POINTER(qk_circuit_desc), _P, C.c_int64, C.c_int64]
+_lib.qk_server_submit.argtypes = [_P, _P, C.c_int64, C.c_int32, C.c_double, _I64P]
+_lib.qk_server_poll.argtypes = [_P, C.c_int64, _P, C.c_int64, C.POINTER(C.c_int32)]
+_lib.qk_server_wait.argtypes = [_P, C.c_int64, C.c_int32, C.POINTER(C.c_int32)]
+_lib.qk_server_cancel.argtypes = [_P, C.c_int64]
+_lib.qk_server_request_times.argtypes = [_P, C.c_int64, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]
+_lib.qk_server_stats.argtypes = [_P, _I64P, _I64P, _I64P, _I64P]
+_lib.qk_server_destroy.argtypes = [_P]
+for _f in ("qk_server_create", "qk_server_load_support", "qk_server_submit", "qk_server_poll",
+           "qk_server_wait", "qk_server_cancel", "qk_server_request_times", "qk_server_stats",
+           "qk_server_destroy"):
+    getattr(_lib, _f).restype = C.c_int
+
+QK_REQ_QUEUED, QK_REQ_RUNNING, QK_REQ_DONE, QK_REQ_FAILED, QK_REQ_CANCELLED = 0, 1, 2, 3, 4
+
+EXPORTED = ["qk_server_create", "qk_server_load_support", "qk_server_submit",
+            "qk_server_poll", "qk_server_wait", "qk_server_cancel", "qk_server_request_times",
+            "qk_server_stats", "qk_server_destroy",
+            "qk_mps_build", "qk_mps_import", "qk_mps_info", "qk_mps_chi", "qk_mps_release",
             "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
             "qk_resolve_precision", "qk_set_refine_threshold", "qk_status_string",
             "qk_last_error"]
@@ -209,7 +235,12 @@ def _fuse(fuse):
     f.x_rows_dev, f.ld_xr = _mat(fuse["x_rows"], "x_rows")
     f.x_cols_dev, f.ld_xc = _mat(fuse["x_cols"], "x_cols")
     f.gamma = float(fuse["gamma"])
-    f.w = float(fuse["w"])
+    f.w = float(fuse.get("w", 0.5))
+    wr = fuse.get("w_rows")
+    if wr is not None:
+        if not (wr.is_cuda and wr.dtype == torch.float64 and wr.dim() == 1 and wr.is_contiguous()):
+            raise TypeError("w_rows must be a contiguous float64 CUDA vector")
+        f.w_rows_dev = wr.data_ptr()
     f.kc_dev, f.ld_kc = _opt(fuse.get("kc"), "kc")
     f.k_dev, f.ld_k = _opt(fuse.get("k"), "k")
     return f
@@ -284,3 +315,96 @@ def qk_status_string(s: int) -> str:
 
 def qk_last_error() -> str:
     return _lib.qk_last_error().decode()
+
+
+# ---- serving ------------------------------------------------------------------
+
+class Server:
+    """Owns a qk_server handle (continuous batching against resident supports)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        self.n_support = {}
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("server destroyed")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            _lib.qk_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def qk_server_create(budget_bytes=0, max_rows_per_iter=0, n_streams=0, prec="auto",
+                     gamma_scale=1.0) -> Server:
+    cfg = qk_server_config(int(budget_bytes), int(max_rows_per_iter), int(n_streams),
+                           PREC[prec] if isinstance(prec, str) else int(prec), float(gamma_scale))
+    h = C.c_void_p()
+    _check(_lib.qk_server_create(C.byref(cfg), C.byref(h)))
+    return Server(h)
+
+
+def qk_server_load_support(server: Server, x, n_layers, chi_max, cutoff=1e-10, entangle=True):
+    xp, ld = _mat(x, "x")
+    desc = circuit(x.shape[1], n_layers, chi_max, cutoff, entangle)
+    _check(_lib.qk_server_load_support(server.handle, C.byref(desc), xp, x.shape[0], ld))
+    server.n_support[x.shape[1]] = x.shape[0]
+
+
+def qk_server_submit(server: Server, x_rows: np.ndarray, w: float) -> int:
+    x = np.ascontiguousarray(x_rows, dtype=np.float64)
+    if x.ndim != 2:
+        raise ValueError("x_rows must be 2-D")
+    rid = C.c_int64()
+    _check(_lib.qk_server_submit(server.handle, x.ctypes.data_as(C.c_void_p), x.shape[0],
+                                 x.shape[1], float(w), C.byref(rid)))
+    return rid.value
+
+
+def qk_server_poll(server: Server, rid: int, out: np.ndarray | None = None):
+    """Returns (state, rows or None); rows are fetched (and released) when DONE."""
+    st = C.c_int32()
+    if out is not None:
+        if out.dtype != np.float64 or not out.flags.c_contiguous:
+            raise TypeError("out must be a C-contiguous float64 array")
+        _check(_lib.qk_server_poll(server.handle, rid, out.ctypes.data_as(C.c_void_p),
+                                   out.shape[1], C.byref(st)))
+        return st.value, (out if st.value == QK_REQ_DONE else None)
+    _check(_lib.qk_server_poll(server.handle, rid, None, 0, C.byref(st)))
+    return st.value, None
+
+
+def qk_server_wait(server: Server, rid: int, timeout_ms: int = -1) -> int:
+    st = C.c_int32()
+    _check(_lib.qk_server_wait(server.handle, rid, int(timeout_ms), C.byref(st)))
+    return st.value
+
+
+def qk_server_cancel(server: Server, rid: int):
+    _check(_lib.qk_server_cancel(server.handle, rid))
+
+
+def qk_server_request_times(server: Server, rid: int):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    _check(_lib.qk_server_request_times(server.handle, rid, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def qk_server_stats(server: Server) -> dict:
+    v = [C.c_int64() for _ in range(4)]
+    _check(_lib.qk_server_stats(server.handle, *[C.byref(x) for x in v]))
+    return {"n_done": v[0].value, "n_iters": v[1].value, "peak_budget_bytes": v[2].value,
+            "entries_done": v[3].value}
+
+
+def qk_server_destroy(server: Server):
+    server.close()

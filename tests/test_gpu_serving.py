@@ -1,0 +1,134 @@
+"""Serving: continuous batching against resident support sets.
+
+Checks that returned rows match the FP64 oracle (Eqs. (3), (7), (11) with
+the request's w), that a request's rows are bitwise the same alone and in a
+mixed batch, that a small HBM budget queues requests instead of failing,
+and the rejection / cancellation paths.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import checks, classical, mps  # noqa: E402
+from synthdata import config_inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (16, 64)
+NSUP = {16: 96, 64: 80}
+
+
+@pytest.fixture(scope="module")
+def qk():
+    import paper_2602_01330_amd.qk as qk
+    return qk
+
+
+@pytest.fixture(scope="module")
+def data():
+    out = {}
+    for d in DIMS:
+        sup, test, _ = config_inputs("C5", d=d, n_train=NSUP[d], n_test=40)
+        out[d] = (sup, test)
+    return out
+
+
+def make_server(qk, data, **kw):
+    srv = qk.qk_server_create(**kw)
+    for d in DIMS:
+        qk.qk_server_load_support(srv, torch.as_tensor(data[d][0], device="cuda"), 2, 64)
+    return srv
+
+
+def fetch(qk, srv, rid, n_rows, n_sup):
+    st = qk.qk_server_wait(srv, rid, 60000)
+    assert st == qk.QK_REQ_DONE, (st, qk.qk_last_error())
+    out = np.empty((n_rows, n_sup))
+    st, rows = qk.qk_server_poll(srv, rid, out)
+    assert st == qk.QK_REQ_DONE
+    return rows
+
+
+def oracle_rows(x, sup, w):
+    L, d = 2, x.shape[1]
+    A = mps.pad_batch(mps.build_batch(x, L, 64))
+    B = mps.pad_batch(mps.build_batch(sup, L, 64))
+    K, _ = mps.gram(A, B)
+    return classical.mix(K, classical.rbf_gram(x, sup, 1.0 / d), w)
+
+
+def test_rows_match_oracle(qk, data):
+    srv = make_server(qk, data)
+    try:
+        reqs = []
+        for k, (d, n, w) in enumerate([(16, 3, 0.2), (64, 7, 0.9), (16, 1, 1.0), (64, 12, 0.0)]):
+            x = data[d][1][k:k + n]
+            reqs.append((qk.qk_server_submit(srv, x, w), x, d, w))
+        for rid, x, d, w in reqs:
+            print(f"[serve] d={d} rows={len(x)} w={w}", flush=True)
+            got = fetch(qk, srv, rid, len(x), NSUP[d])
+            ok, dmax, rel = checks.gate_a(got, oracle_rows(x, data[d][0], w))
+            assert ok, (d, dmax, rel)
+    finally:
+        srv.close()
+
+
+def test_alone_and_mixed_are_bitwise_equal(qk, data):
+    rng = np.random.default_rng(3)
+    plan = [(int(rng.choice(DIMS)), int(rng.integers(1, 9)), float(rng.uniform()))
+            for _ in range(12)]
+    xs = [data[d][1][k:k + n] for k, (d, n, w) in enumerate(plan)]
+    srv = make_server(qk, data)
+    try:
+        alone = []
+        for (d, n, w), x in zip(plan, xs):  # one request in flight at a time
+            alone.append(fetch(qk, srv, qk.qk_server_submit(srv, x, w), n, NSUP[d]).copy())
+        ids = [qk.qk_server_submit(srv, x, w) for (d, n, w), x in zip(plan, xs)]
+        mixed = [fetch(qk, srv, rid, n, NSUP[d]).copy() for rid, (d, n, w) in zip(ids, plan)]
+        stats = qk.qk_server_stats(srv)
+        assert stats["n_iters"] < 2 * len(plan)  # the burst was batched
+    finally:
+        srv.close()
+    for a, m in zip(alone, mixed):
+        assert np.array_equal(a, m)
+
+
+def test_small_budget_queues_requests(qk, data):
+    one = 12 * 64 * 2 * 16 * 24 + 12 * 80 * 8 + 12 * 65 * 4 + 12 * 72 + 4096
+    srv = make_server(qk, data, budget_bytes=int(1.5 * one))
+    try:
+        x = data[64][1][:12]
+        ids = [qk.qk_server_submit(srv, x, 0.5) for _ in range(6)]
+        rows = [fetch(qk, srv, rid, 12, NSUP[64]).copy() for rid in ids]
+        stats = qk.qk_server_stats(srv)
+        assert stats["peak_budget_bytes"] <= int(1.5 * one)
+        assert stats["n_iters"] >= 6  # one request per iteration fits
+        for r in rows[1:]:
+            assert np.array_equal(r, rows[0])
+    finally:
+        srv.close()
+
+
+def test_rejections_and_cancel(qk, data):
+    srv = make_server(qk, data, budget_bytes=1 << 20)
+    try:
+        with pytest.raises(qk.QkError):
+            qk.qk_server_submit(srv, np.zeros((2, 32)), 0.5)  # no support for d = 32
+        with pytest.raises(qk.QkError):
+            qk.qk_server_submit(srv, data[16][1][:2], 1.5)  # w outside [0, 1]
+        bad = data[16][1][:2].copy()
+        bad[0, 0] = np.nan
+        with pytest.raises(qk.QkError):
+            qk.qk_server_submit(srv, bad, 0.5)
+        big = np.tile(data[64][1][:1], (600, 1))  # above budget and row cap
+        rid = qk.qk_server_submit(srv, big, 0.5)
+        assert qk.qk_server_wait(srv, rid, 60000) == qk.QK_REQ_FAILED
+        ids = [qk.qk_server_submit(srv, data[16][1][:4], 0.5) for _ in range(20)]
+        qk.qk_server_cancel(srv, ids[-1])
+        states = [qk.qk_server_wait(srv, i, 60000) for i in ids]
+        assert states[-1] in (qk.QK_REQ_CANCELLED, qk.QK_REQ_DONE)
+        assert all(s in (qk.QK_REQ_DONE, qk.QK_REQ_CANCELLED) for s in states)
+        assert qk.qk_server_stats(srv)["n_done"] >= 19
+    finally:
+        srv.close()
