@@ -61,7 +61,7 @@ def cpu_baseline(x_tr, seconds_target=15.0):
     """Time the FP64 oracle on a bounded sample with a process pool."""
     import multiprocessing as mp
     cores = min(len(os.sched_getaffinity(0)), 16)
-    n_build, n_pairs = 4, 1536
+    n_build, n_pairs = 8, 12288
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores, initializer=_pool_init) as pool:
@@ -113,6 +113,9 @@ def serving(args):
     from synthdata import config_inputs, gen_requests
     from synthdata.generators import C5_DIMS
 
+    # the client submits on a Poisson schedule from one thread while another
+    # drains results; a short GIL switch interval keeps the schedule on time
+    sys.setswitchinterval(2e-4)
     dev = torch.device("cuda:0")
     srv = qk.qk_server_create(budget_bytes=1 << 30, max_rows_per_iter=512, n_streams=2,
                               prec="auto")
@@ -177,6 +180,55 @@ def serving(args):
             "submit_span_s": float(max(sub) - min(sub)) if sub else 0.0,
             "n_iterations": stats["n_iters"],
             "peak_budget_mb": stats["peak_budget_bytes"] / 2**20}
+
+
+def ragged(args):
+    """Ten feature dimensions d in {2, ..., 784}, 1000 cluster samples each,
+    L = 2, chi_max = min(2^(d/2), 64), symmetric 1000 x 1000 per d: one
+    persistent launch over all of them, and each d alone. MPS resident."""
+    import numpy as np
+    import torch
+
+    import paper_2602_01330_amd.qk as qk
+    from synthdata import config_inputs
+    from synthdata.generators import C4_DIMS, chi_cap
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    batches, outs, tasks = {}, {}, []
+    for d in C4_DIMS:
+        x, _, _ = config_inputs("C4", d=d, n_train=1000, n_test=0)
+        batches[d] = qk.qk_mps_build(torch.as_tensor(x, device=dev), 2, chi_cap("C4", d))
+        outs[d] = torch.empty((1000, 1000), dtype=torch.float64, device=dev)
+        tasks.append({"rows": batches[d], "cols": batches[d], "symmetric": True,
+                      "kq": outs[d]})
+    pairs = 1000 * 1001 // 2
+
+    def timed(ts, reps=3):
+        qk.qk_overlap_gram_multi(ts, "auto")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            qk.qk_overlap_gram_multi(ts, "auto")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for t in tasks:  # tune every (chi_pad, n-bucket) key once
+        qk.qk_autotune(t["rows"], t["cols"], True, max_tiles=256)
+    all_ms = timed(tasks)
+    per_d = {}
+    for d, t in zip(C4_DIMS, tasks):
+        ms = timed([t])
+        per_d[str(d)] = {"ms": ms, "entries_per_s": pairs / (ms / 1e3)}
+    sum_alone = sum(v["ms"] for v in per_d.values())
+    log(f"ragged: one launch {all_ms:.2f} ms, sum of per-d launches {sum_alone:.2f} ms")
+    return {"workload": "d in {2,4,8,...,512,784}, 1000 samples each, symmetric, L=2, "
+                        "chi_max=min(2^(d/2),64); MPS resident",
+            "one_launch_ms": all_ms, "one_launch_entries_per_s": 10 * pairs / (all_ms / 1e3),
+            "sum_of_single_d_launches_ms": sum_alone, "per_d": per_d,
+            "sweep_form_per_d": {str(d): qk.qk_resolve_precision(batches[d], batches[d])
+                                 for d in C4_DIMS}}
 
 
 def run(args):
@@ -252,11 +304,15 @@ def run(args):
                 "chi_max_realized": info["chi_realized_max"], "chi_pad": info["chi_pad"]}
 
     chosen = args.prec
+    tune = None
     if chosen == "auto":
-        x1 = xtr[:2]
-        b = qk.qk_mps_build(x1, 2, 64)
-        chosen = qk.qk_resolve_precision(b, b)
+        # the project autotuner times the eligible forms on a slice of the
+        # train x train tiles; AUTO then resolves to the winner
+        b = qk.qk_mps_build(xtr, 2, 64, 1e-10, store=qk.QK_STORE_ALL)
+        chosen = qk.qk_autotune(b, b, True, max_tiles=2048)
+        tune = qk.qk_tune_export()
         b.close()
+        log(f"bench: autotune chose {chosen}")
     res = measure(chosen, args.steps, args.warmup)
     value = pairs / (res["ms_per_step"] / 1e3)
     bound, peak = PEAKS[chosen]
@@ -271,7 +327,7 @@ def run(args):
                                "cutoff 1e-10, fused RBF (gamma=1/d) + mix w=0.5",
                    "n_train": ntr, "n_test": nte, "d": d, "n_layers": 2, "chi_max": 64,
                    "chi_realized_max": res["chi_max_realized"], "chi_pad": res["chi_pad"],
-                   "unique_pairs": pairs, "sweep_form": chosen},
+                   "unique_pairs": pairs, "sweep_form": chosen, "autotune_table": tune},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
                      "kernel": "sweep (one persistent launch per step)",
@@ -282,6 +338,9 @@ def run(args):
         line["plain_fp64"] = {"value": pairs / (p["ms_per_step"] / 1e3),
                               "ms_per_step": p["ms_per_step"], "sweep_ms": p["sweep_ms"]}
         line["speedup_vs_plain_fp64"] = value / line["plain_fp64"]["value"]
+    if not args.no_ragged:
+        log("bench: ragged multi-d run")
+        line["ragged"] = ragged(args)
     if args.serve_seconds > 0:
         log("bench: serving run")
         line["serving"] = serving(args)
@@ -301,6 +360,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-ragged", action="store_true", help="skip the ten-d ragged run")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="measured seconds of the serving run (0 skips it)")
     ap.add_argument("--serve-warmup", type=float, default=3.0)

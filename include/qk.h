@@ -207,6 +207,7 @@ typedef struct {
 /*
  * qk_overlap_gram_multi -- all tasks in one persistent launch; tiles of all
  * tasks form one list in longest-processing-time order (cost n * chi^3).
+ * QK_PREC_AUTO resolves with the task of largest total cost.
  * At most 16 tasks. Errors as qk_overlap_gram.
  */
 QK_API qk_status qk_overlap_gram_multi(const qk_gram_task* tasks, int32_t n_tasks,
@@ -243,6 +244,25 @@ QK_API qk_status qk_dual_mix(const double* kq_dev, int64_t ld_kq, const double* 
  * disables refinement for that form. Process-wide setting.
  */
 QK_API qk_status qk_set_refine_threshold(qk_precision prec, double tau);
+
+/*
+ * qk_autotune -- times the sweep forms that meet the stated tolerance
+ * (complex FP64, complex FP32 on VALU with 2..4 persistent workgroups per CU,
+ * complex FP32 on MFMA, split BF16x3 on MFMA) on the first max_tiles 16 x 16
+ * tiles of rows x cols (refinement off while timing), and records the
+ * fastest under the key (chi_pad, ceil(log2 n_qubits)); QK_PREC_AUTO then
+ * resolves to it for every batch pair with that key. Synchronises the
+ * stream. Writes the winner to *chosen (may be NULL).
+ */
+QK_API qk_status qk_autotune(const qk_mps_batch* rows, const qk_mps_batch* cols,
+                             int32_t symmetric, int32_t max_tiles, void* hip_stream,
+                             qk_precision* chosen);
+
+/* Tuning table as text, one entry per line: "chi_pad bucket form wg_per_cu
+ * us_per_tile". Export writes at most cap bytes (NUL-terminated) and the
+ * needed size to *len; import merges a table (INVALID_ARG if malformed). */
+QK_API qk_status qk_tune_export(char* buf, int64_t cap, int64_t* len);
+QK_API qk_status qk_tune_import(const char* text);
 
 /* Resolves QK_PREC_AUTO for a batch pair: writes the form the library
  * would run (from the tuning table, else the built-in default). */

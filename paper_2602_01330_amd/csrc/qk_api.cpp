@@ -220,7 +220,8 @@ double refine_tau(qk_precision p) {
   return (p >= 0 && p < 6) ? g_refine_tau[p] : 0.0;
 }
 
-qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, hipStream_t s) {
+qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, hipStream_t s,
+                    int64_t max_tiles = -1) {
   // longest-processing-time order: per-tile cost ~ nq * T^3
   std::stable_sort(tasks.begin(), tasks.end(), [](const QkTask& a, const QkTask& b) {
     return (double)a.nq * a.T * a.T * a.T > (double)b.nq * b.T * b.T * b.T;
@@ -234,9 +235,14 @@ qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, h
     tt.t[k] = tasks[k];
   }
   tt.n_tasks = (int32_t)tasks.size();
+  if (max_tiles >= 0 && acc > max_tiles) acc = max_tiles;  // autotuning slice
   tt.total_tiles = acc;
   if (acc == 0) return QK_OK;
-  const int grid64 = (int)std::min<int64_t>(acc, (int64_t)device_cus() * 2);
+  // persistent workgroups per CU: from the tuning table, else per form
+  QkTuneEntry te;
+  const bool tuned = qk_tune_lookup(tasks[0].T, tasks[0].nq, &te) && te.form == prec;
+  const int grid64 = (int)std::min<int64_t>(
+      acc, (int64_t)device_cus() * (tuned && prec == QK_PREC_FP64 ? te.wg_per_cu : 2));
   if (prec == QK_PREC_FP64) {
     QK_HIP(qk_launch_sweep_fp64(tt, grid64, nullptr, s), "sweep launch");
     return QK_OK;
@@ -249,7 +255,8 @@ qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, h
   const double ln_tau = refine ? std::log(tau) : 0.0;
   hipError_t e;
   if (prec == QK_PREC_FP32) {
-    int grid = (int)std::min<int64_t>(acc, (int64_t)device_cus() * 3);
+    int grid = (int)std::min<int64_t>(
+        acc, (int64_t)device_cus() * (tuned ? te.wg_per_cu : 3));
     e = qk_launch_sweep_fp32(tt, grid, flags, ln_tau, s);
   } else {
     e = qk_launch_sweep_mfma(tt, prec, device_cus(), flags, ln_tau, s);
@@ -453,7 +460,20 @@ qk_status qk_overlap_gram_multi(const qk_gram_task* tasks, int32_t n_tasks,
     return fail(QK_ERR_INVALID_ARG, "need 1..16 tasks");
   hipStream_t s = (hipStream_t)hip_stream;
   if (prec == QK_PREC_AUTO) {
-    qk_status st = qk_resolve_precision(tasks[0].rows, tasks[0].cols, &prec);
+    // one launch, one form: the form tuned for the most expensive task (cost
+    // per tile ~ n_qubits * chi_pad^3), which dominates the launch
+    int top = 0;
+    double best = -1.0;
+    for (int k = 0; k < n_tasks; ++k) {
+      if (!tasks[k].rows || !tasks[k].cols) return fail(QK_ERR_INVALID_ARG, "batch is NULL");
+      const double c = (double)tasks[k].rows->nq * tasks[k].rows->T * tasks[k].rows->T *
+                       tasks[k].rows->T * (double)tasks[k].rows->n * (double)tasks[k].cols->n;
+      if (c > best) {
+        best = c;
+        top = k;
+      }
+    }
+    qk_status st = qk_resolve_precision(tasks[top].rows, tasks[top].cols, &prec);
     if (st != QK_OK) return st;
   }
   if (prec < QK_PREC_FP64 || prec > QK_PREC_FP32_MFMA)
@@ -477,6 +497,88 @@ qk_status qk_overlap_gram_multi(const qk_gram_task* tasks, int32_t n_tasks,
     QK_HIP(hipStreamWaitEvent(s, tasks[k].cols->ready, 0), "wait for column batch");
   }
   return run_tasks(tv, prec, tau, s);
+}
+
+qk_status qk_autotune(const qk_mps_batch* rows, const qk_mps_batch* cols, int32_t symmetric,
+                      int32_t max_tiles, void* hip_stream, qk_precision* chosen) {
+  if (!rows || !cols || max_tiles < 1) return fail(QK_ERR_INVALID_ARG, "bad autotune arguments");
+  hipStream_t s = (hipStream_t)hip_stream;
+  struct Cand {
+    qk_precision p;
+    int wg;
+  };
+  std::vector<Cand> cands;
+  if (rows->t64 && cols->t64)
+    for (int wg : {1, 2}) cands.push_back({QK_PREC_FP64, wg});
+  if (rows->t32 && cols->t32) {
+    for (int wg : {2, 3, 4}) cands.push_back({QK_PREC_FP32, wg});
+    if (qk_mfma_supports(QK_PREC_FP32_MFMA, rows->T)) {
+      cands.push_back({QK_PREC_FP32_MFMA, 1});
+      cands.push_back({QK_PREC_BF16X3, 1});
+    }
+  }
+  if (cands.empty()) return fail(QK_ERR_UNSUPPORTED, "no sweep form applies to these batches");
+  double* scratch = nullptr;
+  QK_HIP(hipMallocAsync((void**)&scratch, std::max<int64_t>(rows->n * cols->n, 1) * sizeof(double), s),
+         "autotune scratch");
+  hipEvent_t e0, e1;
+  QK_HIP(hipEventCreate(&e0), "event");
+  QK_HIP(hipEventCreate(&e1), "event");
+  QK_HIP(hipStreamWaitEvent(s, rows->ready, 0), "wait");
+  QK_HIP(hipStreamWaitEvent(s, cols->ready, 0), "wait");
+  double best = 1e300;
+  Cand win = cands[0];
+  int64_t tiles = 1;
+  qk_status st = QK_OK;
+  for (const Cand& c : cands) {
+    std::vector<QkTask> tv(1);
+    st = fill_task(tv[0], rows, cols, symmetric, c.p == QK_PREC_FP64, false, nullptr, 0,
+                   scratch, cols->n, nullptr, tile_for(c.p));
+    if (st != QK_OK) break;
+    tiles = std::min<int64_t>(tv[0].n_tiles, max_tiles);
+    qk_tune_store(rows->T, rows->nq, QkTuneEntry{c.p, c.wg, 0.0});
+    st = run_tasks(tv, c.p, 0.0, s, max_tiles);  // warm-up
+    if (st != QK_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(e0, s) != hipSuccess) { st = fail(QK_ERR_HIP, "event"); break; }
+    for (int rep = 0; rep < 3 && st == QK_OK; ++rep) st = run_tasks(tv, c.p, 0.0, s, max_tiles);
+    if (st != QK_OK) break;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(QK_ERR_HIP, "autotune timing");
+      break;
+    }
+    const double us_tile = 1e3 * ms / 3.0 / (double)std::max<int64_t>(tiles, 1);
+    if (us_tile < best) {
+      best = us_tile;
+      win = c;
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFreeAsync(scratch, s);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != QK_OK) return st;
+  qk_tune_store(rows->T, rows->nq, QkTuneEntry{win.p, win.wg, best});
+  if (chosen) *chosen = win.p;
+  return QK_OK;
+}
+
+qk_status qk_tune_export(char* buf, int64_t cap, int64_t* len) {
+  const std::string t = qk_tune_export_text();
+  if (len) *len = (int64_t)t.size() + 1;
+  if (buf && cap > 0) {
+    const int64_t n = std::min<int64_t>(cap - 1, (int64_t)t.size());
+    memcpy(buf, t.data(), n);
+    buf[n] = 0;
+  }
+  return QK_OK;
+}
+
+qk_status qk_tune_import(const char* text) {
+  if (!text) return fail(QK_ERR_INVALID_ARG, "NULL text");
+  if (!qk_tune_import_text(text)) return fail(QK_ERR_INVALID_ARG, "malformed tuning table");
+  return QK_OK;
 }
 
 qk_status qk_set_refine_threshold(qk_precision prec, double tau) {

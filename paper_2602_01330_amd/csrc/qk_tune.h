@@ -1,6 +1,8 @@
 // Sweep-form selection and the MFMA sweep launcher.
 #pragma once
 
+#include <string>
+
 #include "qk_internal.h"
 
 // True if the MFMA sweep of form p is instantiated for padded bond T.
@@ -12,3 +14,16 @@ hipError_t qk_launch_sweep_mfma(const QkTaskTable& tt, qk_precision p, int cus,
 
 // QK_PREC_AUTO: the form to run for batches with padded bond T and nq sites.
 qk_precision qk_tune_choose(int T, int nq, bool have_fp32, bool have_fp64);
+
+// Tuning table: (T, ceil(log2(nq))) -> fastest form and persistent
+// workgroups per CU measured by qk_autotune.
+struct QkTuneEntry {
+  qk_precision form;
+  int wg_per_cu;
+  double us_per_tile;
+};
+int qk_tune_bucket(int nq);
+bool qk_tune_lookup(int T, int nq, QkTuneEntry* e);
+void qk_tune_store(int T, int nq, const QkTuneEntry& e);
+std::string qk_tune_export_text();
+bool qk_tune_import_text(const std::string& text);

@@ -82,6 +82,11 @@ _lib.qk_dual_mix.argtypes = [_P, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int64,
                              _P, C.c_int64, _P]
 _lib.qk_resolve_precision.argtypes = [_P, _P, C.POINTER(C.c_int)]
 _lib.qk_set_refine_threshold.argtypes = [C.c_int, C.c_double]
+_lib.qk_autotune.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_int)]
+_lib.qk_tune_export.argtypes = [C.c_char_p, C.c_int64, C.POINTER(C.c_int64)]
+_lib.qk_tune_import.argtypes = [C.c_char_p]
+for _f in ("qk_autotune", "qk_tune_export", "qk_tune_import"):
+    getattr(_lib, _f).restype = C.c_int
 _lib.qk_status_string.restype = C.c_char_p
 _lib.qk_status_string.argtypes = [C.c_int]
 _lib.qk_last_error.restype = C.c_char_p
@@ -118,7 +123,8 @@ EXPORTED = ["qk_server_create", "qk_server_load_support", "qk_server_submit",
             "qk_server_stats", "qk_server_destroy",
             "qk_mps_build", "qk_mps_import", "qk_mps_info", "qk_mps_chi", "qk_mps_release",
             "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
-            "qk_resolve_precision", "qk_set_refine_threshold", "qk_status_string",
+            "qk_resolve_precision", "qk_set_refine_threshold", "qk_autotune",
+            "qk_tune_export", "qk_tune_import", "qk_status_string",
             "qk_last_error"]
 
 
@@ -304,6 +310,27 @@ def qk_set_refine_threshold(prec, tau: float):
     """FP64 recomputation of tiles holding K_q > tau for a reduced form."""
     p = PREC[prec] if isinstance(prec, str) else int(prec)
     _check(_lib.qk_set_refine_threshold(p, float(tau)))
+
+
+def qk_autotune(rows: MpsBatch, cols: MpsBatch, symmetric=False, max_tiles=2048,
+                stream=None) -> str:
+    """Times the eligible sweep forms on a slice of the tiles; AUTO uses the winner."""
+    out = C.c_int()
+    _check(_lib.qk_autotune(rows.handle, cols.handle, 1 if symmetric else 0, int(max_tiles),
+                            _stream(stream), C.byref(out)))
+    return PREC_NAME[out.value]
+
+
+def qk_tune_export() -> str:
+    n = C.c_int64()
+    _check(_lib.qk_tune_export(None, 0, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    _check(_lib.qk_tune_export(buf, n.value, C.byref(n)))
+    return buf.value.decode()
+
+
+def qk_tune_import(text: str):
+    _check(_lib.qk_tune_import(text.encode()))
 
 
 REFINE_DEFAULT = {"fp32": 1e-2, "fp32_mfma": 1e-2, "bf16x3": 1e-2, "bf16x2": 1e-3}

@@ -38,3 +38,17 @@ def test_binding_covers_the_abi():
     import paper_2602_01330_amd.qk as qk
     for n in declared():
         assert n in qk.EXPORTED and hasattr(qk, n), n
+
+
+def test_tuning_table_round_trip_without_gpu():
+    """qk_tune_import / qk_tune_export parse and print the table on the host."""
+    import paper_2602_01330_amd.qk as qk
+    qk.qk_tune_import("4 10 5 1 12.5\n2 1 1 3 0.25\n")
+    text = qk.qk_tune_export()
+    rows = {tuple(l.split()[:4]) for l in text.strip().splitlines()}
+    assert ("4", "10", "5", "1") in rows and ("2", "1", "1", "3") in rows
+    import pytest
+    with pytest.raises(qk.QkError):
+        qk.qk_tune_import("4 10 99 1 1.0\n")  # unknown form
+    with pytest.raises(qk.QkError):
+        qk.qk_tune_import("garbage")
