@@ -30,6 +30,12 @@ PEAKS = {  # published MI355X figures, TFLOP/s
     "fp64": ("alu", 78.6), "fp32": ("alu", 157.3), "fp32_mfma": ("mfma", 157.3),
     "bf16x2": ("mfma", 2500.0), "bf16x3": ("mfma", 2500.0),
 }
+# HBM bytes per sweep launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# summarised under profiles/ (scaled by the copy-kernel calibration), valid
+# only for the kernel source they were taken with.
+TRAFFIC = {"fp32_mfma": {"source": "paper_2602_01330_amd/csrc/sweep_mfma.hip",
+                         "sha256_prefix": "7009ece61520bb6b",
+                         "bytes": 603.3e9 + 0.652e9}}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp32_mfma": "f32", "bf16x2": "bf16", "bf16x3": "bf16"}
 
 
@@ -55,6 +61,17 @@ def algorithmic_flops(chi_rows, chi_cols, symmetric):
         diag = 16.0 * float(((a0 * b0 * b1) + (a1 * a0 * b1)).sum())
         total = 0.5 * (total + diag)
     return total
+
+
+def traffic_for(form):
+    """Measured HBM bytes per launch, or None if the kernel changed since."""
+    import hashlib
+    t = TRAFFIC.get(form)
+    if t is None:
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()
+    return t["bytes"] if h.startswith(t["sha256_prefix"]) else None
 
 
 def cpu_baseline(x_tr, seconds_target=15.0):
@@ -329,7 +346,7 @@ def run(args):
                    "chi_realized_max": res["chi_max_realized"], "chi_pad": res["chi_pad"],
                    "unique_pairs": pairs, "sweep_form": chosen, "autotune_table": tune},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic_for(chosen),
                      "kernel": "sweep (one persistent launch per step)",
                      "kernel_ms": res["sweep_ms"], "algorithmic_flop": res["flops"]},
     }
