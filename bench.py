@@ -385,8 +385,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the Gram tiles shard across GPUs without "
-              "communication in the sweep (see DESIGN.md), but multi-GPU runs are not part "
-              "of this build; use --gpus 1.", file=sys.stderr)
+              "communication in the sweep, but multi-GPU execution is not implemented; "
+              "use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     run(args)
 
