@@ -47,8 +47,13 @@ template <int LD>
 __device__ bool jacobi_columns(double2* X, double2* V, int R, int C, double floor2) {
   const int lane = threadIdx.x;
   const int npairs = C >> 1;
-  int g = 64 / npairs;  // lanes per pair, a power of two
-  g = g >= 32 ? 32 : (g >= 16 ? 16 : (g >= 8 ? 8 : (g >= 4 ? 4 : (g >= 2 ? 2 : 1))));
+  // lanes per pair: the smallest power of two covering the rows (so the
+  // dot-product reductions take log2(rows) shuffle steps), but no more than
+  // the wave can give every pair
+  int cap = 64 / npairs;
+  cap = cap >= 32 ? 32 : (cap >= 16 ? 16 : (cap >= 8 ? 8 : (cap >= 4 ? 4 : (cap >= 2 ? 2 : 1))));
+  int g = 1;
+  while (g < R && g < cap) g <<= 1;
   const int pair = lane / g;
   const int sub = lane % g;
   const bool active = pair < npairs;

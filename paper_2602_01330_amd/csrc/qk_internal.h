@@ -70,6 +70,18 @@ struct QkTask {
 
 constexpr int QK_MAX_TASKS = 16;
 
+// Tile processed by persistent workgroup `wg` (of `grid`) in round `round`.
+// Workgroups are dispatched round-robin over the 8 XCDs (wg % 8), each with
+// its own L2; when the grid is a multiple of 8, XCD x takes the contiguous
+// slice [x * grid/8, (x+1) * grid/8) of each round's tiles, so the tiles an
+// XCD runs together share their row samples (and different XCDs work on
+// different column samples). A bijection of [0, grid) in every round.
+__device__ inline int64_t qk_tile_of(int64_t round, int wg, int grid) {
+  const int64_t base = round * (int64_t)grid;
+  if (grid % 8) return base + wg;
+  return base + (int64_t)(wg % 8) * (grid / 8) + wg / 8;
+}
+
 struct QkTaskTable {
   QkTask t[QK_MAX_TASKS];
   int32_t n_tasks;

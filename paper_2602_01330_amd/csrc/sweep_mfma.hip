@@ -453,7 +453,9 @@ template <int F>
 __global__ __launch_bounds__(kThreads) void sweep_mfma_kernel(QkTaskTable tt, uint32_t* flags,
                                                               double ln_tau) {
   __shared__ MfmaSmem sm;
-  for (int64_t q = blockIdx.x; q < tt.total_tiles; q += gridDim.x) {
+  for (int64_t rnd = 0; rnd * gridDim.x < tt.total_tiles; ++rnd) {
+    const int64_t q = qk_tile_of(rnd, blockIdx.x, gridDim.x);
+    if (q >= tt.total_tiles) break;  // only the last round is partial
     int k = 0;
     while (k + 1 < tt.n_tasks && tt.t[k + 1].tile_begin <= q) ++k;
     const QkTask& t = tt.t[k];

@@ -260,7 +260,9 @@ __global__ __launch_bounds__(kThreads) void sweep_valu_kernel(QkTaskTable tt,
                                                               double ln_tau) {
   __shared__ SweepSmem<R, MaxT<R>::v> sm4;
   __shared__ unsigned tile_mask[kQkMaskWords];
-  for (int64_t q = blockIdx.x; q < tt.total_tiles; q += gridDim.x) {
+  for (int64_t rnd = 0; rnd * gridDim.x < tt.total_tiles; ++rnd) {
+    const int64_t q = qk_tile_of(rnd, blockIdx.x, gridDim.x);
+    if (q >= tt.total_tiles) continue;  // last round only; no barrier skipped
     const uint32_t* mi = mask_in ? mask_in + q * kQkMaskWords : nullptr;
     if (mi) {  // uniform per workgroup: skip tiles without a marked pair
       unsigned any = 0;
