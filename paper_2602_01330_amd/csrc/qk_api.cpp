@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -246,6 +247,13 @@ qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, h
   if (prec == QK_PREC_FP64) {
     QK_HIP(qk_launch_sweep_fp64(tt, grid64, nullptr, s), "sweep launch");
     return QK_OK;
+  }
+  // the reduced-precision sweeps address one site's packed sample array with
+  // 32-bit byte offsets
+  for (const QkTask& t : tasks) {
+    const int64_t slot_bytes = (int64_t)2 * t.T * t.T * 8;
+    if (std::max(t.na, t.nb) * slot_bytes > (int64_t)UINT32_MAX)
+      return fail(QK_ERR_UNSUPPORTED, "batch too large for a 32-bit packed site array");
   }
   const bool refine = tau > 0.0;
   uint32_t* flags = nullptr;

@@ -67,18 +67,34 @@ struct MfmaSmem {
   unsigned mask[kQkMaskWords];
 };
 
-// max over lanes l ^ 1 and l ^ 2 (DPP quad permutations) and l ^ 16 (swizzle)
-__device__ inline float max_xor_1_2_16(float m) {
-  m = fmaxf(m, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(m), 0xB1, 0xF, 0xF, false)));
-  m = fmaxf(m, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(m), 0x4E, 0xF, 0xF, false)));
-  m = fmaxf(m, __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(m), 0x401F)));
+// max over lanes l ^ 1 and l ^ 2 (DPP quad permutations) and l ^ 16
+// (swizzle) of the bit patterns of non-negative floats, whose unsigned order
+// is their numeric order
+__device__ inline unsigned umax_xor_1_2_16(unsigned m) {
+  m = max(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0xB1, 0xF, 0xF, false));
+  m = max(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x4E, 0xF, 0xF, false));
+  m = max(m, (unsigned)__builtin_amdgcn_ds_swizzle((int)m, 0x401F));
   return m;
 }
 
-__device__ inline int frexp_exp(float m) {
-  return (int)((__float_as_uint(m) >> 23) & 0xff) - 126;
+// exponent e with |x| < 2^e <= 2|x| for the float with bit pattern m > 0;
+// 0 for m == 0 and for inf / NaN (those are left to reach the output)
+__device__ inline int scale_exp(unsigned m) {
+  const int ex = (int)(m >> 23);
+  return (m == 0u || ex >= 255) ? 0 : ex - 126;
 }
 __device__ inline float pow2f(int e) { return __uint_as_float((unsigned)(e + 127) << 23); }
+
+// Buffer descriptor over one site's packed sample array: loads at byte
+// offsets at or beyond `bytes` return zero, which pads bond blocks smaller
+// than 4 x 4 and the unused operand rows without any per-element select.
+__device__ inline __amdgpu_buffer_rsrc_t site_rsrc(const char* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ inline float2 ld2(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
 
 __device__ inline __bf16 bf16_trunc(float x) {
   unsigned short h = (unsigned short)(__float_as_uint(x) >> 16);
@@ -232,7 +248,7 @@ __device__ inline void tile_coords(const QkTask& t, int64_t lt, int& ti, int& tj
 
 #define QK_LDS_FENCE() __asm__ volatile("" ::: "memory")
 
-template <int F, bool kFullT>
+template <int F>
 __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t* mask,
                          int64_t tile_id, double ln_tau) {
   const int tid = threadIdx.x;
@@ -241,60 +257,54 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
   const int g = lane >> 4, n = lane & 15;
   const int wr = w >> 2, wc = w & 3;
   const int64_t i0 = (int64_t)ti * kTile + 4 * wr, j0 = (int64_t)tj * kTile + 4 * wc;
-  const float2* ta = static_cast<const float2*>(t.ta);
-  const float2* tb = static_cast<const float2*>(t.tb);
-  const int T = kFullT ? 4 : t.T, TT = T * T, slotT = 2 * TT;
+  const int T = t.T, TT = T * T, slotT = 2 * TT;
   const int nq = t.nq;
   float* gb = sm.g[w];
   float* eb = sm.e[w];
 
-  // ---- per-lane 32-bit operand offsets from the wave's (scalar) site base.
-  // Samples past the end are clamped to the last one: those pairs compute
-  // garbage that is never written, and every pair's E is independent.
+  // ---- per-lane byte offsets into a site's packed sample array (constant
+  // over the sites). Samples past the end are clamped to the last one: those
+  // pairs compute garbage that is never written, and every pair's E is
+  // independent. Elements outside the T x T bond block, and the A values of
+  // the zero rows of step L, take the out-of-range offset and load as zero.
   // step R, column q: B^s[b = g][b' = n&3], s = n>>3
   const int rs = n >> 3, rcout = (n >> 2) & 1, rbp = n & 3;
   // step L, row p: A^s[a = g][a' = n&3] for s = 0, 1 (lanes n < 8)
   const int lcp = n >> 2, lap = n & 3;
-  // byte offsets from the start of the site's sample array (never negative;
-  // below n * slot * 8 bytes, which fits 32 bits for any batch of interest)
+  const unsigned bbytes = (unsigned)((int64_t)t.nb * slotT * 8);
+  const unsigned abytes = (unsigned)((int64_t)t.na * slotT * 8);
+  const bool bin = g < T && rbp < T;
+  const bool ain = g < T && lap < T && n < 8;
   unsigned boff[4], aoff[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int64_t j = (j0 + q) < t.nb ? (j0 + q) : (t.nb - 1);
     const int64_t i = (i0 + q) < t.na ? (i0 + q) : (t.na - 1);
-    boff[q] = (unsigned)((j * slotT + rs * TT + (g < T ? g : 0) * T + (rbp < T ? rbp : 0)) * 8);
-    aoff[q] = (unsigned)((i * slotT + (g < T ? g : 0) * T + (lap < T ? lap : 0)) * 8);
+    boff[q] = bin ? (unsigned)((j * slotT + rs * TT + g * T + rbp) * 8) : bbytes;
+    aoff[q] = ain ? (unsigned)((i * slotT + g * T + lap) * 8) : abytes;
   }
-  // zero the elements outside the padded bond block (only when T < 4)
-  const bool bin = kFullT || (g < T && rbp < T);
-  const bool ain = kFullT || (g < T && lap < T);
-  const int64_t bstride = (int64_t)t.nb * slotT * 8, astride = (int64_t)t.na * slotT * 8;
-  const char* bbase = reinterpret_cast<const char*>(tb);
-  const char* abase = reinterpret_cast<const char*>(ta);
   const unsigned a1off = (unsigned)(TT * 8);
+  const char* bbase = static_cast<const char*>(t.tb);
+  const char* abase = static_cast<const char*>(t.ta);
+  const int64_t bstride = bbytes, astride = abytes;
 
   struct Ops {
     float2 b[4];
     float2 a[4][2];
   };
-  // loads are unconditional (the site index is clamped), so they can land
-  // straight in the operand registers and stay in flight
+  // the loads land straight in the operand registers and stay in flight
+  // until their first use one step later
   auto fetch_b = [&](int k, Ops& o) {
-    const char* pb = bbase + (int64_t)k * bstride;
+    const __amdgpu_buffer_rsrc_t r = site_rsrc(bbase + (int64_t)k * bstride, bbytes);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float2 v = *reinterpret_cast<const float2*>(pb + boff[q]);
-      o.b[q] = kFullT ? v : make_float2(bin ? v.x : 0.f, bin ? v.y : 0.f);
-    }
+    for (int q = 0; q < 4; ++q) o.b[q] = ld2(r, boff[q]);
   };
   auto fetch_a = [&](int k, Ops& o) {
-    const char* pa = abase + (int64_t)k * astride;
+    const __amdgpu_buffer_rsrc_t r = site_rsrc(abase + (int64_t)k * astride, abytes);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const float2 v0 = *reinterpret_cast<const float2*>(pa + aoff[q]);
-      const float2 v1 = *reinterpret_cast<const float2*>(pa + aoff[q] + a1off);
-      o.a[q][0] = kFullT ? v0 : make_float2(ain ? v0.x : 0.f, ain ? v0.y : 0.f);
-      o.a[q][1] = kFullT ? v1 : make_float2(ain ? v1.x : 0.f, ain ? v1.y : 0.f);
+      o.a[q][0] = ld2(r, aoff[q]);
+      o.a[q][1] = ld2(r, aoff[q] + a1off);
     }
   };
 
@@ -336,6 +346,9 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
       }
     }
     QK_LDS_FENCE();
+    // keep the step-L operand work (which waits for the A loads) below this
+    // point, so step R waits only for the B loads issued one site earlier
+    __builtin_amdgcn_sched_barrier(0);
     // ---- step L: E' = Ahat_i^dagger G for the wave's four rows, then the
     // exact power-of-two rescale every few sites (pair (p, q) lives on lanes
     // g in {0,1}, n>>2 == q: 4 lanes b' x 4 registers), then E' to LDS
@@ -349,12 +362,11 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
         bop[p][1] = gv[1];
         bop[p][2] = gv[2];
         bop[p][3] = gv[3];
-        const float2 a0 = cur.a[p][0], a1 = cur.a[p][1];
-        const bool z = n >= 8;
-        aop[p][0] = z ? 0.f : (lcp == 0 ? a0.x : -a0.y);  // s = 0, c_in = 0
-        aop[p][1] = z ? 0.f : (lcp == 0 ? a0.y : a0.x);   // s = 0, c_in = 1
-        aop[p][2] = z ? 0.f : (lcp == 0 ? a1.x : -a1.y);  // s = 1, c_in = 0
-        aop[p][3] = z ? 0.f : (lcp == 0 ? a1.y : a1.x);   // s = 1, c_in = 1
+        const float2 a0 = cur.a[p][0], a1 = cur.a[p][1];  // zero on rows n >= 8
+        aop[p][0] = lcp == 0 ? a0.x : -a0.y;  // s = 0, c_in = 0
+        aop[p][1] = lcp == 0 ? a0.y : a0.x;   // s = 0, c_in = 1
+        aop[p][2] = lcp == 0 ? a1.x : -a1.y;  // s = 1, c_in = 0
+        aop[p][3] = lcp == 0 ? a1.y : a1.x;   // s = 1, c_in = 1
       }
       fetch_a(kn, cur);  // in flight until the next step L
       f4 acc[4];
@@ -364,10 +376,12 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
       if ((k % kRescaleEvery) == kRescaleEvery - 1 || !more) {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-          float m = fmaxf(fmaxf(fabsf(acc[p][0]), fabsf(acc[p][1])),
-                          fmaxf(fabsf(acc[p][2]), fabsf(acc[p][3])));
-          m = max_xor_1_2_16(m);
-          const int e = m > 0.f ? frexp_exp(m) : 0;
+          unsigned m = max(max(__float_as_uint(acc[p][0]) & 0x7fffffffu,
+                               __float_as_uint(acc[p][1]) & 0x7fffffffu),
+                           max(__float_as_uint(acc[p][2]) & 0x7fffffffu,
+                               __float_as_uint(acc[p][3]) & 0x7fffffffu));
+          m = umax_xor_1_2_16(m);
+          const int e = scale_exp(m);
           const float sc = pow2f(-e);
           expo[p] += e;
 #pragma unroll
@@ -394,8 +408,15 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
     QK_LDS_FENCE();
   };
 
+  // Drain the previous tile's output stores first: with stores and loads
+  // both outstanding the vector memory counter no longer counts in order, and
+  // every operand use in the loop would wait for all loads. Then B before A,
+  // as inside the loop, so that each use waits only for its own loads.
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt / lgkmcnt untouched
   fetch_b(0, cur);
+  __builtin_amdgcn_sched_barrier(0);
   fetch_a(0, cur);
+  __builtin_amdgcn_sched_barrier(0);
   for (int k = 0; k < nq; ++k) site_step(k);
 
   // ---- epilogue: pair (p, q) = (pi >> 2, pi & 3), four lanes per pair
@@ -461,8 +482,7 @@ __global__ __launch_bounds__(kThreads) void sweep_mfma_kernel(QkTaskTable tt, ui
     const QkTask& t = tt.t[k];
     int ti, tj;
     tile_coords(t, q - t.tile_begin, ti, tj);
-    if (t.T == 4) run_tile<F, true>(t, ti, tj, sm, flags, q, ln_tau);
-    else run_tile<F, false>(t, ti, tj, sm, flags, q, ln_tau);
+    run_tile<F>(t, ti, tj, sm, flags, q, ln_tau);
     __syncthreads();
   }
 }
