@@ -15,13 +15,21 @@
 //     the MFMA peak at chi = 4).
 //
 // A wavefront owns a 4 x 4 block of pairs and runs its whole chain of sites
-// without workgroup barriers: every lane loads its own operand values of the
-// next site (prefetched one site ahead; the 16 waves of a workgroup share the
-// 16 row and 16 column samples of a 16 x 16 tile, so the loads hit the CU's
-// L1/L2), and the two re-layouts between the steps (MFMA output -> operand of
-// the other step) go through a per-wave LDS area. Each
-// pair's E is scaled by an exact power of two every fourth site (per-pair
-// int32 exponent); the FP32 range leaves ample room for four sites of decay.
+// without workgroup barriers. Every lane loads its own operand values of the
+// next site with buffer loads (prefetched one site ahead, straight into the
+// operand registers; the 16 waves of a workgroup share the 16 row and 16
+// column samples of a 16 x 16 tile, so repeats hit the CU's L1). Offsets past
+// a site array's end read as zero in hardware, which pads bond blocks smaller
+// than 4 x 4 and the zero rows of step L without any per-element select. The
+// two re-layouts between the steps (MFMA output -> operand of the other step)
+// go through a per-wave LDS area. Each pair's E is scaled by an exact power
+// of two every kRescaleEvery sites (per-pair int32 exponent).
+//
+// On gfx950 plain VALU instructions do not overlap the FP32 MFMAs of the
+// same SIMD, so the loop keeps per-site VALU work small: the realified
+// operand forms are two selects per complex value, addresses come from a
+// per-site buffer descriptor (scalar) plus constant per-lane offsets, and the
+// rescale reduces integer bit patterns.
 //
 // Forms: FP32 operands on v_mfma_f32_16x16x4f32; or split BF16 on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation -- BF16x2: x = h + l with
@@ -46,7 +54,14 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 enum Form { kF32 = 0, kBF16x2 = 1, kBF16x3 = 2 };
 
-constexpr int kWaves = 16;
+// A wave owns kColBlocks 4 x 4 pair blocks side by side (same four rows):
+// the row operands and their forms are loaded and built once for all of them.
+// Two blocks per wave halve the row operand work but need more than 128
+// registers, i.e. two waves per SIMD instead of four; one block per wave
+// measured faster on the 784-qubit image workload.
+constexpr int kColBlocks = 1;
+constexpr int kWavesPerRow = 4 / kColBlocks;
+constexpr int kWaves = 16 / kColBlocks;  // waves per 16 x 16 pair tile
 constexpr int kThreads = 64 * kWaves;
 constexpr int kTile = 16;
 // Per-wave LDS areas (floats). Strides are chosen so that the accesses of
@@ -58,12 +73,17 @@ constexpr int kTile = 16;
 //     written b32 by lanes (c, (q,b)), read b64 by lanes (b, (p,a)).
 constexpr int kGp = 336, kGq = 80, kGa = 16;
 constexpr int kEq = 136, kEp = 34;
-constexpr int kRescaleEvery = 4;  // sites between exact rescales
+// Sites between exact rescales. The transfer map of two normalised
+// left-canonical MPS is a contraction, so E never overflows; between two
+// rescales its largest entry (in [1/2, 1) after a rescale) must not fall
+// below the FP32 normal range, i.e. shrink by 2^126 within this many sites,
+// which only pairs whose overlap is already negligible can do.
+constexpr int kRescaleEvery = 8;
 
 struct MfmaSmem {
-  float g[kWaves][4 * kGp];
-  float e[kWaves][4 * kEq];
-  int ex[kWaves][16];
+  float g[16][4 * kGp];  // per 4 x 4 pair block
+  float e[16][4 * kEq];
+  int ex[16][16];
   unsigned mask[kQkMaskWords];
 };
 
@@ -251,16 +271,24 @@ __device__ inline void tile_coords(const QkTask& t, int64_t lt, int& ti, int& tj
 template <int F>
 __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t* mask,
                          int64_t tile_id, double ln_tau) {
+  constexpr int NB = kColBlocks;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index: scalar
   const int lane = tid & 63;
   const int g = lane >> 4, n = lane & 15;
-  const int wr = w >> 2, wc = w & 3;
-  const int64_t i0 = (int64_t)ti * kTile + 4 * wr, j0 = (int64_t)tj * kTile + 4 * wc;
+  const int wr = w / kWavesPerRow, wc0 = (w % kWavesPerRow) * NB;
+  const int64_t i0 = (int64_t)ti * kTile + 4 * wr;
+  int64_t j0[NB];
+  float* gb[NB];
+  float* eb[NB];
+#pragma unroll
+  for (int x = 0; x < NB; ++x) {
+    j0[x] = (int64_t)tj * kTile + 4 * (wc0 + x);
+    gb[x] = sm.g[wr * 4 + wc0 + x];
+    eb[x] = sm.e[wr * 4 + wc0 + x];
+  }
   const int T = t.T, TT = T * T, slotT = 2 * TT;
   const int nq = t.nq;
-  float* gb = sm.g[w];
-  float* eb = sm.e[w];
 
   // ---- per-lane byte offsets into a site's packed sample array (constant
   // over the sites). Samples past the end are clamped to the last one: those
@@ -275,12 +303,15 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
   const unsigned abytes = (unsigned)((int64_t)t.na * slotT * 8);
   const bool bin = g < T && rbp < T;
   const bool ain = g < T && lap < T && n < 8;
-  unsigned boff[4], aoff[4];
+  unsigned boff[NB][4], aoff[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int64_t j = (j0 + q) < t.nb ? (j0 + q) : (t.nb - 1);
+#pragma unroll
+    for (int x = 0; x < NB; ++x) {
+      const int64_t j = (j0[x] + q) < t.nb ? (j0[x] + q) : (t.nb - 1);
+      boff[x][q] = bin ? (unsigned)((j * slotT + rs * TT + g * T + rbp) * 8) : bbytes;
+    }
     const int64_t i = (i0 + q) < t.na ? (i0 + q) : (t.na - 1);
-    boff[q] = bin ? (unsigned)((j * slotT + rs * TT + g * T + rbp) * 8) : bbytes;
     aoff[q] = ain ? (unsigned)((i * slotT + g * T + lap) * 8) : abytes;
   }
   const unsigned a1off = (unsigned)(TT * 8);
@@ -289,7 +320,7 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
   const int64_t bstride = bbytes, astride = abytes;
 
   struct Ops {
-    float2 b[4];
+    float2 b[NB][4];
     float2 a[4][2];
   };
   // the loads land straight in the operand registers and stay in flight
@@ -297,7 +328,9 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
   auto fetch_b = [&](int k, Ops& o) {
     const __amdgpu_buffer_rsrc_t r = site_rsrc(bbase + (int64_t)k * bstride, bbytes);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) o.b[q] = ld2(r, boff[q]);
+    for (int x = 0; x < NB; ++x)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o.b[x][q] = ld2(r, boff[x][q]);
   };
   auto fetch_a = [&](int k, Ops& o) {
     const __amdgpu_buffer_rsrc_t r = site_rsrc(abase + (int64_t)k * astride, abytes);
@@ -309,13 +342,16 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
   };
 
   // E in step-R operand form: lane (p = n>>2, a = n&3, b = g) holds Re/Im E[a][b]
-  float eR[4][2];
+  float eR[NB][4][2];
+  int expo[NB][4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    eR[q][0] = ((n & 3) == 0 && g == 0) ? 1.f : 0.f;
-    eR[q][1] = 0.f;
-  }
-  int expo[4] = {0, 0, 0, 0};
+  for (int x = 0; x < NB; ++x)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      eR[x][q][0] = ((n & 3) == 0 && g == 0) ? 1.f : 0.f;
+      eR[x][q][1] = 0.f;
+      expo[x][q] = 0;
+    }
 
   // one site; each operand set is refetched for the next site right after
   // its last use
@@ -323,87 +359,106 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
   auto site_step = [&](int k) {
     const bool more = k + 1 < nq;
     const int kn = more ? k + 1 : k;
-    // ---- step R: G = E Bhat_j for the wave's four columns (four independent
-    // chains, issued chunk-major)
+    // ---- step R: G = E Bhat_j for each block's four columns (four
+    // independent chains per block, issued chunk-major)
     {
-      float bop[4][2];
+      f4 acc[NB][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        bop[q][0] = rcout ? cur.b[q].y : cur.b[q].x;
-        bop[q][1] = rcout ? cur.b[q].x : -cur.b[q].y;
+      for (int x = 0; x < NB; ++x) {
+        float bop[4][2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          bop[q][0] = rcout ? cur.b[x][q].y : cur.b[x][q].x;
+          bop[q][1] = rcout ? cur.b[x][q].x : -cur.b[x][q].y;
+          acc[x][q] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+        mma4<F, 2>(eR[x], bop, acc[x]);
       }
-      fetch_b(kn, cur);  // in flight during step L
-      f4 acc[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-      mma4<F, 2>(eR, bop, acc);
+      fetch_b(kn, cur);  // in flight until the next step R
       // lane holds G[(p=g, a=r)][(s, cout, b')] of pair (g, q)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        float* gw = &gb[g * kGp + q * kGq + rbp * 4 + (rs * 2 + rcout)];
+      for (int x = 0; x < NB; ++x)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) gw[r * kGa] = acc[q][r];
-      }
+        for (int q = 0; q < 4; ++q) {
+          float* gw = &gb[x][g * kGp + q * kGq + rbp * 4 + (rs * 2 + rcout)];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) gw[r * kGa] = acc[x][q][r];
+        }
     }
     QK_LDS_FENCE();
     // keep the step-L operand work (which waits for the A loads) below this
     // point, so step R waits only for the B loads issued one site earlier
     __builtin_amdgcn_sched_barrier(0);
-    // ---- step L: E' = Ahat_i^dagger G for the wave's four rows, then the
-    // exact power-of-two rescale every few sites (pair (p, q) lives on lanes
-    // g in {0,1}, n>>2 == q: 4 lanes b' x 4 registers), then E' to LDS
+    // ---- step L: E' = Ahat_i^dagger G for the wave's four rows (the row
+    // operand built once for all blocks), then the exact power-of-two rescale
+    // every few sites (pair (p, q) lives on lanes g in {0,1}, n>>2 == q: 4
+    // lanes b' x 4 registers), then E' to LDS
     {
       const int q = n >> 2, bp = n & 3;  // output column (q, b')
-      float bop[4][4], aop[4][4];
+      float aop[4][4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const f4 gv = *reinterpret_cast<const f4*>(&gb[p * kGp + q * kGq + g * kGa + bp * 4]);
-        bop[p][0] = gv[0];
-        bop[p][1] = gv[1];
-        bop[p][2] = gv[2];
-        bop[p][3] = gv[3];
         const float2 a0 = cur.a[p][0], a1 = cur.a[p][1];  // zero on rows n >= 8
         aop[p][0] = lcp == 0 ? a0.x : -a0.y;  // s = 0, c_in = 0
         aop[p][1] = lcp == 0 ? a0.y : a0.x;   // s = 0, c_in = 1
         aop[p][2] = lcp == 0 ? a1.x : -a1.y;  // s = 1, c_in = 0
         aop[p][3] = lcp == 0 ? a1.y : a1.x;   // s = 1, c_in = 1
       }
-      fetch_a(kn, cur);  // in flight until the next step L
-      f4 acc[4];
+      f4 acc[NB][4];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) acc[p] = f4{0.f, 0.f, 0.f, 0.f};
-      mma4<F, 4>(aop, bop, acc);
-      if ((k % kRescaleEvery) == kRescaleEvery - 1 || !more) {
+      for (int x = 0; x < NB; ++x) {
+        float bop[4][4];
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-          unsigned m = max(max(__float_as_uint(acc[p][0]) & 0x7fffffffu,
-                               __float_as_uint(acc[p][1]) & 0x7fffffffu),
-                           max(__float_as_uint(acc[p][2]) & 0x7fffffffu,
-                               __float_as_uint(acc[p][3]) & 0x7fffffffu));
-          m = umax_xor_1_2_16(m);
-          const int e = scale_exp(m);
-          const float sc = pow2f(-e);
-          expo[p] += e;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[p][r] *= sc;
+          const f4 gv = *reinterpret_cast<const f4*>(&gb[x][p * kGp + q * kGq + g * kGa + bp * 4]);
+          bop[p][0] = gv[0];
+          bop[p][1] = gv[1];
+          bop[p][2] = gv[2];
+          bop[p][3] = gv[3];
+          acc[x][p] = f4{0.f, 0.f, 0.f, 0.f};
         }
+        mma4<F, 4>(aop, bop, acc[x]);
       }
-      if (g < 2) {
+      fetch_a(kn, cur);  // in flight until the next step L
+      const bool rescale = (k % kRescaleEvery) == kRescaleEvery - 1 || !more;
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
+      for (int x = 0; x < NB; ++x) {
+        if (rescale) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) eb[q * kEq + p * kEp + r * 8 + bp * 2 + g] = acc[p][r];
+          for (int p = 0; p < 4; ++p) {
+            unsigned m = max(max(__float_as_uint(acc[x][p][0]) & 0x7fffffffu,
+                                 __float_as_uint(acc[x][p][1]) & 0x7fffffffu),
+                             max(__float_as_uint(acc[x][p][2]) & 0x7fffffffu,
+                                 __float_as_uint(acc[x][p][3]) & 0x7fffffffu));
+            m = umax_xor_1_2_16(m);
+            const int e = scale_exp(m);
+            const float sc = pow2f(-e);
+            expo[x][p] += e;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[x][p][r] *= sc;
+          }
+        }
+        if (g < 2) {
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              eb[x][q * kEq + p * kEp + r * 8 + bp * 2 + g] = acc[x][p][r];
+        }
       }
     }
     QK_LDS_FENCE();
     {
       const int p = n >> 2, a = n & 3;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float2 ev = *reinterpret_cast<const float2*>(&eb[q * kEq + p * kEp + a * 8 + g * 2]);
-        eR[q][0] = ev.x;
-        eR[q][1] = ev.y;
-      }
+      for (int x = 0; x < NB; ++x)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float2 ev =
+              *reinterpret_cast<const float2*>(&eb[x][q * kEq + p * kEp + a * 8 + g * 2]);
+          eR[x][q][0] = ev.x;
+          eR[x][q][1] = ev.y;
+        }
     }
     QK_LDS_FENCE();
   };
@@ -419,51 +474,60 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
   __builtin_amdgcn_sched_barrier(0);
   for (int k = 0; k < nq; ++k) site_step(k);
 
-  // ---- epilogue: pair (p, q) = (pi >> 2, pi & 3), four lanes per pair
+  // ---- epilogue: pair (p, q) = (pi >> 2, pi & 3) of each block, four lanes
+  // per pair
   if (g == 0 && (n & 3) == 0) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) sm.ex[w][p * 4 + (n >> 2)] = expo[p];
+    for (int x = 0; x < NB; ++x)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) sm.ex[wr * 4 + wc0 + x][p * 4 + (n >> 2)] = expo[x][p];
   }
   if (tid < kQkMaskWords) sm.mask[tid] = 0;
   __syncthreads();
   const int pi = lane & 15, part = lane >> 4;
   const int p = pi >> 2, q = pi & 3;
-  const int64_t i = i0 + p, j = j0 + q;
-  const bool valid = i < t.na && j < t.nb && (!t.symmetric || j >= i);
-  const float2 av = *reinterpret_cast<const float2*>(&eb[q * kEq + p * kEp]);
-  const double re = (double)av.x, im = (double)av.y;
-  const double mag2 = re * re + im * im;
-  const double lnk = mag2 > 0.0 ? log(mag2) + 2.0 * (double)sm.ex[w][pi] * 0.69314718055994530942
-                                : -INFINITY;
-  const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
-  double d2 = 0.0;
-  if (t.fuse && valid) {
-    const double* xr = t.xr + i * t.ld_xr;
-    const double* xc = t.xc + j * t.ld_xc;
-    for (int f = part; f < nq; f += 4) {
-      const double df = xr[f] - xc[f];
-      d2 += df * df;
+  const int64_t i = i0 + p;
+#pragma unroll
+  for (int x = 0; x < NB; ++x) {
+    const int64_t j = j0[x] + q;
+    const bool valid = i < t.na && j < t.nb && (!t.symmetric || j >= i);
+    const float2 av = *reinterpret_cast<const float2*>(&eb[x][q * kEq + p * kEp]);
+    const double re = (double)av.x, im = (double)av.y;
+    const double mag2 = re * re + im * im;
+    const double lnk =
+        mag2 > 0.0
+            ? log(mag2) + 2.0 * (double)sm.ex[wr * 4 + wc0 + x][pi] * 0.69314718055994530942
+            : -INFINITY;
+    const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
+    double d2 = 0.0;
+    if (t.fuse && valid) {
+      const double* xr = t.xr + i * t.ld_xr;
+      const double* xc = t.xc + j * t.ld_xc;
+      for (int f = part; f < nq; f += 4) {
+        const double df = xr[f] - xc[f];
+        d2 += df * df;
+      }
     }
-  }
-  d2 += __shfl_xor(d2, 16, 64);
-  d2 += __shfl_xor(d2, 32, 64);
-  if (valid && part == 0) {
-    auto put = [&](double* ptr, int64_t ld, double v) {
-      if (!ptr) return;
-      ptr[i * ld + j] = v;
-      if (t.symmetric && j != i) ptr[j * ld + i] = v;
-    };
-    put(t.kq, t.ld_kq, kq);
-    put(t.lnkq, t.ld_ln, lnk);
-    if (t.fuse) {
-      const double kc = exp(-t.gamma * d2);
-      const double w = t.w_rows ? t.w_rows[i] : t.w;
-      put(t.kc, t.ld_kc, kc);
-      put(t.k, t.ld_k, w * kq + (1.0 - w) * kc);
-    }
-    if (mask && lnk > ln_tau) {
-      const int bit = (int)(i - (int64_t)ti * kTile) * kTile + (int)(j - (int64_t)tj * kTile);
-      atomicOr(&sm.mask[bit >> 5], 1u << (bit & 31));
+    d2 += __shfl_xor(d2, 16, 64);
+    d2 += __shfl_xor(d2, 32, 64);
+    if (valid && part == 0) {
+      auto put = [&](double* ptr, int64_t ld, double v) {
+        if (!ptr) return;
+        ptr[i * ld + j] = v;
+        if (t.symmetric && j != i) ptr[j * ld + i] = v;
+      };
+      put(t.kq, t.ld_kq, kq);
+      put(t.lnkq, t.ld_ln, lnk);
+      if (t.fuse) {
+        const double kc = exp(-t.gamma * d2);
+        const double wgt = t.w_rows ? t.w_rows[i] : t.w;
+        put(t.kc, t.ld_kc, kc);
+        put(t.k, t.ld_k, wgt * kq + (1.0 - wgt) * kc);
+      }
+      if (mask && lnk > ln_tau) {
+        const int bit = (int)(i - (int64_t)ti * kTile) * kTile + (int)(j - (int64_t)tj * kTile);
+        atomicOr(&sm.mask[bit >> 5], 1u << (bit & 31));
+      }
     }
   }
   __syncthreads();
