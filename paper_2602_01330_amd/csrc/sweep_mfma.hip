@@ -80,12 +80,19 @@ constexpr int kEq = 136, kEp = 34;
 // which only pairs whose overlap is already negligible can do.
 constexpr int kRescaleEvery = 8;
 
+// Feature rows staged for the fused RBF distances after the sweep, over the
+// (then idle) G areas: 32 samples x kXChunk doubles, padded rows.
+constexpr int kXChunk = 256;
+constexpr int kXStride = kXChunk + 2;
+
 struct MfmaSmem {
-  float g[16][4 * kGp];  // per 4 x 4 pair block
+  alignas(16) float g[16][4 * kGp];  // per 4 x 4 pair block
   float e[16][4 * kEq];
   int ex[16][16];
   unsigned mask[kQkMaskWords];
 };
+static_assert(32 * kXStride * sizeof(double) <= sizeof(float) * 16 * 4 * kGp,
+              "feature staging fits in the G areas");
 
 // max over lanes l ^ 1 and l ^ 2 (DPP quad permutations) and l ^ 16
 // (swizzle) of the bit patterns of non-negative floats, whose unsigned order
@@ -483,33 +490,70 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
       for (int p = 0; p < 4; ++p) sm.ex[wr * 4 + wc0 + x][p * 4 + (n >> 2)] = expo[x][p];
   }
   if (tid < kQkMaskWords) sm.mask[tid] = 0;
-  __syncthreads();
   const int pi = lane & 15, part = lane >> 4;
   const int p = pi >> 2, q = pi & 3;
   const int64_t i = i0 + p;
+  // final E[0][0] and exponent of each pair to registers (the wave's own LDS
+  // areas), then every wave is done with the G areas
+  float2 efin[NB];
+  int xfin[NB];
+#pragma unroll
+  for (int x = 0; x < NB; ++x) {
+    efin[x] = *reinterpret_cast<const float2*>(&eb[x][q * kEq + p * kEp]);
+    xfin[x] = sm.ex[wr * 4 + wc0 + x][pi];
+  }
+  __syncthreads();
+  // fused RBF: squared distances by direct difference, the tile's 16 row and
+  // 16 column feature vectors staged through LDS in chunks (each feature
+  // element is read from memory once per tile); lane `part` of a pair sums
+  // the features f = part mod 4 of each chunk
+  double d2[NB];
+#pragma unroll
+  for (int x = 0; x < NB; ++x) d2[x] = 0.0;
+  if (t.fuse) {
+    double* xs = reinterpret_cast<double*>(&sm.g[0][0]);
+    const int64_t ti0 = (int64_t)ti * kTile, tj0 = (int64_t)tj * kTile;
+    for (int f0 = 0; f0 < nq; f0 += kXChunk) {
+      const int nf = min(kXChunk, nq - f0);
+      for (int e = tid; e < 32 * nf; e += kThreads) {
+        const int smp = e / nf, f = e - smp * nf;
+        double v = 0.0;
+        if (smp < 16) {
+          const int64_t r = ti0 + smp;
+          if (r < t.na) v = t.xr[r * t.ld_xr + f0 + f];
+        } else {
+          const int64_t c = tj0 + smp - 16;
+          if (c < t.nb) v = t.xc[c * t.ld_xc + f0 + f];
+        }
+        xs[smp * kXStride + f] = v;
+      }
+      __syncthreads();
+      const double* xrow = xs + (4 * wr + p) * kXStride;
+#pragma unroll
+      for (int x = 0; x < NB; ++x) {
+        const double* xcol = xs + (16 + 4 * (wc0 + x) + q) * kXStride;
+        double acc = 0.0;
+        for (int f = part; f < nf; f += 4) {
+          const double df = xrow[f] - xcol[f];
+          acc += df * df;
+        }
+        d2[x] += acc;
+      }
+      __syncthreads();
+    }
+  }
 #pragma unroll
   for (int x = 0; x < NB; ++x) {
     const int64_t j = j0[x] + q;
     const bool valid = i < t.na && j < t.nb && (!t.symmetric || j >= i);
-    const float2 av = *reinterpret_cast<const float2*>(&eb[x][q * kEq + p * kEp]);
-    const double re = (double)av.x, im = (double)av.y;
+    const double re = (double)efin[x].x, im = (double)efin[x].y;
     const double mag2 = re * re + im * im;
     const double lnk =
-        mag2 > 0.0
-            ? log(mag2) + 2.0 * (double)sm.ex[wr * 4 + wc0 + x][pi] * 0.69314718055994530942
-            : -INFINITY;
+        mag2 > 0.0 ? log(mag2) + 2.0 * (double)xfin[x] * 0.69314718055994530942 : -INFINITY;
     const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
-    double d2 = 0.0;
-    if (t.fuse && valid) {
-      const double* xr = t.xr + i * t.ld_xr;
-      const double* xc = t.xc + j * t.ld_xc;
-      for (int f = part; f < nq; f += 4) {
-        const double df = xr[f] - xc[f];
-        d2 += df * df;
-      }
-    }
-    d2 += __shfl_xor(d2, 16, 64);
-    d2 += __shfl_xor(d2, 32, 64);
+    double d2x = d2[x];
+    d2x += __shfl_xor(d2x, 16, 64);
+    d2x += __shfl_xor(d2x, 32, 64);
     if (valid && part == 0) {
       auto put = [&](double* ptr, int64_t ld, double v) {
         if (!ptr) return;
@@ -519,7 +563,7 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
       put(t.kq, t.ld_kq, kq);
       put(t.lnkq, t.ld_ln, lnk);
       if (t.fuse) {
-        const double kc = exp(-t.gamma * d2);
+        const double kc = exp(-t.gamma * d2x);
         const double wgt = t.w_rows ? t.w_rows[i] : t.w;
         put(t.kc, t.ld_kc, kc);
         put(t.k, t.ld_k, wgt * kq + (1.0 - wgt) * kc);
