@@ -52,10 +52,13 @@ __device__ bool jacobi_columns(double2* X, double2* V, int R, int C, double floo
   // the wave can give every pair
   int cap = 64 / npairs;
   cap = cap >= 32 ? 32 : (cap >= 16 ? 16 : (cap >= 8 ? 8 : (cap >= 4 ? 4 : (cap >= 2 ? 2 : 1))));
-  int g = 1;
-  while (g < R && g < cap) g <<= 1;
-  const int pair = lane / g;
-  const int sub = lane % g;
+  int g = 1, lg = 0;
+  while (g < R && g < cap) {
+    g <<= 1;
+    ++lg;
+  }
+  const int pair = lane >> lg;
+  const int sub = lane & (g - 1);
   const bool active = pair < npairs;
   const int players = C - 1;
   const double tol = 1e-14;
@@ -65,12 +68,17 @@ __device__ bool jacobi_columns(double2* X, double2* V, int R, int C, double floo
     for (int r = 0; r < players; ++r) {
       int p = 0, q = 0;
       if (active) {
+        // round-robin tournament: r, pair < players, so one conditional
+        // subtraction reduces each index
         if (pair == 0) {
           p = 0;
-          q = 1 + (r % players);
+          q = 1 + r;
         } else {
-          p = 1 + (r + pair) % players;
-          q = 1 + (r - pair + players) % players;
+          int u = r + pair, v = r - pair + players;
+          if (u >= players) u -= players;
+          if (v >= players) v -= players;
+          p = 1 + u;
+          q = 1 + v;
         }
       }
       double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
@@ -90,16 +98,17 @@ __device__ bool jacobi_columns(double2* X, double2* V, int R, int C, double floo
         gr += __shfl_xor(gr, off, 64);
         gi += __shfl_xor(gi, off, 64);
       }
-      const double gabs = sqrt(gr * gr + gi * gi);
+      const double gabs2 = gr * gr + gi * gi;
       const bool do_rot =
-          active && al > floor2 && be > floor2 && gabs > tol * sqrt(al * be);
+          active && al > floor2 && be > floor2 && gabs2 > tol * tol * (al * be);
       if (do_rot) {
-        const double zeta = (be - al) / (2.0 * gabs);
+        const double inv_gabs = rsqrt(gabs2);
+        const double zeta = 0.5 * (be - al) * inv_gabs;
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t);
+        const double c = rsqrt(1.0 + t * t);
         const double s = c * t;
         // e^{-i phi} = conj(gamma) / |gamma|
-        const double2 ph = make_double2(gr / gabs, -gi / gabs);
+        const double2 ph = make_double2(gr * inv_gabs, -gi * inv_gabs);
         for (int row = sub; row < R; row += g) {
           double2 xp = X[p * LD + row];
           double2 xq = cmul(ph, X[q * LD + row]);
@@ -136,14 +145,15 @@ struct BuildSmem {
 template <int W>
 __global__ __launch_bounds__(64) void mps_build_kernel(
     const double* __restrict__ x, int64_t ld_x, int64_t N, int nq, int n_layers,
-    int chi_max, int entangle, double cutoff, int T, double2* __restrict__ t64,
+    int chi_max, int entangle, double cutoff, double2* __restrict__ t64,
     int32_t* __restrict__ chi_tab, int32_t* __restrict__ status) {
   constexpr int D = 2 * W;
   __shared__ BuildSmem<W> sm;
   const int64_t i = blockIdx.x;
   const int lane = threadIdx.x;
-  const int TT = T * T;
-  const int slot = 2 * TT;
+  // the packed bond block is W x W (W is the batch's padded bond dimension),
+  // so every layout index below is a compile-time shift or mask
+  constexpr int T = W, TT = W * W, slot = 2 * TT;
   const double* xi = x + i * ld_x;
   int32_t* chi = chi_tab + i * (int64_t)(nq + 1);
   auto site = [&](int k) -> double2* { return t64 + ((int64_t)k * N + i) * slot; };
@@ -198,9 +208,14 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
       double sh, ch;
       sincos(0.5 * theta, &sh, &ch);
       double fro = 0.0;
-      for (int e = lane; e < R * C; e += 64) {
-        int row = e % R, col = e / R;
-        int s = row / cl, a = row % cl, t = col / cr, c = col % cr;
+      // lanes walk the padded (s, a) x (t, c) index space (compile-time
+      // strides) and skip the padding, placing each entry at its compact
+      // position row = s * cl + a, col = t * cr + c
+      for (int e = lane; e < 4 * W * W; e += 64) {
+        const int rp = e % (2 * W), cp = e / (2 * W);
+        const int s = rp / W, a = rp % W, t = cp / W, c = cp % W;
+        if (a >= cl || c >= cr) continue;
+        const int row = s * cl + a, col = t * cr + c;
         double2 acc = make_double2(0, 0);
         for (int b = 0; b < cm; ++b)
           acc = cadd(acc, cmul(sm.sa[s * W * W + a * W + b], sm.sb[t * W * W + b * W + c]));
@@ -325,7 +340,7 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
 #define QK_BUILD_CASE(WV)                                                     \
   case WV:                                                                    \
     hipLaunchKernelGGL(mps_build_kernel<WV>, grid, block, 0, s, x, ld_x, n,   \
-                       nq, n_layers, chi_max, entangle, cutoff, T, t64, chi,  \
+                       nq, n_layers, chi_max, entangle, cutoff, t64, chi,     \
                        status);                                               \
     break;
   switch (T) {
