@@ -264,6 +264,18 @@ QK_API qk_status qk_autotune(const qk_mps_batch* rows, const qk_mps_batch* cols,
 QK_API qk_status qk_tune_export(char* buf, int64_t cap, int64_t* len);
 QK_API qk_status qk_tune_import(const char* text);
 
+/*
+ * Launch timing for measurement. qk_set_launch_timing(1) makes every later
+ * qk_overlap_gram / qk_overlap_gram_multi call record HIP events on its
+ * stream around its sweep launch and around its FP64 refinement pass;
+ * qk_last_launch_ms waits for the most recent such call's last event and
+ * writes the two elapsed times in milliseconds (refine_ms = 0 when no
+ * refinement ran). Process-wide, for one caller at a time; returns
+ * QK_ERR_INVALID_ARG when timing is off or no timed call has been made.
+ */
+QK_API qk_status qk_set_launch_timing(int32_t enable);
+QK_API qk_status qk_last_launch_ms(float* sweep_ms, float* refine_ms);
+
 /* Resolves QK_PREC_AUTO for a batch pair: writes the form the library
  * would run (from the tuning table, else the built-in default). */
 QK_API qk_status qk_resolve_precision(const qk_mps_batch* rows,

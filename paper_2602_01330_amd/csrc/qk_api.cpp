@@ -221,6 +221,17 @@ double refine_tau(qk_precision p) {
   return (p >= 0 && p < 6) ? g_refine_tau[p] : 0.0;
 }
 
+// Optional launch timing (HIP events on the launch stream).
+struct LaunchTiming {
+  std::mutex mu;
+  bool enabled = false, recorded = false, refined = false;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+} g_timing;
+
+void timing_mark(int which, hipStream_t s) {
+  if (g_timing.enabled) (void)hipEventRecord(g_timing.ev[which], s);
+}
+
 qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, hipStream_t s,
                     int64_t max_tiles = -1) {
   // longest-processing-time order: per-tile cost ~ nq * T^3
@@ -238,14 +249,21 @@ qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, h
   tt.n_tasks = (int32_t)tasks.size();
   if (max_tiles >= 0 && acc > max_tiles) acc = max_tiles;  // autotuning slice
   tt.total_tiles = acc;
+  std::lock_guard<std::mutex> tlk(g_timing.mu);
+  g_timing.recorded = false;  // set once this call's events are all recorded
+  g_timing.refined = false;
   if (acc == 0) return QK_OK;
   // persistent workgroups per CU: from the tuning table, else per form
   QkTuneEntry te;
   const bool tuned = qk_tune_lookup(tasks[0].T, tasks[0].nq, &te) && te.form == prec;
   const int grid64 = (int)std::min<int64_t>(
       acc, (int64_t)device_cus() * (tuned && prec == QK_PREC_FP64 ? te.wg_per_cu : 2));
+  timing_mark(0, s);
   if (prec == QK_PREC_FP64) {
     QK_HIP(qk_launch_sweep_fp64(tt, grid64, nullptr, s), "sweep launch");
+    timing_mark(1, s);
+    timing_mark(2, s);
+    g_timing.recorded = g_timing.enabled;
     return QK_OK;
   }
   // the reduced-precision sweeps address one site's packed sample array with
@@ -269,7 +287,9 @@ qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, h
   } else {
     e = qk_launch_sweep_mfma(tt, prec, device_cus(), flags, ln_tau, s);
   }
+  timing_mark(1, s);
   if (e == hipSuccess && refine) {
+    g_timing.refined = true;
     // FP64 pass over the flagged tiles only, same tile numbering
     QkTaskTable t64 = tt;
     for (int k = 0; k < t64.n_tasks; ++k) {
@@ -278,8 +298,10 @@ qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, h
     }
     e = qk_launch_sweep_fp64(t64, grid64, flags, s);
   }
+  timing_mark(2, s);
   if (refine) (void)hipFreeAsync(flags, s);
   if (e != hipSuccess) return hip_fail(e, "sweep launch");
+  g_timing.recorded = g_timing.enabled;
   return QK_OK;
 }
 
@@ -299,6 +321,30 @@ void qk_mps_release_nosync(qk_mps_batch* b, hipStream_t s) {
 }
 
 extern "C" {
+
+qk_status qk_set_launch_timing(int32_t enable) {
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  if (enable && !g_timing.ev[0]) {
+    for (auto& e : g_timing.ev) QK_HIP(hipEventCreate(&e), "event creation");
+  }
+  g_timing.enabled = enable != 0;
+  g_timing.recorded = false;
+  return QK_OK;
+}
+
+qk_status qk_last_launch_ms(float* sweep_ms, float* refine_ms) {
+  if (!sweep_ms || !refine_ms) return fail(QK_ERR_INVALID_ARG, "null output");
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  if (!g_timing.enabled || !g_timing.recorded)
+    return fail(QK_ERR_INVALID_ARG, "launch timing is off or no timed call was made");
+  QK_HIP(hipEventSynchronize(g_timing.ev[2]), "event wait");
+  float a = 0.f, b = 0.f;
+  QK_HIP(hipEventElapsedTime(&a, g_timing.ev[0], g_timing.ev[1]), "elapsed time");
+  if (g_timing.refined) QK_HIP(hipEventElapsedTime(&b, g_timing.ev[1], g_timing.ev[2]), "elapsed time");
+  *sweep_ms = a;
+  *refine_ms = b;
+  return QK_OK;
+}
 
 const char* qk_status_string(qk_status s) {
   switch (s) {

@@ -82,6 +82,10 @@ _lib.qk_dual_mix.argtypes = [_P, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int64,
                              _P, C.c_int64, _P]
 _lib.qk_resolve_precision.argtypes = [_P, _P, C.POINTER(C.c_int)]
 _lib.qk_set_refine_threshold.argtypes = [C.c_int, C.c_double]
+_lib.qk_set_launch_timing.argtypes = [C.c_int32]
+_lib.qk_last_launch_ms.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float)]
+for _f in ("qk_set_launch_timing", "qk_last_launch_ms"):
+    getattr(_lib, _f).restype = C.c_int
 _lib.qk_autotune.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_int)]
 _lib.qk_tune_export.argtypes = [C.c_char_p, C.c_int64, C.POINTER(C.c_int64)]
 _lib.qk_tune_import.argtypes = [C.c_char_p]
@@ -125,7 +129,7 @@ EXPORTED = ["qk_server_create", "qk_server_load_support", "qk_server_submit",
             "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
             "qk_resolve_precision", "qk_set_refine_threshold", "qk_autotune",
             "qk_tune_export", "qk_tune_import", "qk_status_string",
-            "qk_last_error"]
+            "qk_last_error", "qk_set_launch_timing", "qk_last_launch_ms"]
 
 
 def _check(st):
@@ -310,6 +314,18 @@ def qk_set_refine_threshold(prec, tau: float):
     """FP64 recomputation of tiles holding K_q > tau for a reduced form."""
     p = PREC[prec] if isinstance(prec, str) else int(prec)
     _check(_lib.qk_set_refine_threshold(p, float(tau)))
+
+
+def qk_set_launch_timing(enable: bool):
+    """Record HIP events around the sweep and refinement launches of later calls."""
+    _check(_lib.qk_set_launch_timing(1 if enable else 0))
+
+
+def qk_last_launch_ms():
+    """(sweep_ms, refine_ms) of the most recent timed gram call (waits for it)."""
+    a, b = C.c_float(), C.c_float()
+    _check(_lib.qk_last_launch_ms(C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 def qk_autotune(rows: MpsBatch, cols: MpsBatch, symmetric=False, max_tiles=2048,
