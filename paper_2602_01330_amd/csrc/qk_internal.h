@@ -82,6 +82,54 @@ __device__ inline int64_t qk_tile_of(int64_t round, int wg, int grid) {
   return base + (int64_t)(wg % 8) * (grid / 8) + wg / 8;
 }
 
+// Task-local tile index -> (tile row, tile column). Tiles are enumerated in
+// bands of kQkBand tile rows: within a band column by column, within a column
+// row by row (symmetric tasks: upper triangle incl. the diagonal). A run of
+// 32 consecutive tiles -- what one XCD holds at a time under qk_tile_of --
+// then covers 4 row blocks x 8 column blocks, whose 12 sample blocks the
+// XCD's L2 serves to all 32 workgroups. Shared by every sweep kernel, so a
+// refinement pass finds the tiles its mask words were written for.
+constexpr int kQkBand = 4;
+
+__device__ inline void qk_tile_coords(const QkTask& t, int64_t lt, int& ti, int& tj) {
+  const int64_t nc = t.tiles_c;
+  if (!t.symmetric) {
+    const int64_t nr = t.n_tiles / nc;
+    const int64_t band = lt / (kQkBand * nc);
+    const int64_t l = lt - band * (kQkBand * nc);
+    const int64_t r0 = band * kQkBand;
+    const int64_t h = nr - r0 < kQkBand ? nr - r0 : kQkBand;
+    ti = (int)(r0 + l % h);
+    tj = (int)(l / h);
+    return;
+  }
+  // full bands before band R hold C(R) = 4 n R - 8 R^2 + 2 R tiles
+  const int64_t n = nc;
+  const int64_t nb = (n + kQkBand - 1) / kQkBand;
+  auto before = [&](int64_t r) { return 4 * n * r - 8 * r * r + 2 * r; };
+  const double b = 4.0 * (double)n + 2.0;
+  const double disc = b * b - 32.0 * (double)lt;
+  int64_t R = (int64_t)((b - sqrt(disc > 0.0 ? disc : 0.0)) / 16.0);
+  if (R < 0) R = 0;
+  if (R > nb - 1) R = nb - 1;
+  while (R > 0 && before(R) > lt) --R;
+  while (R + 1 < nb && before(R + 1) <= lt) ++R;
+  const int64_t l = lt - before(R);
+  const int64_t r0 = kQkBand * R;
+  const int64_t h = n - r0 < kQkBand ? n - r0 : kQkBand;
+  const int64_t part = h * (h - 1) / 2;  // the band's first h-1 columns are partial
+  if (l < part) {
+    int64_t c = 0;
+    while ((c + 1) * (c + 2) / 2 <= l) ++c;
+    ti = (int)(r0 + (l - c * (c + 1) / 2));
+    tj = (int)(r0 + c);
+  } else {
+    const int64_t l2 = l - part;
+    ti = (int)(r0 + l2 % h);
+    tj = (int)(r0 + h - 1 + l2 / h);
+  }
+}
+
 struct QkTaskTable {
   QkTask t[QK_MAX_TASKS];
   int32_t n_tasks;

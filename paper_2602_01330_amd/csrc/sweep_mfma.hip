@@ -98,19 +98,21 @@ static_assert(32 * kXStride * sizeof(double) <= sizeof(float) * 16 * 4 * kGp,
 // (swizzle) of the bit patterns of non-negative floats, whose unsigned order
 // is their numeric order
 __device__ inline unsigned umax_xor_1_2_16(unsigned m) {
-  m = max(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0xB1, 0xF, 0xF, false));
-  m = max(m, (unsigned)__builtin_amdgcn_mov_dpp((int)m, 0x4E, 0xF, 0xF, false));
+  // old value 0 is the identity of the max, so each permute folds into the
+  // max as a DPP operand
+  m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0xB1, 0xF, 0xF, false));
+  m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0x4E, 0xF, 0xF, false));
   m = max(m, (unsigned)__builtin_amdgcn_ds_swizzle((int)m, 0x401F));
   return m;
 }
 
-// exponent e with |x| < 2^e <= 2|x| for the float with bit pattern m > 0;
-// 0 for m == 0 and for inf / NaN (those are left to reach the output)
-__device__ inline int scale_exp(unsigned m) {
-  const int ex = (int)(m >> 23);
-  return (m == 0u || ex >= 255) ? 0 : ex - 126;
-}
-__device__ inline float pow2f(int e) { return __uint_as_float((unsigned)(e + 127) << 23); }
+// Scale for a pair whose largest |entry| has the bit pattern m: 2^(126 - ex)
+// with ex the biased exponent of m, which brings that entry into [1/2, 1).
+// ex = 0 (zero or subnormal maximum) scales by 2^126, leaving zeros at zero;
+// ex = 255 (inf / NaN) gives a huge negative factor, so non-finite values
+// stay non-finite; ex <= 253 always holds for finite E, whose entries never
+// exceed 1 (the transfer map is a contraction).
+__device__ inline float rescale_factor(unsigned ex) { return __uint_as_float((253u - ex) << 23); }
 
 // Buffer descriptor over one site's packed sample array: loads at byte
 // offsets at or beyond `bytes` return zero, which pads bond blocks smaller
@@ -255,23 +257,6 @@ __device__ inline void mma4(const float (*a)[NC], const float (*b)[NC], f4* acc)
   }
 }
 
-__device__ inline void tile_coords(const QkTask& t, int64_t lt, int& ti, int& tj) {
-  if (!t.symmetric) {
-    ti = (int)(lt / t.tiles_c);
-    tj = (int)(lt % t.tiles_c);
-    return;
-  }
-  const int64_t n = t.tiles_c;
-  double b = 2.0 * n + 1.0;
-  int64_t r = (int64_t)((b - sqrt(b * b - 8.0 * (double)lt)) * 0.5);
-  if (r < 0) r = 0;
-  if (r > n - 1) r = n - 1;
-  auto start = [&](int64_t q) { return q * n - q * (q - 1) / 2; };
-  while (r > 0 && start(r) > lt) --r;
-  while (r + 1 < n && start(r + 1) <= lt) ++r;
-  ti = (int)r;
-  tj = (int)(r + (lt - start(r)));
-}
 
 #define QK_LDS_FENCE() __asm__ volatile("" ::: "memory")
 
@@ -427,20 +412,24 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
         mma4<F, 4>(aop, bop, acc[x]);
       }
       fetch_a(kn, cur);  // in flight until the next step L
-      const bool rescale = (k % kRescaleEvery) == kRescaleEvery - 1 || !more;
+      // waves rescale at staggered sites, so that one wave's reduction chain
+      // overlaps the others' MFMAs (any schedule is exact: the exponent is
+      // tracked per pair)
+      const bool rescale = ((k + w) % kRescaleEvery) == kRescaleEvery - 1;
 #pragma unroll
       for (int x = 0; x < NB; ++x) {
         if (rescale) {
 #pragma unroll
           for (int p = 0; p < 4; ++p) {
-            unsigned m = max(max(__float_as_uint(acc[x][p][0]) & 0x7fffffffu,
-                                 __float_as_uint(acc[x][p][1]) & 0x7fffffffu),
-                             max(__float_as_uint(acc[x][p][2]) & 0x7fffffffu,
-                                 __float_as_uint(acc[x][p][3]) & 0x7fffffffu));
-            m = umax_xor_1_2_16(m);
-            const int e = scale_exp(m);
-            const float sc = pow2f(-e);
-            expo[x][p] += e;
+            // largest |entry| of the lane (NaN-propagating maximum, no
+            // canonicalising), then over the pair's lanes as bit patterns
+            const float lm = __builtin_elementwise_maximum(
+                __builtin_elementwise_maximum(fabsf(acc[x][p][0]), fabsf(acc[x][p][1])),
+                __builtin_elementwise_maximum(fabsf(acc[x][p][2]), fabsf(acc[x][p][3])));
+            const unsigned m = umax_xor_1_2_16(__float_as_uint(lm));
+            const unsigned ex = m >> 23;
+            const float sc = rescale_factor(ex);
+            expo[x][p] += (int)ex - 126;
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[x][p][r] *= sc;
           }
@@ -589,7 +578,7 @@ __global__ __launch_bounds__(kThreads) void sweep_mfma_kernel(QkTaskTable tt, ui
     while (k + 1 < tt.n_tasks && tt.t[k + 1].tile_begin <= q) ++k;
     const QkTask& t = tt.t[k];
     int ti, tj;
-    tile_coords(t, q - t.tile_begin, ti, tj);
+    qk_tile_coords(t, q - t.tile_begin, ti, tj);
     run_tile<F>(t, ti, tj, sm, flags, q, ln_tau);
     __syncthreads();
   }

@@ -47,25 +47,6 @@ __device__ inline float pow2(float, int e) {  // 2^e for -126 <= e <= 127
   return __uint_as_float((unsigned)(e + 127) << 23);
 }
 
-// Maps a task-local tile index to (tile row, tile col).
-__device__ inline void tile_coords(const QkTask& t, int64_t lt, int& ti, int& tj) {
-  if (!t.symmetric) {
-    ti = (int)(lt / t.tiles_c);
-    tj = (int)(lt % t.tiles_c);
-    return;
-  }
-  // upper triangle (tj >= ti) of an n x n tile grid, row-major
-  const int64_t n = t.tiles_c;
-  double b = 2.0 * n + 1.0;
-  int64_t r = (int64_t)((b - sqrt(b * b - 8.0 * (double)lt)) * 0.5);
-  if (r < 0) r = 0;
-  if (r > n - 1) r = n - 1;
-  auto start = [&](int64_t q) { return q * n - q * (q - 1) / 2; };
-  while (r > 0 && start(r) > lt) --r;
-  while (r + 1 < n && start(r + 1) <= lt) ++r;
-  ti = (int)r;
-  tj = (int)(r + (lt - start(r)));
-}
 
 template <typename R, int T>
 struct SweepSmem {
@@ -276,7 +257,7 @@ __global__ __launch_bounds__(kThreads) void sweep_valu_kernel(QkTaskTable tt,
     while (ti_task + 1 < tt.n_tasks && tt.t[ti_task + 1].tile_begin <= q) ++ti_task;
     const QkTask& t = tt.t[ti_task];
     int ti, tj;
-    tile_coords(t, q - t.tile_begin, ti, tj);
+    qk_tile_coords(t, q - t.tile_begin, ti, tj);
     switch (t.T) {
       case 1:
         run_tile<R, 1>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 1>*>(&sm4), tf, mi, ln_tau);
