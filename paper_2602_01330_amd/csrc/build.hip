@@ -319,13 +319,18 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
   if (lane == 0) atomicMax(status + 1, chi_seen);
 }
 
-__global__ void pack32_kernel(const double2* __restrict__ a, float2* __restrict__ b,
+// FP64 complex -> packed FP32 (-Im, Re, Im)
+__global__ void pack32_kernel(const double2* __restrict__ a, float* __restrict__ b,
                               int64_t count) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < count; i += stride) {
-    double2 v = a[i];
-    b[i] = make_float2((float)v.x, (float)v.y);
+    const double2 v = a[i];
+    const float re = (float)v.x, im = (float)v.y;
+    float* o = b + i * kQkPackFloats;
+    o[0] = -im;
+    o[1] = re;
+    o[2] = im;
   }
 }
 
@@ -356,7 +361,7 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
   return hipGetLastError();
 }
 
-hipError_t qk_launch_pack32(const double2* t64, float2* t32, int64_t count,
+hipError_t qk_launch_pack32(const double2* t64, float* t32, int64_t count,
                             hipStream_t s) {
   if (count == 0) return hipSuccess;
   int64_t blocks = (count + 255) / 256;

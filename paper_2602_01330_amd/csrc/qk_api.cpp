@@ -107,7 +107,7 @@ qk_status alloc_batch(const qk_circuit_desc* c, int64_t n, int T, uint32_t store
   if (hipMallocAsync((void**)&b->t64, std::max<int64_t>(elems, 1) * sizeof(double2), s) != hipSuccess)
     return cleanup(QK_ERR_OUT_OF_MEMORY, "device allocation of FP64 site tensors failed");
   if ((store & QK_STORE_FP32) &&
-      hipMallocAsync((void**)&b->t32, std::max<int64_t>(elems, 1) * sizeof(float2), s) != hipSuccess)
+      hipMallocAsync((void**)&b->t32, std::max<int64_t>(elems, 1) * kQkPackFloats * sizeof(float), s) != hipSuccess)
     return cleanup(QK_ERR_OUT_OF_MEMORY, "device allocation of FP32 site tensors failed");
   if (hipMallocAsync((void**)&b->chi, std::max<int64_t>(n * (c->n_qubits + 1), 1) * sizeof(int32_t), s) != hipSuccess)
     return cleanup(QK_ERR_OUT_OF_MEMORY, "device allocation of the bond table failed");
@@ -118,7 +118,7 @@ qk_status alloc_batch(const qk_circuit_desc* c, int64_t n, int T, uint32_t store
   if (hipEventCreateWithFlags(&b->ready, hipEventDisableTiming) != hipSuccess)
     return cleanup(QK_ERR_HIP, "event creation failed");
   b->bytes = elems * (int64_t)sizeof(double2) +
-             ((store & QK_STORE_FP32) ? elems * (int64_t)sizeof(float2) : 0) +
+             ((store & QK_STORE_FP32) ? elems * (int64_t)(kQkPackFloats * sizeof(float)) : 0) +
              n * (c->n_qubits + 1) * (int64_t)sizeof(int32_t);
   *out = b;
   return QK_OK;
@@ -269,7 +269,7 @@ qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, h
   // the reduced-precision sweeps address one site's packed sample array with
   // 32-bit byte offsets
   for (const QkTask& t : tasks) {
-    const int64_t slot_bytes = (int64_t)2 * t.T * t.T * 8;
+    const int64_t slot_bytes = (int64_t)2 * t.T * t.T * kQkPackFloats * 4;
     if (std::max(t.na, t.nb) * slot_bytes > (int64_t)UINT32_MAX)
       return fail(QK_ERR_UNSUPPORTED, "batch too large for a 32-bit packed site array");
   }

@@ -14,6 +14,11 @@ enum : int32_t {
   QK_FLAG_NOCONV = 4       // a Jacobi SVD hit its sweep limit
 };
 
+// Packed FP32 complex element z = x + i y, stored as (-y, x, y): bytes 4..11
+// hold z = (x, y) and bytes 0..7 hold i z = (-y, x), so a matrix-core lane
+// takes either realified operand form with one 8-byte load and no arithmetic.
+constexpr int kQkPackFloats = 3;
+
 struct qk_mps_batch {
   int device = 0;
   int64_t n = 0;          // samples
@@ -22,7 +27,7 @@ struct qk_mps_batch {
   int32_t chi_ws = 1;     // bond bound used by the build
   int32_t T = 1;          // padded bond dimension of the packed tensors
   double2* t64 = nullptr; // [nq][n][2][T][T] complex FP64
-  float2* t32 = nullptr;  // [nq][n][2][T][T] complex FP32
+  float* t32 = nullptr;   // [nq][n][2][T][T] complex FP32, kQkPackFloats floats each
   int32_t* chi = nullptr; // [n][nq+1] realized bond dimensions
   int32_t* status = nullptr;  // [0] flag bits, [1] max realized chi
   hipStream_t stream = nullptr;
@@ -42,7 +47,7 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
                            int n_layers, int chi_max, int entangle,
                            double cutoff, int chi_ws, int T, double2* t64,
                            int32_t* chi, int32_t* status, hipStream_t s);
-hipError_t qk_launch_pack32(const double2* t64, float2* t32, int64_t count,
+hipError_t qk_launch_pack32(const double2* t64, float* t32, int64_t count,
                             hipStream_t s);
 
 // One Gram block of a (possibly multi-task) sweep launch (sweep kernels).

@@ -95,7 +95,7 @@ namespace {
 int64_t request_bytes(const Request& r, const Support& sup) {
   const int64_t T = sup.mps->T, d = r.d, rows = r.n_rows, ns = sup.n;
   const int64_t tiles = ((rows + 15) / 16) * ((ns + 15) / 16);
-  return rows * d * 2 * T * T * (int64_t)(sizeof(double2) + sizeof(float2))  // MPS forms
+  return rows * d * 2 * T * T * (int64_t)(sizeof(double2) + kQkPackFloats * sizeof(float))  // MPS forms
          + rows * (d + 1) * 4                                                 // bond table
          + rows * d * 8 + rows * 8                                            // features, w
          + rows * ns * 8                                                      // K rows

@@ -26,10 +26,13 @@
 // of two every kRescaleEvery sites (per-pair int32 exponent).
 //
 // On gfx950 plain VALU instructions do not overlap the FP32 MFMAs of the
-// same SIMD, so the loop keeps per-site VALU work small: the realified
-// operand forms are two selects per complex value, addresses come from a
-// per-site buffer descriptor (scalar) plus constant per-lane offsets, and the
-// rescale reduces integer bit patterns.
+// same SIMD, so the loop keeps per-site VALU work small. The realified
+// operand forms need no arithmetic: every packed element holds z and i z
+// (one extra float), each lane loads the form its output part needs, and E
+// enters step R as (Im E, Re E) so that the one negated entry of the
+// realified product falls on the i z form. Addresses come from a per-site
+// buffer descriptor (scalar) plus constant per-lane offsets, and the rescale
+// reduces bit patterns with DPP.
 //
 // Forms: FP32 operands on v_mfma_f32_16x16x4f32; or split BF16 on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation -- BF16x2: x = h + l with
@@ -291,8 +294,9 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
   const int rs = n >> 3, rcout = (n >> 2) & 1, rbp = n & 3;
   // step L, row p: A^s[a = g][a' = n&3] for s = 0, 1 (lanes n < 8)
   const int lcp = n >> 2, lap = n & 3;
-  const unsigned bbytes = (unsigned)((int64_t)t.nb * slotT * 8);
-  const unsigned abytes = (unsigned)((int64_t)t.na * slotT * 8);
+  constexpr int kEB = kQkPackFloats * 4;  // bytes per packed complex element
+  const unsigned bbytes = (unsigned)((int64_t)t.nb * slotT * kEB);
+  const unsigned abytes = (unsigned)((int64_t)t.na * slotT * kEB);
   const bool bin = g < T && rbp < T;
   const bool ain = g < T && lap < T && n < 8;
   unsigned boff[NB][4], aoff[4];
@@ -301,12 +305,17 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
 #pragma unroll
     for (int x = 0; x < NB; ++x) {
       const int64_t j = (j0[x] + q) < t.nb ? (j0[x] + q) : (t.nb - 1);
-      boff[x][q] = bin ? (unsigned)((j * slotT + rs * TT + g * T + rbp) * 8) : bbytes;
+      // the lane's operand pair is z = (x, y) (packed bytes 4..11) or
+      // i z = (-y, x) (bytes 0..7): output part c = 0 (Im of G) takes z,
+      // c = 1 (Re of G) takes i z
+      boff[x][q] = bin ? (unsigned)((j * slotT + rs * TT + g * T + rbp) * kEB + (rcout ? 0 : 4))
+                       : bbytes;
     }
     const int64_t i = (i0 + q) < t.na ? (i0 + q) : (t.na - 1);
-    aoff[q] = ain ? (unsigned)((i * slotT + g * T + lap) * 8) : abytes;
+    // rows c' = 0 (Re of E') take z, rows c' = 1 (Im of E') take i z
+    aoff[q] = ain ? (unsigned)((i * slotT + g * T + lap) * kEB + (lcp ? 0 : 4)) : abytes;
   }
-  const unsigned a1off = (unsigned)(TT * 8);
+  const unsigned a1off = (unsigned)(TT * kEB);
   const char* bbase = static_cast<const char*>(t.tb);
   const char* abase = static_cast<const char*>(t.ta);
   const int64_t bstride = bbytes, astride = abytes;
@@ -333,15 +342,18 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
     }
   };
 
-  // E in step-R operand form: lane (p = n>>2, a = n&3, b = g) holds Re/Im E[a][b]
+  // E in step-R operand form: lane (p = n>>2, a = n&3, b = g) holds
+  // (Im E[a][b], Re E[a][b]) as the contraction parts (0, 1). Against the B
+  // forms z = (x, y) and i z = (-y, x) this gives Im(E B) = Im E x + Re E y
+  // and Re(E B) = Re E x - Im E y with no sign work.
   float eR[NB][4][2];
   int expo[NB][4];
 #pragma unroll
   for (int x = 0; x < NB; ++x)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      eR[x][q][0] = ((n & 3) == 0 && g == 0) ? 1.f : 0.f;
-      eR[x][q][1] = 0.f;
+      eR[x][q][0] = 0.f;
+      eR[x][q][1] = ((n & 3) == 0 && g == 0) ? 1.f : 0.f;
       expo[x][q] = 0;
     }
 
@@ -360,19 +372,20 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
         float bop[4][2];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          bop[q][0] = rcout ? cur.b[x][q].y : cur.b[x][q].x;
-          bop[q][1] = rcout ? cur.b[x][q].x : -cur.b[x][q].y;
+          bop[q][0] = cur.b[x][q].x;
+          bop[q][1] = cur.b[x][q].y;
           acc[x][q] = f4{0.f, 0.f, 0.f, 0.f};
         }
         mma4<F, 2>(eR[x], bop, acc[x]);
       }
       fetch_b(kn, cur);  // in flight until the next step R
-      // lane holds G[(p=g, a=r)][(s, cout, b')] of pair (g, q)
+      // lane holds G[(p=g, a=r)][(s, c, b')] of pair (g, q), c = 0 the
+      // imaginary and c = 1 the real part; stored as (s, Re / Im)
 #pragma unroll
       for (int x = 0; x < NB; ++x)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          float* gw = &gb[x][g * kGp + q * kGq + rbp * 4 + (rs * 2 + rcout)];
+          float* gw = &gb[x][g * kGp + q * kGq + rbp * 4 + (rs * 2 + (rcout ^ 1))];
 #pragma unroll
           for (int r = 0; r < 4; ++r) gw[r * kGa] = acc[x][q][r];
         }
@@ -390,11 +403,13 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
       float aop[4][4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const float2 a0 = cur.a[p][0], a1 = cur.a[p][1];  // zero on rows n >= 8
-        aop[p][0] = lcp == 0 ? a0.x : -a0.y;  // s = 0, c_in = 0
-        aop[p][1] = lcp == 0 ? a0.y : a0.x;   // s = 0, c_in = 1
-        aop[p][2] = lcp == 0 ? a1.x : -a1.y;  // s = 1, c_in = 0
-        aop[p][3] = lcp == 0 ? a1.y : a1.x;   // s = 1, c_in = 1
+        // z or i z of A^s[a][a'] (zero on rows n >= 8): against (Re G, Im G)
+        // this gives Re(conj(A) G) on rows c' = 0 and Im(conj(A) G) on c' = 1
+        const float2 a0 = cur.a[p][0], a1 = cur.a[p][1];
+        aop[p][0] = a0.x;  // s = 0, c_in = 0
+        aop[p][1] = a0.y;  // s = 0, c_in = 1
+        aop[p][2] = a1.x;  // s = 1, c_in = 0
+        aop[p][3] = a1.y;  // s = 1, c_in = 1
       }
       f4 acc[NB][4];
 #pragma unroll
@@ -452,8 +467,8 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
         for (int q = 0; q < 4; ++q) {
           const float2 ev =
               *reinterpret_cast<const float2*>(&eb[x][q * kEq + p * kEp + a * 8 + g * 2]);
-          eR[x][q][0] = ev.x;
-          eR[x][q][1] = ev.y;
+          eR[x][q][0] = ev.y;  // Im
+          eR[x][q][1] = ev.x;  // Re
         }
     }
     QK_LDS_FENCE();

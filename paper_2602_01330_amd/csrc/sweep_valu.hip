@@ -33,6 +33,16 @@ struct Cx<float> {
   using V = float2;
 };
 
+// Complex element idx of a site array: FP64 (Re, Im) pairs, or the packed
+// FP32 (-Im, Re, Im) triples whose last two floats are (Re, Im).
+__device__ inline double2 load_c(const double* base, int64_t idx) {
+  return reinterpret_cast<const double2*>(base)[idx];
+}
+__device__ inline float2 load_c(const float* base, int64_t idx) {
+  const float* e = base + idx * kQkPackFloats;
+  return make_float2(e[1], e[2]);
+}
+
 // Exponent e with m = f * 2^e, f in [0.5, 1); m > 0 and normal.
 __device__ inline int frexp_exp(double m) {
   return (int)((__double_as_longlong(m) >> 52) & 0x7ff) - 1022;
@@ -67,8 +77,8 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, SweepSmem<R, T>& sm,
   const int r = tid / kTile, c = tid % kTile;
   const int64_t i0 = (int64_t)ti * kTile, j0 = (int64_t)tj * kTile;
   const int64_t i = i0 + r, j = j0 + c;
-  const C* ta = static_cast<const C*>(t.ta);
-  const C* tb = static_cast<const C*>(t.tb);
+  const R* ta = static_cast<const R*>(t.ta);
+  const R* tb = static_cast<const R*>(t.tb);
   const int nq = t.nq;
 
   // global -> register staging of one site for the whole tile
@@ -86,9 +96,9 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, SweepSmem<R, T>& sm,
         int rem = e % (kTile * kSlot);
         int smp = rem / kSlot;
         if (side == 0) {
-          if (i0 + smp < t.na) v = ta[((int64_t)k * t.na + i0) * kSlot + rem];
+          if (i0 + smp < t.na) v = load_c(ta, ((int64_t)k * t.na + i0) * kSlot + rem);
         } else {
-          if (j0 + smp < t.nb) v = tb[((int64_t)k * t.nb + j0) * kSlot + rem];
+          if (j0 + smp < t.nb) v = load_c(tb, ((int64_t)k * t.nb + j0) * kSlot + rem);
         }
       }
       stage[q] = v;
