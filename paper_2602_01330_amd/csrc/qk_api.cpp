@@ -274,10 +274,18 @@ qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, h
       return fail(QK_ERR_UNSUPPORTED, "batch too large for a 32-bit packed site array");
   }
   const bool refine = tau > 0.0;
+  // refinement scratch: mask words per tile, then the list of marked tiles
+  // and its length
   uint32_t* flags = nullptr;
-  if (refine)
-    QK_HIP(hipMallocAsync((void**)&flags, acc * kQkMaskWords * sizeof(uint32_t), s),
+  int32_t* marked = nullptr;
+  int32_t* n_marked = nullptr;
+  if (refine) {
+    QK_HIP(hipMallocAsync((void**)&flags, (acc * (kQkMaskWords + 1) + 1) * sizeof(uint32_t), s),
            "refinement mask allocation");
+    marked = reinterpret_cast<int32_t*>(flags + acc * kQkMaskWords);
+    n_marked = marked + acc;
+    QK_HIP(qk_launch_zero_i32(n_marked, 1, s), "refinement counter reset");
+  }
   const double ln_tau = refine ? std::log(tau) : 0.0;
   hipError_t e;
   if (prec == QK_PREC_FP32) {
@@ -296,7 +304,7 @@ qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, h
       t64.t[k].ta = t64.t[k].ta64;
       t64.t[k].tb = t64.t[k].tb64;
     }
-    e = qk_launch_sweep_fp64(t64, grid64, flags, s);
+    e = qk_launch_refine_fp64(t64, grid64, flags, marked, n_marked, s);
   }
   timing_mark(2, s);
   if (refine) (void)hipFreeAsync(flags, s);

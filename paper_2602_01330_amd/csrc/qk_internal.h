@@ -149,6 +149,13 @@ struct QkTaskTable {
 constexpr int kQkMaskWords = 8;
 hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, const uint32_t* mask_in,
                                 hipStream_t s);
+// Zero-fill of n int32 words by a kernel (no memset node in captured graphs).
+hipError_t qk_launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
+// FP64 recomputation of exactly the tiles whose mask words mark a pair:
+// lists them in `list` (total_tiles entries; *count must be 0 on entry),
+// then sweeps the listed tiles spread over `grid` workgroups.
+hipError_t qk_launch_refine_fp64(const QkTaskTable& tt, int grid, const uint32_t* mask,
+                                 int32_t* list, int32_t* count, hipStream_t s);
 hipError_t qk_launch_sweep_fp32(const QkTaskTable& tt, int grid, uint32_t* mask_out,
                                 double ln_tau, hipStream_t s);
 int qk_sweep_valu_tile();

@@ -244,6 +244,42 @@ struct MaxT<float> {
   static constexpr int v = 4;
 };
 
+// One 16 x 16 tile of the task table: skipped when a refinement mask marks
+// none of its pairs, else swept (and, for a reduced form, its mask written).
+template <typename R>
+__device__ void sweep_one_tile(const QkTaskTable& tt, int64_t q, const uint32_t* mask_in,
+                               uint32_t* mask_out, double ln_tau, SweepSmem<R, MaxT<R>::v>& sm4,
+                               unsigned* tile_mask) {
+  const uint32_t* mi = mask_in ? mask_in + q * kQkMaskWords : nullptr;
+  if (mi) {  // uniform per workgroup: skip tiles without a marked pair
+    unsigned any = 0;
+    for (int wd = 0; wd < kQkMaskWords; ++wd) any |= mi[wd];
+    if (!any) return;
+  }
+  if (threadIdx.x < kQkMaskWords) tile_mask[threadIdx.x] = 0;
+  __syncthreads();
+  unsigned* tf = mask_out ? tile_mask : nullptr;
+  int ti_task = 0;
+  while (ti_task + 1 < tt.n_tasks && tt.t[ti_task + 1].tile_begin <= q) ++ti_task;
+  const QkTask& t = tt.t[ti_task];
+  int ti, tj;
+  qk_tile_coords(t, q - t.tile_begin, ti, tj);
+  switch (t.T) {
+    case 1:
+      run_tile<R, 1>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 1>*>(&sm4), tf, mi, ln_tau);
+      break;
+    case 2:
+      run_tile<R, 2>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 2>*>(&sm4), tf, mi, ln_tau);
+      break;
+    default:
+      run_tile<R, 4>(t, ti, tj, sm4, tf, mi, ln_tau);
+      break;
+  }
+  __syncthreads();
+  if (mask_out && threadIdx.x < kQkMaskWords)
+    mask_out[q * kQkMaskWords + threadIdx.x] = tile_mask[threadIdx.x];
+}
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void sweep_valu_kernel(QkTaskTable tt,
                                                               const uint32_t* mask_in,
@@ -254,35 +290,31 @@ __global__ __launch_bounds__(kThreads) void sweep_valu_kernel(QkTaskTable tt,
   for (int64_t rnd = 0; rnd * gridDim.x < tt.total_tiles; ++rnd) {
     const int64_t q = qk_tile_of(rnd, blockIdx.x, gridDim.x);
     if (q >= tt.total_tiles) continue;  // last round only; no barrier skipped
-    const uint32_t* mi = mask_in ? mask_in + q * kQkMaskWords : nullptr;
-    if (mi) {  // uniform per workgroup: skip tiles without a marked pair
-      unsigned any = 0;
-      for (int wd = 0; wd < kQkMaskWords; ++wd) any |= mi[wd];
-      if (!any) continue;
-    }
-    if (threadIdx.x < kQkMaskWords) tile_mask[threadIdx.x] = 0;
-    __syncthreads();
-    unsigned* tf = mask_out ? tile_mask : nullptr;
-    int ti_task = 0;
-    while (ti_task + 1 < tt.n_tasks && tt.t[ti_task + 1].tile_begin <= q) ++ti_task;
-    const QkTask& t = tt.t[ti_task];
-    int ti, tj;
-    qk_tile_coords(t, q - t.tile_begin, ti, tj);
-    switch (t.T) {
-      case 1:
-        run_tile<R, 1>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 1>*>(&sm4), tf, mi, ln_tau);
-        break;
-      case 2:
-        run_tile<R, 2>(t, ti, tj, *reinterpret_cast<SweepSmem<R, 2>*>(&sm4), tf, mi, ln_tau);
-        break;
-      default:
-        run_tile<R, 4>(t, ti, tj, sm4, tf, mi, ln_tau);
-        break;
-    }
-    __syncthreads();
-    if (mask_out && threadIdx.x < kQkMaskWords)
-      mask_out[q * kQkMaskWords + threadIdx.x] = tile_mask[threadIdx.x];
+    sweep_one_tile<R>(tt, q, mask_in, mask_out, ln_tau, sm4, tile_mask);
   }
+}
+
+// Refinement: list the tiles holding marked pairs (in any order: each
+// tile's result does not depend on it), so that the FP64 pass spreads them
+// evenly over its workgroups instead of leaving a few workgroups with several.
+__global__ void compact_marked_kernel(const uint32_t* __restrict__ mask, int64_t total_tiles,
+                                      int32_t* __restrict__ list, int32_t* __restrict__ count) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= total_tiles) return;
+  unsigned any = 0;
+  for (int wd = 0; wd < kQkMaskWords; ++wd) any |= mask[q * kQkMaskWords + wd];
+  if (any) list[atomicAdd(count, 1)] = (int32_t)q;
+}
+
+__global__ __launch_bounds__(kThreads) void sweep_refine_kernel(QkTaskTable tt,
+                                                                const uint32_t* mask_in,
+                                                                const int32_t* list,
+                                                                const int32_t* count) {
+  __shared__ SweepSmem<double, MaxT<double>::v> sm4;
+  __shared__ unsigned tile_mask[kQkMaskWords];
+  const int n = *count;
+  for (int x = blockIdx.x; x < n; x += gridDim.x)
+    sweep_one_tile<double>(tt, list[x], mask_in, nullptr, 0.0, sm4, tile_mask);
 }
 
 }  // namespace
@@ -294,6 +326,30 @@ hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, const uint32_t*
   if (tt.total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(sweep_valu_kernel<double>, dim3(grid), dim3(kThreads), 0, s, tt, mask_in,
                      (uint32_t*)nullptr, 0.0);
+  return hipGetLastError();
+}
+
+namespace {
+__global__ void zero_i32_kernel(int32_t* p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+}  // namespace
+
+hipError_t qk_launch_zero_i32(int32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t qk_launch_refine_fp64(const QkTaskTable& tt, int grid, const uint32_t* mask,
+                                 int32_t* list, int32_t* count, hipStream_t s) {
+  if (tt.total_tiles == 0) return hipSuccess;
+  const int64_t blocks = (tt.total_tiles + 255) / 256;
+  hipLaunchKernelGGL(compact_marked_kernel, dim3((unsigned)blocks), dim3(256), 0, s, mask,
+                     tt.total_tiles, list, count);
+  hipLaunchKernelGGL(sweep_refine_kernel, dim3(grid), dim3(kThreads), 0, s, tt, mask,
+                     (const int32_t*)list, (const int32_t*)count);
   return hipGetLastError();
 }
 
