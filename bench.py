@@ -269,10 +269,14 @@ def run(args):
     out_te = {k: torch.empty((nte, ntr), **f64) for k in ("kq", "ln", "kc", "k")}
     stream = torch.cuda.current_stream()
 
+    side = torch.cuda.Stream()  # default priority
+
     def one_step(prec, timing=None):
         store = qk.QK_STORE_FP64 if prec == "fp64" else qk.QK_STORE_ALL
+        # the two independent builds overlap on two streams (the test build
+        # alone fills one wave per SIMD); the gram call waits for both
         btr = qk.qk_mps_build(xtr, 2, 64, 1e-10, store=store)
-        bte = qk.qk_mps_build(xte, 2, 64, 1e-10, store=store)
+        bte = qk.qk_mps_build(xte, 2, 64, 1e-10, store=store, stream=side)
         tasks = [
             {"rows": btr, "cols": btr, "symmetric": True, "kq": out["kq"], "lnkq": out["ln"],
              "fuse": {"x_rows": xtr, "x_cols": xtr, "gamma": 1.0 / d, "w": 0.5,

@@ -36,6 +36,35 @@ __device__ inline double2 cscale(double2 a, double s) {
   return make_double2(a.x * s, a.y * s);
 }
 
+// Sum of v over aligned groups of 2^lg lanes (lg <= 5), every lane receiving
+// its group's sum. Within a 16-lane row the partners come from DPP (quad
+// permutations, then the half-row and row mirrors, each pairing lanes of
+// the two halves reduced so far), which keeps the data in VALU; only the
+// 32-lane step crosses rows.
+__device__ inline double dpp_f64(double v, int ctrl_sel) {
+  const long long b = __double_as_longlong(v);
+  int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+  switch (ctrl_sel) {
+    case 0: lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false); break;
+    case 1: lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false); break;
+    case 2: lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false); break;
+    default: lo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false);
+             hi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false); break;
+  }
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double group_sum(double v, int lg) {
+  if (lg > 0) v += dpp_f64(v, 0);  // lane ^ 1
+  if (lg > 1) v += dpp_f64(v, 1);  // lane ^ 2
+  if (lg > 2) v += dpp_f64(v, 2);  // 7 - lane within 8
+  if (lg > 3) v += dpp_f64(v, 3);  // 15 - lane within 16
+  if (lg > 4) v += __shfl_xor(v, 16, 64);
+  return v;
+}
+
 // One-sided Jacobi on the columns of X (R rows x C columns, column-major in
 // LDS with leading dimension LD), accumulating V (C x C, column-major, LD).
 // On return the columns of X are mutually orthogonal and X_in V = X_out.
@@ -92,12 +121,10 @@ __device__ bool jacobi_columns(double2* X, double2* V, int R, int C, double floo
           gi += xp.x * xq.y - xp.y * xq.x;
         }
       }
-      for (int off = 1; off < g; off <<= 1) {
-        al += __shfl_xor(al, off, 64);
-        be += __shfl_xor(be, off, 64);
-        gr += __shfl_xor(gr, off, 64);
-        gi += __shfl_xor(gi, off, 64);
-      }
+      al = group_sum(al, lg);
+      be = group_sum(be, lg);
+      gr = group_sum(gr, lg);
+      gi = group_sum(gi, lg);
       const double gabs2 = gr * gr + gi * gi;
       const bool do_rot =
           active && al > floor2 && be > floor2 && gabs2 > tol * tol * (al * be);
