@@ -78,7 +78,7 @@ def cpu_baseline(x_tr, seconds_target=15.0):
     """Time the FP64 oracle on a bounded sample with a process pool."""
     import multiprocessing as mp
     cores = min(len(os.sched_getaffinity(0)), 16)
-    n_build, n_pairs = 8, 12288
+    n_build, n_pairs = 8, 24576
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores, initializer=_pool_init) as pool:
@@ -91,7 +91,17 @@ def cpu_baseline(x_tr, seconds_target=15.0):
     sweep_rate = cores * n_pairs / sweep_s        # pairs / s
     pairs = 4000 * 4001 // 2 + 1000 * 4000
     job_s = 5000 / build_rate + pairs / sweep_rate
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": pairs / job_s, "unit": "entries/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model,
             "sample": (f"{cores} processes x ({n_build} TEBD builds + {n_pairs} FP64 pair "
                        f"sweeps) at d=784, L=2; wall {wall:.1f}s; whole-job rate "
                        f"extrapolated to 5000 builds + {pairs} pairs")}
@@ -248,6 +258,67 @@ def ragged(args):
                                  for d in C4_DIMS}}
 
 
+def small_configs(args):
+    """The two smaller configurations as whole jobs (device builds + one fused
+    gram launch, inputs resident): 200 x 8 features at L = 1 (symmetric) and
+    2000 + 500 x 64 features at L = 2 (train x train + test x train); the
+    chosen form (AUTO) against the plain FP64 sweep."""
+    import torch
+
+    import paper_2602_01330_amd.qk as qk
+    from synthdata import CONFIGS, config_inputs
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name in ("C1", "C2"):
+        c = CONFIGS[name]
+        x_tr, x_te, _ = config_inputs(name)
+        xtr = torch.as_tensor(x_tr, device=dev)
+        xte = torch.as_tensor(x_te, device=dev) if len(x_te) else None
+        ntr, nte = len(x_tr), len(x_te)
+        pairs = ntr * (ntr + 1) // 2 + nte * ntr
+        f64 = dict(dtype=torch.float64, device=dev)
+        ktr = {k: torch.empty((ntr, ntr), **f64) for k in ("kq", "kc", "k")}
+        kte = {k: torch.empty((max(nte, 1), ntr), **f64) for k in ("kq", "kc", "k")}
+
+        def step(prec):
+            store = qk.QK_STORE_FP64 if prec == "fp64" else qk.QK_STORE_ALL
+            btr = qk.qk_mps_build(xtr, c.n_layers, c.chi_max, c.cutoff, store=store)
+            tasks = [{"rows": btr, "cols": btr, "symmetric": True, "kq": ktr["kq"],
+                      "fuse": {"x_rows": xtr, "x_cols": xtr, "gamma": 1.0 / c.d, "w": c.w,
+                               "kc": ktr["kc"], "k": ktr["k"]}}]
+            keep = [btr]
+            if xte is not None:
+                bte = qk.qk_mps_build(xte, c.n_layers, c.chi_max, c.cutoff, store=store)
+                keep.append(bte)
+                tasks.append({"rows": bte, "cols": btr, "symmetric": False, "kq": kte["kq"],
+                              "fuse": {"x_rows": xte, "x_cols": xtr, "gamma": 1.0 / c.d,
+                                       "w": c.w, "kc": kte["kc"], "k": kte["k"]}})
+            qk.qk_overlap_gram_multi(tasks, prec)
+            return keep
+
+        res = {"workload": f"{ntr} train + {nte} test, d={c.d}, L={c.n_layers}, "
+                           f"chi_max={c.chi_max}", "unique_pairs": pairs}
+        for prec in ("auto", "fp64"):
+            step(prec)
+            torch.cuda.synchronize()
+            reps = 5
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                keep = step(prec)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            del keep
+            res[prec] = {"ms_per_job": ms, "entries_per_s": pairs / (ms / 1e3)}
+        res["speedup_vs_plain_fp64"] = res["auto"]["entries_per_s"] / res["fp64"]["entries_per_s"]
+        log(f"{name}: auto {res['auto']['ms_per_job']:.2f} ms, fp64 {res['fp64']['ms_per_job']:.2f} ms")
+        out[name] = res
+    return out
+
+
 def run(args):
     import numpy as np
     import torch
@@ -373,6 +444,9 @@ def run(args):
     if not args.no_ragged:
         log("bench: ragged multi-d run")
         line["ragged"] = ragged(args)
+    if not args.no_small:
+        log("bench: smaller configurations")
+        line["small_configs"] = small_configs(args)
     if args.serve_seconds > 0:
         log("bench: serving run")
         line["serving"] = serving(args)
@@ -393,6 +467,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-ragged", action="store_true", help="skip the ten-d ragged run")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the two smaller whole-job configurations")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="measured seconds of the serving run (0 skips it)")
     ap.add_argument("--serve-warmup", type=float, default=3.0)
