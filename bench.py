@@ -300,6 +300,11 @@ def small_configs(args):
 
         res = {"workload": f"{ntr} train + {nte} test, d={c.d}, L={c.n_layers}, "
                            f"chi_max={c.chi_max}", "unique_pairs": pairs}
+        # the autotuner picks AUTO's form for this size (tiny jobs favour the
+        # single-launch FP64 sweep over a reduced form plus its refinement)
+        tb = qk.qk_mps_build(xtr, c.n_layers, c.chi_max, c.cutoff, store=qk.QK_STORE_ALL)
+        res["auto_form"] = qk.qk_autotune(tb, tb, True, max_tiles=256)
+        tb.close()
         for prec in ("auto", "fp64"):
             step(prec)
             torch.cuda.synchronize()
