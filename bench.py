@@ -249,13 +249,16 @@ def ragged(args):
         ms = timed([t])
         per_d[str(d)] = {"ms": ms, "entries_per_s": pairs / (ms / 1e3)}
     sum_alone = sum(v["ms"] for v in per_d.values())
-    log(f"ragged: one launch {all_ms:.2f} ms, sum of per-d launches {sum_alone:.2f} ms")
+    forms = {str(d): qk.qk_resolve_precision(batches[d], batches[d]) for d in C4_DIMS}
+    n_launch = len(set(forms.values()))  # AUTO runs one launch per distinct tuned form
+    log(f"ragged: all ten d in {n_launch} launch(es) {all_ms:.2f} ms, "
+        f"sum of per-d launches {sum_alone:.2f} ms")
     return {"workload": "d in {2,4,8,...,512,784}, 1000 samples each, symmetric, L=2, "
                         "chi_max=min(2^(d/2),64); MPS resident",
             "one_launch_ms": all_ms, "one_launch_entries_per_s": 10 * pairs / (all_ms / 1e3),
+            "launches_per_call": n_launch,
             "sum_of_single_d_launches_ms": sum_alone, "per_d": per_d,
-            "sweep_form_per_d": {str(d): qk.qk_resolve_precision(batches[d], batches[d])
-                                 for d in C4_DIMS}}
+            "sweep_form_per_d": forms}
 
 
 def small_configs(args):
@@ -282,8 +285,7 @@ def small_configs(args):
         ktr = {k: torch.empty((ntr, ntr), **f64) for k in ("kq", "kc", "k")}
         kte = {k: torch.empty((max(nte, 1), ntr), **f64) for k in ("kq", "kc", "k")}
 
-        def step(prec):
-            store = qk.QK_STORE_FP64 if prec == "fp64" else qk.QK_STORE_ALL
+        def step(prec, store):
             btr = qk.qk_mps_build(xtr, c.n_layers, c.chi_max, c.cutoff, store=store)
             tasks = [{"rows": btr, "cols": btr, "symmetric": True, "kq": ktr["kq"],
                       "fuse": {"x_rows": xtr, "x_cols": xtr, "gamma": 1.0 / c.d, "w": c.w,
@@ -305,14 +307,17 @@ def small_configs(args):
         tb = qk.qk_mps_build(xtr, c.n_layers, c.chi_max, c.cutoff, store=qk.QK_STORE_ALL)
         res["auto_form"] = qk.qk_autotune(tb, tb, True, max_tiles=256)
         tb.close()
-        for prec in ("auto", "fp64"):
-            step(prec)
+        # AUTO builds only the tensors its chosen form reads (the reduced forms
+        # also read the FP64 ones, for their refinement pass)
+        auto_store = qk.QK_STORE_FP64 if res["auto_form"] == "fp64" else qk.QK_STORE_ALL
+        for prec, store in (("auto", auto_store), ("fp64", qk.QK_STORE_FP64)):
+            step(prec, store)
             torch.cuda.synchronize()
             reps = 5
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for _ in range(reps):
-                keep = step(prec)
+                keep = step(prec, store)
             e1.record(stream)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / reps

@@ -207,8 +207,10 @@ typedef struct {
 /*
  * qk_overlap_gram_multi -- all tasks in one persistent launch; tiles of all
  * tasks form one list in longest-processing-time order (cost n * chi^3).
- * QK_PREC_AUTO resolves with the task of largest total cost.
- * At most 16 tasks. Errors as qk_overlap_gram.
+ * QK_PREC_AUTO resolves every task on its own (as qk_resolve_precision), so
+ * a task's result does not depend on the other tasks; tasks that resolve to
+ * the same form share one launch, one launch per form in order of first
+ * appearance. At most 16 tasks. Errors as qk_overlap_gram.
  */
 QK_API qk_status qk_overlap_gram_multi(const qk_gram_task* tasks, int32_t n_tasks,
                                 qk_precision prec, void* hip_stream);
@@ -249,7 +251,9 @@ QK_API qk_status qk_set_refine_threshold(qk_precision prec, double tau);
  * qk_autotune -- times the sweep forms that meet the stated tolerance
  * (complex FP64, complex FP32 on VALU with 2..4 persistent workgroups per CU,
  * complex FP32 on MFMA, split BF16x3 on MFMA) on the first max_tiles 16 x 16
- * tiles of rows x cols (refinement off while timing), and records the
+ * tiles of rows x cols (when these are all the tiles, each reduced form
+ * with its FP64 refinement pass as AUTO would run it, provided both batches
+ * hold FP64 tensors; on a partial slice the sweep alone), and records the
  * fastest under the key (chi_pad, ceil(log2 n_qubits)); QK_PREC_AUTO then
  * resolves to it for every batch pair with that key. Synchronises the
  * stream. Writes the winner to *chosen (may be NULL).

@@ -522,21 +522,29 @@ qk_status qk_overlap_gram_multi(const qk_gram_task* tasks, int32_t n_tasks,
     return fail(QK_ERR_INVALID_ARG, "need 1..16 tasks");
   hipStream_t s = (hipStream_t)hip_stream;
   if (prec == QK_PREC_AUTO) {
-    // one launch, one form: the form tuned for the most expensive task (cost
-    // per tile ~ n_qubits * chi_pad^3), which dominates the launch
-    int top = 0;
-    double best = -1.0;
+    // every task takes the form tuned for its own shape, so a task's result
+    // does not depend on the tasks it is batched with; tasks that share a form
+    // share one launch, the groups run back to back on the stream
+    qk_precision form[QK_MAX_TASKS];
     for (int k = 0; k < n_tasks; ++k) {
       if (!tasks[k].rows || !tasks[k].cols) return fail(QK_ERR_INVALID_ARG, "batch is NULL");
-      const double c = (double)tasks[k].rows->nq * tasks[k].rows->T * tasks[k].rows->T *
-                       tasks[k].rows->T * (double)tasks[k].rows->n * (double)tasks[k].cols->n;
-      if (c > best) {
-        best = c;
-        top = k;
-      }
+      qk_status st = qk_resolve_precision(tasks[k].rows, tasks[k].cols, &form[k]);
+      if (st != QK_OK) return st;
     }
-    qk_status st = qk_resolve_precision(tasks[top].rows, tasks[top].cols, &prec);
-    if (st != QK_OK) return st;
+    bool done[QK_MAX_TASKS] = {};
+    for (int k = 0; k < n_tasks; ++k) {
+      if (done[k]) continue;
+      qk_gram_task group[QK_MAX_TASKS];
+      int n = 0;
+      for (int j = k; j < n_tasks; ++j)
+        if (!done[j] && form[j] == form[k]) {
+          group[n++] = tasks[j];
+          done[j] = true;
+        }
+      qk_status st = qk_overlap_gram_multi(group, n, form[k], hip_stream);
+      if (st != QK_OK) return st;
+    }
+    return QK_OK;
   }
   if (prec < QK_PREC_FP64 || prec > QK_PREC_FP32_MFMA)
     return fail(QK_ERR_INVALID_ARG, "unknown precision");
@@ -594,16 +602,30 @@ qk_status qk_autotune(const qk_mps_batch* rows, const qk_mps_batch* cols, int32_
   qk_status st = QK_OK;
   for (const Cand& c : cands) {
     std::vector<QkTask> tv(1);
-    st = fill_task(tv[0], rows, cols, symmetric, c.p == QK_PREC_FP64, false, nullptr, 0,
+    // When the slice is the whole job, a reduced form is timed with its FP64
+    // refinement pass (part of what AUTO runs; on small jobs its fixed cost can
+    // decide). On a partial slice it is not: the first tiles lie next to the
+    // diagonal, where far more pairs exceed tau than in the whole job, and the
+    // pass's fixed cost is not spread over the job's tiles.
+    const double tau = c.p == QK_PREC_FP64 ? 0.0 : refine_tau(c.p);
+    bool ref = tau > 0.0 && rows->t64 && cols->t64;
+    st = fill_task(tv[0], rows, cols, symmetric, c.p == QK_PREC_FP64, ref, nullptr, 0,
                    scratch, cols->n, nullptr, tile_for(c.p));
     if (st != QK_OK) break;
+    if (ref && tv[0].n_tiles > max_tiles) {
+      ref = false;
+      st = fill_task(tv[0], rows, cols, symmetric, false, false, nullptr, 0, scratch, cols->n,
+                     nullptr, tile_for(c.p));
+      if (st != QK_OK) break;
+    }
     tiles = std::min<int64_t>(tv[0].n_tiles, max_tiles);
     qk_tune_store(rows->T, rows->nq, QkTuneEntry{c.p, c.wg, 0.0});
-    st = run_tasks(tv, c.p, 0.0, s, max_tiles);  // warm-up
+    st = run_tasks(tv, c.p, ref ? tau : 0.0, s, max_tiles);  // warm-up
     if (st != QK_OK) break;
     float ms = 0.f;
     if (hipEventRecord(e0, s) != hipSuccess) { st = fail(QK_ERR_HIP, "event"); break; }
-    for (int rep = 0; rep < 3 && st == QK_OK; ++rep) st = run_tasks(tv, c.p, 0.0, s, max_tiles);
+    for (int rep = 0; rep < 3 && st == QK_OK; ++rep)
+      st = run_tasks(tv, c.p, ref ? tau : 0.0, s, max_tiles);
     if (st != QK_OK) break;
     if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
         hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {

@@ -74,7 +74,21 @@ def test_rows_match_oracle(qk, data):
         srv.close()
 
 
-def test_alone_and_mixed_are_bitwise_equal(qk, data):
+def _tune_entry(qk, key):
+    for line in qk.qk_tune_export().splitlines():
+        t = line.split()
+        if (int(t[0]), int(t[1])) == key:
+            return line
+    return None
+
+
+@pytest.mark.parametrize("forms", ["as_tuned", "fp64_and_mfma"])
+def test_alone_and_mixed_are_bitwise_equal(qk, data, forms):
+    # chi_pad 4 at L = 2; site-count buckets ceil(log2 d): 4 for d = 16, 6 for d = 64
+    keys = [(4, 4), (4, 6)]
+    saved = {k: _tune_entry(qk, k) for k in keys}
+    if forms == "fp64_and_mfma":  # the two support sets resolve to different forms
+        qk.qk_tune_import(f"4 4 {qk.PREC['fp64']} 1 1.0\n4 6 {qk.PREC['fp32_mfma']} 1 1.0\n")
     rng = np.random.default_rng(3)
     plan = [(int(rng.choice(DIMS)), int(rng.integers(1, 9)), float(rng.uniform()))
             for _ in range(12)]
@@ -90,8 +104,11 @@ def test_alone_and_mixed_are_bitwise_equal(qk, data):
         assert stats["n_iters"] < 2 * len(plan)  # the burst was batched
     finally:
         srv.close()
-    for a, m in zip(alone, mixed):
-        assert np.array_equal(a, m)
+        # restore; a key that had no entry gets the built-in choice for T = 4
+        qk.qk_tune_import("".join((saved[k] or f"{k[0]} {k[1]} {qk.PREC['fp32_mfma']} 1 0")
+                                  + "\n" for k in keys))
+    for (d, n, w), a, m in zip(plan, alone, mixed):
+        assert np.array_equal(a, m), (forms, d, n, w)
 
 
 def test_small_budget_queues_requests(qk, data):
