@@ -270,7 +270,7 @@ qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, h
   // 32-bit byte offsets
   for (const QkTask& t : tasks) {
     const int64_t slot_bytes = (int64_t)2 * t.T * t.T * kQkPackFloats * 4;
-    if (std::max(t.na, t.nb) * slot_bytes > (int64_t)UINT32_MAX)
+    if (std::max(t.na, t.nb) * slot_bytes + 4096 > (int64_t)UINT32_MAX)
       return fail(QK_ERR_UNSUPPORTED, "batch too large for a 32-bit packed site array");
   }
   const bool refine = tau > 0.0;

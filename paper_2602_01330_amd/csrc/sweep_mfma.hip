@@ -599,6 +599,303 @@ __global__ __launch_bounds__(kThreads) void sweep_mfma_kernel(QkTaskTable tt, ui
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 form on the 4x4x1 block MFMA (v_mfma_f32_4x4x1_16b_f32: sixteen
+// independent 4 x 4 outer-product accumulations per instruction, at the
+// same FLOP rate as the 16 x 16 x 4 shape). Block b of an instruction is one
+// pair of the wave's 4 x 4 pair block, so neither step wastes a row:
+//
+//   step R, per pair:  G^s[a][(c,b')] = sum_(c_in,b) E[a][(c_in,b)] Bhat^s[(c_in,b)][(c,b')]
+//     four chains (s, c) of eight K steps; A operand: lane a of the block
+//     holds row a of E (Re and Im for b = 0..3); B operand: lane b' holds
+//     column b' of Bhat. The output leaves lane b' holding column b' of
+//     G^s_c (rows a in the four accumulator registers).
+//   step L, per pair (transposed):  E'^T[b'][(c',a')] = sum_(s,c_in,a) G^s_(c_in)[a][b'] Ahat^s[(c_in,a)][(c',a')]
+//     two chains c' of sixteen K steps; A operand: lane b' holds column b'
+//     of G -- exactly what step R left there; B operand: lane a' holds
+//     column a' of Ahat. The output leaves lane a' holding row a' of E' --
+//     exactly the A operand of the next step R.
+//
+// E and G never leave the registers: no LDS and no lane exchange per site.
+// The column operand Bhat_j depends only on the pair's column, and pairs
+// (p, q) sit in block 4 p + q, so the four 16-lane groups (rows p) need the
+// same values: each group loads one quarter (bond row b = its group index)
+// and every step R instruction broadcasts the group holding its b to all
+// four groups (BLGP = 4 + b). The row operand Ahat_i is loaded whole by the
+// four lanes of every block. Both come from the packed (-Im, Re, Im)
+// elements, three floats per lane and element, which hold every sign the
+// realified products take.
+__device__ inline float3 ld3(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, (int)off, 0, 0);
+  return make_float3(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]));
+}
+
+// packed element (-Im z, Re z, Im z) -> entry of the realified right factor
+// [[Re, Im], [-Im, Re]] at (c_in, c): (0,0) Re, (1,0) -Im, (0,1) Im, (1,1) Re
+__device__ inline float rhat(const float3& v, int c, int c_in) {
+  return c == c_in ? v.y : (c_in ? v.x : v.z);
+}
+// entry of the realified conj(A) factor at (c_in, c'): Re(conj(a) g) =
+// Re a Re g + Im a Im g, Im(conj(a) g) = Re a Im g - Im a Re g
+__device__ inline float lhat(const float3& v, int cp, int c_in) {
+  return cp == c_in ? v.y : (c_in ? v.z : v.x);
+}
+
+template <int BQ>
+__device__ inline void m4_step_r_b(const float (&e)[2][4], const float3 (&wb)[2], f4 (&g)[2][2]) {
+#pragma unroll
+  for (int cin = 0; cin < 2; ++cin)
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        g[s][c] = __builtin_amdgcn_mfma_f32_4x4x1f32(e[cin][BQ], rhat(wb[s], c, cin), g[s][c], 0, 0,
+                                                     4 + BQ);
+}
+
+struct M4Smem {
+  alignas(16) double xs[32 * kXStride];  // feature rows of the tile (fused RBF)
+  unsigned mask[kQkMaskWords];
+};
+
+// A wave owns NB 4 x 4 pair blocks side by side (same four rows): the row
+// operand is loaded once for all of them, which halves the load traffic per
+// MFMA at NB = 2; a 16 x 16 tile then takes 16 / NB waves.
+template <int NB, int T>
+__device__ void run_tile_m4(const QkTask& t, int ti, int tj, M4Smem& sm, uint32_t* mask,
+                            int64_t tile_id, double ln_tau) {
+  constexpr int kThr = kThreads / NB;
+  constexpr int TT = T * T, slotT = 2 * TT;
+  constexpr int kEB = kQkPackFloats * 4;  // bytes per packed element
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index: scalar
+  const int lane = tid & 63;
+  const int x = lane & 3, qq = (lane >> 2) & 3, pp = lane >> 4;
+  const int wr = w / (4 / NB), wc0 = (w % (4 / NB)) * NB;
+  const int64_t i = (int64_t)ti * kTile + 4 * wr + pp;
+  int64_t j[NB];
+#pragma unroll
+  for (int y = 0; y < NB; ++y) j[y] = (int64_t)tj * kTile + 4 * (wc0 + y) + qq;
+  // samples past the end are clamped to the last one: their pairs compute
+  // values that are never written
+  const int64_t ic = i < t.na ? i : t.na - 1;
+  const int nq = t.nq;
+  const unsigned bbytes = (unsigned)((int64_t)t.nb * slotT * kEB);
+  const unsigned abytes = (unsigned)((int64_t)t.na * slotT * kEB);
+  // Per-lane base offsets; the element (s, a) adds a constant. Lanes whose
+  // bond index lies outside the T x T block start at the out-of-range offset
+  // and load zeros (the library keeps n * slot + 4 KiB below 2^32, so the
+  // constants never wrap); bond rows a >= T are not loaded at all.
+  unsigned boff[NB];
+#pragma unroll
+  for (int y = 0; y < NB; ++y) {
+    const int64_t jc = j[y] < t.nb ? j[y] : t.nb - 1;
+    boff[y] = (pp < T && x < T) ? (unsigned)((jc * slotT + pp * T + x) * kEB) : bbytes;
+  }
+  const unsigned aoff = x < T ? (unsigned)((ic * slotT + x) * kEB) : abytes;
+  const char* bbase = static_cast<const char*>(t.tb);
+  const char* abase = static_cast<const char*>(t.ta);
+  const int64_t bstride = bbytes, astride = abytes;
+
+  float3 wb[NB][2];  // column operands: element [s][b = pp][x] of sample j
+  float3 va[2][4];   // row operand: elements [s][a][x] of sample i
+  auto fetch_b = [&](int k) {
+    const __amdgpu_buffer_rsrc_t r = site_rsrc(bbase + (int64_t)k * bstride, bbytes);
+#pragma unroll
+    for (int y = 0; y < NB; ++y)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) wb[y][s] = ld3(r, boff[y] + s * TT * kEB);
+  };
+  auto fetch_a = [&](int k) {
+    const __amdgpu_buffer_rsrc_t r = site_rsrc(abase + (int64_t)k * astride, abytes);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        va[s][a] = a < T ? ld3(r, aoff + (s * TT + a * T) * kEB) : make_float3(0.f, 0.f, 0.f);
+  };
+
+  // lane x of a block holds row a = x of the pair's E: e[c][b] = (Re, Im) E[x][b]
+  float e[NB][2][4];
+#pragma unroll
+  for (int y = 0; y < NB; ++y)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) e[y][c][b] = (c == 0 && b == 0 && x == 0) ? 1.f : 0.f;
+  int expo[NB];
+#pragma unroll
+  for (int y = 0; y < NB; ++y) expo[y] = 0;
+
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // drain the previous tile's stores (vmcnt(0))
+  fetch_b(0);
+  __builtin_amdgcn_sched_barrier(0);
+  fetch_a(0);
+  __builtin_amdgcn_sched_barrier(0);
+  for (int k = 0; k < nq; ++k) {
+    const int kn = k + 1 < nq ? k + 1 : k;
+    f4 g[NB][2][2];
+#pragma unroll
+    for (int y = 0; y < NB; ++y) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) g[y][s][c] = f4{0.f, 0.f, 0.f, 0.f};
+      m4_step_r_b<0>(e[y], wb[y], g[y]);
+      m4_step_r_b<1>(e[y], wb[y], g[y]);
+      m4_step_r_b<2>(e[y], wb[y], g[y]);
+      m4_step_r_b<3>(e[y], wb[y], g[y]);
+    }
+    fetch_b(kn);  // in flight until the next step R
+    __builtin_amdgcn_sched_barrier(0);
+    f4 en[NB][2];
+#pragma unroll
+    for (int y = 0; y < NB; ++y) en[y][0] = en[y][1] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int cin = 0; cin < 2; ++cin)
+#pragma unroll
+          for (int y = 0; y < NB; ++y)
+#pragma unroll
+            for (int cp = 0; cp < 2; ++cp)
+              en[y][cp] = __builtin_amdgcn_mfma_f32_4x4x1f32(g[y][s][cin][a],
+                                                             lhat(va[s][a], cp, cin), en[y][cp],
+                                                             0, 0, 0);
+    fetch_a(kn);  // in flight until the next step L
+    if (((k + w) % kRescaleEvery) == kRescaleEvery - 1) {
+      // exact power-of-two rescale of each pair (a block's four lanes)
+#pragma unroll
+      for (int y = 0; y < NB; ++y) {
+        float lm = 0.f;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) lm = __builtin_elementwise_maximum(lm, fabsf(en[y][c][b]));
+        unsigned m = __float_as_uint(lm);
+        m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0xB1, 0xF, 0xF, false));
+        m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0x4E, 0xF, 0xF, false));
+        const unsigned ex = m >> 23;
+        const float sc = rescale_factor(ex);
+        expo[y] += (int)ex - 126;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) en[y][c][b] *= sc;
+      }
+    }
+#pragma unroll
+    for (int y = 0; y < NB; ++y)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) e[y][c][b] = en[y][c][b];
+  }
+
+  // ---- epilogue: lane x = 0 of a block holds E[0][0] of its pair
+  if (tid < kQkMaskWords) sm.mask[tid] = 0;
+  double d2[NB];
+#pragma unroll
+  for (int y = 0; y < NB; ++y) d2[y] = 0.0;
+  if (t.fuse) {
+    // fused RBF: squared distances by direct difference, the tile's 16 row
+    // and 16 column feature vectors staged through LDS in chunks; lane x of
+    // a pair sums the features f = x mod 4 of each chunk
+    const int64_t ti0 = (int64_t)ti * kTile, tj0 = (int64_t)tj * kTile;
+    for (int f0 = 0; f0 < nq; f0 += kXChunk) {
+      const int nf = min(kXChunk, nq - f0);
+      __syncthreads();
+      for (int el = tid; el < 32 * nf; el += kThr) {
+        const int smp = el / nf, f = el - smp * nf;
+        double v = 0.0;
+        if (smp < 16) {
+          const int64_t r = ti0 + smp;
+          if (r < t.na) v = t.xr[r * t.ld_xr + f0 + f];
+        } else {
+          const int64_t c = tj0 + smp - 16;
+          if (c < t.nb) v = t.xc[c * t.ld_xc + f0 + f];
+        }
+        sm.xs[smp * kXStride + f] = v;
+      }
+      __syncthreads();
+      const double* xrow = sm.xs + (4 * wr + pp) * kXStride;
+#pragma unroll
+      for (int y = 0; y < NB; ++y) {
+        const double* xcol = sm.xs + (16 + 4 * (wc0 + y) + qq) * kXStride;
+        double acc = 0.0;
+        for (int f = x; f < nf; f += 4) {
+          const double df = xrow[f] - xcol[f];
+          acc += df * df;
+        }
+        d2[y] += acc;
+      }
+    }
+#pragma unroll
+    for (int y = 0; y < NB; ++y) {
+      d2[y] += __shfl_xor(d2[y], 1, 64);
+      d2[y] += __shfl_xor(d2[y], 2, 64);
+    }
+  }
+  __syncthreads();  // mask words cleared
+#pragma unroll
+  for (int y = 0; y < NB; ++y) {
+    const bool valid = x == 0 && i < t.na && j[y] < t.nb && (!t.symmetric || j[y] >= i);
+    const double re = (double)e[y][0][0], im = (double)e[y][1][0];
+    const double mag2 = re * re + im * im;
+    const double lnk =
+        mag2 > 0.0 ? log(mag2) + 2.0 * (double)expo[y] * 0.69314718055994530942 : -INFINITY;
+    const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
+    if (valid) {
+      const int64_t jj = j[y];
+      auto put = [&](double* ptr, int64_t ld, double v) {
+        if (!ptr) return;
+        ptr[i * ld + jj] = v;
+        if (t.symmetric && jj != i) ptr[jj * ld + i] = v;
+      };
+      put(t.kq, t.ld_kq, kq);
+      put(t.lnkq, t.ld_ln, lnk);
+      if (t.fuse) {
+        const double kc = exp(-t.gamma * d2[y]);
+        const double wgt = t.w_rows ? t.w_rows[i] : t.w;
+        put(t.kc, t.ld_kc, kc);
+        put(t.k, t.ld_k, wgt * kq + (1.0 - wgt) * kc);
+      }
+      if (mask && lnk > ln_tau) {
+        const int bit = (int)(i - (int64_t)ti * kTile) * kTile + (int)(jj - (int64_t)tj * kTile);
+        atomicOr(&sm.mask[bit >> 5], 1u << (bit & 31));
+      }
+    }
+  }
+  __syncthreads();
+  if (mask && tid < kQkMaskWords) mask[tile_id * kQkMaskWords + tid] = sm.mask[tid];
+}
+
+// Pair blocks per wave of the FP32 form, and workgroups per CU (LDS holds
+// two workgroups' feature staging).
+constexpr int kM4Blocks = 2;
+constexpr int kM4WgPerCu = 2;
+
+// (HIP's second launch bound is the minimum number of waves per SIMD)
+__global__ __launch_bounds__(kThreads / kM4Blocks, kM4WgPerCu * kWaves / kM4Blocks / 4) void sweep_m4_kernel(
+    QkTaskTable tt, uint32_t* flags, double ln_tau) {
+  __shared__ M4Smem sm;
+  for (int64_t rnd = 0; rnd * gridDim.x < tt.total_tiles; ++rnd) {
+    const int64_t q = qk_tile_of(rnd, blockIdx.x, gridDim.x);
+    if (q >= tt.total_tiles) break;  // only the last round is partial
+    int k = 0;
+    while (k + 1 < tt.n_tasks && tt.t[k + 1].tile_begin <= q) ++k;
+    const QkTask& t = tt.t[k];
+    int ti, tj;
+    qk_tile_coords(t, q - t.tile_begin, ti, tj);
+    if (t.T == 4) run_tile_m4<kM4Blocks, 4>(t, ti, tj, sm, flags, q, ln_tau);
+    else if (t.T == 2) run_tile_m4<kM4Blocks, 2>(t, ti, tj, sm, flags, q, ln_tau);
+    else run_tile_m4<kM4Blocks, 1>(t, ti, tj, sm, flags, q, ln_tau);
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 bool qk_mfma_supports(qk_precision p, int T) {
@@ -613,9 +910,12 @@ hipError_t qk_launch_sweep_mfma(const QkTaskTable& tt, qk_precision p, int cus,
   if (tt.total_tiles == 0) return hipSuccess;
   const int grid = (int)(tt.total_tiles < (int64_t)cus ? tt.total_tiles : cus);
   switch (p) {
-    case QK_PREC_FP32_MFMA:
-      hipLaunchKernelGGL(sweep_mfma_kernel<kF32>, dim3(grid), dim3(kThreads), 0, s, tt, flags, ln_tau);
+    case QK_PREC_FP32_MFMA: {
+      const int64_t g4 = (int64_t)cus * kM4WgPerCu;
+      hipLaunchKernelGGL(sweep_m4_kernel, dim3((int)(tt.total_tiles < g4 ? tt.total_tiles : g4)),
+                         dim3(kThreads / kM4Blocks), 0, s, tt, flags, ln_tau);
       break;
+    }
     case QK_PREC_BF16X2:
       hipLaunchKernelGGL(sweep_mfma_kernel<kBF16x2>, dim3(grid), dim3(kThreads), 0, s, tt, flags, ln_tau);
       break;
