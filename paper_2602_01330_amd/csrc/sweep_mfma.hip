@@ -427,10 +427,11 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, MfmaSmem& sm, uint32_t
         mma4<F, 4>(aop, bop, acc[x]);
       }
       fetch_a(kn, cur);  // in flight until the next step L
-      // waves rescale at staggered sites, so that one wave's reduction chain
-      // overlaps the others' MFMAs (any schedule is exact: the exponent is
-      // tracked per pair)
-      const bool rescale = ((k + w) % kRescaleEvery) == kRescaleEvery - 1;
+      // every pair rescales at the same sites: a power-of-two scale is exact
+      // except where entries enter the subnormal range, so a schedule that
+      // depended on the wave would make a pair's last bits depend on its
+      // position in the launch
+      const bool rescale = (k % kRescaleEvery) == kRescaleEvery - 1;
 #pragma unroll
       for (int x = 0; x < NB; ++x) {
         if (rescale) {
@@ -625,8 +626,10 @@ __global__ __launch_bounds__(kThreads) void sweep_mfma_kernel(QkTaskTable tt, ui
 // four lanes of every block. Both come from the packed (-Im, Re, Im)
 // elements, three floats per lane and element, which hold every sign the
 // realified products take.
-__device__ inline float3 ld3(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, (int)off, 0, 0);
+// soff is a wave-uniform constant (the element's offset from the lane's
+// base): it travels in the instruction's scalar offset, not in a VGPR
+__device__ inline float3 ld3(__amdgpu_buffer_rsrc_t r, unsigned off, int soff = 0) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, (int)off, soff, 0);
   return make_float3(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]));
 }
 
@@ -682,10 +685,11 @@ __device__ void run_tile_m4(const QkTask& t, int ti, int tj, M4Smem& sm, uint32_
   const int nq = t.nq;
   const unsigned bbytes = (unsigned)((int64_t)t.nb * slotT * kEB);
   const unsigned abytes = (unsigned)((int64_t)t.na * slotT * kEB);
-  // Per-lane base offsets; the element (s, a) adds a constant. Lanes whose
-  // bond index lies outside the T x T block start at the out-of-range offset
-  // and load zeros (the library keeps n * slot + 4 KiB below 2^32, so the
-  // constants never wrap); bond rows a >= T are not loaded at all.
+  // Per-lane base offsets; the element (s, a) adds a constant scalar offset.
+  // Lanes whose bond index lies outside the T x T block start at the
+  // out-of-range offset and load zeros (whether or not the range check counts
+  // the scalar part: valid elements lie inside the array, and the library
+  // keeps n * slot + 4 KiB below 2^32); bond rows a >= T are not loaded.
   unsigned boff[NB];
 #pragma unroll
   for (int y = 0; y < NB; ++y) {
@@ -704,7 +708,7 @@ __device__ void run_tile_m4(const QkTask& t, int ti, int tj, M4Smem& sm, uint32_
 #pragma unroll
     for (int y = 0; y < NB; ++y)
 #pragma unroll
-      for (int s = 0; s < 2; ++s) wb[y][s] = ld3(r, boff[y] + s * TT * kEB);
+      for (int s = 0; s < 2; ++s) wb[y][s] = ld3(r, boff[y], s * TT * kEB);
   };
   auto fetch_a = [&](int k) {
     const __amdgpu_buffer_rsrc_t r = site_rsrc(abase + (int64_t)k * astride, abytes);
@@ -712,7 +716,7 @@ __device__ void run_tile_m4(const QkTask& t, int ti, int tj, M4Smem& sm, uint32_
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int a = 0; a < 4; ++a)
-        va[s][a] = a < T ? ld3(r, aoff + (s * TT + a * T) * kEB) : make_float3(0.f, 0.f, 0.f);
+        va[s][a] = a < T ? ld3(r, aoff, (s * TT + a * T) * kEB) : make_float3(0.f, 0.f, 0.f);
   };
 
   // lane x of a block holds row a = x of the pair's E: e[c][b] = (Re, Im) E[x][b]
@@ -765,8 +769,11 @@ __device__ void run_tile_m4(const QkTask& t, int ti, int tj, M4Smem& sm, uint32_
                                                              lhat(va[s][a], cp, cin), en[y][cp],
                                                              0, 0, 0);
     fetch_a(kn);  // in flight until the next step L
-    if (((k + w) % kRescaleEvery) == kRescaleEvery - 1) {
-      // exact power-of-two rescale of each pair (a block's four lanes)
+    if ((k % kRescaleEvery) == kRescaleEvery - 1) {
+      // power-of-two rescale of each pair (a block's four lanes), at the same
+      // sites for every pair, so that a pair's result does not depend on its
+      // position in the launch (the scale is exact except for entries in the
+      // subnormal range)
 #pragma unroll
       for (int y = 0; y < NB; ++y) {
         float lm = 0.f;

@@ -205,6 +205,20 @@ def test_determinism_bitwise(qk):
     assert np.array_equal(a["ln"], b["ln"])
 
 
+@pytest.mark.parametrize("prec", FORMS)
+def test_position_in_launch_does_not_change_bits(qk, prec):
+    # the same pairs computed at other places inside the tiles (rows and
+    # columns shifted by prepending other samples) give bit-identical results
+    X, _ = gen_clusters(40, 256, 3)
+    rows, cols = X[:14], X[14:]
+    a = gpu_gram(qk, rows, 2, 64, prec, False, Y=cols)
+    b = gpu_gram(qk, np.vstack([X[20:27], rows]), 2, 64, prec, False,
+                 Y=np.vstack([X[:5], cols]))
+    print(f"[position {prec}] max |d lnK| = {np.max(np.abs(a['ln'] - b['ln'][7:, 5:])):.3e}",
+          flush=True)
+    assert np.array_equal(a["ln"], b["ln"][7:, 5:])
+
+
 @pytest.mark.parametrize("prec,bound", [("fp32", 1e-3), ("fp32_mfma", 1e-3),
                                         ("bf16x3", 1e-3), ("bf16x2", 3e-2)])
 def test_raw_precision_at_784_qubits(qk, prec, bound):
