@@ -656,8 +656,14 @@ __device__ inline void m4_step_r_b(const float (&e)[2][4], const float3 (&wb)[2]
                                                      4 + BQ);
 }
 
+// Per-wave staging slot of the row operand: 4 rows x 32 elements (s, a, x)
+// of one site, each element padded to 16 bytes for aligned b128 reads.
+constexpr int kM4StRow = 32 * 4;  // floats per staged row
 struct M4Smem {
-  alignas(16) double xs[32 * kXStride];  // feature rows of the tile (fused RBF)
+  union {
+    alignas(16) double xs[32 * kXStride];   // feature rows of the tile (fused RBF, after the sweep)
+    alignas(16) float st[16][4 * kM4StRow];  // row-operand staging, one slot per wave (during it)
+  } u;
   unsigned mask[kQkMaskWords];
 };
 
@@ -696,12 +702,32 @@ __device__ void run_tile_m4(const QkTask& t, int ti, int tj, M4Smem& sm, uint32_
     const int64_t jc = j[y] < t.nb ? j[y] : t.nb - 1;
     boff[y] = (pp < T && x < T) ? (unsigned)((jc * slotT + pp * T + x) * kEB) : bbytes;
   }
-  const unsigned aoff = x < T ? (unsigned)((ic * slotT + x) * kEB) : abytes;
   const char* bbase = static_cast<const char*>(t.tb);
   const char* abase = static_cast<const char*>(t.ta);
   const int64_t bstride = bbytes, astride = abytes;
+  // The row operand is staged through the wave's own LDS slot: the wave's
+  // 4 rows x 32 elements of a site are loaded from memory once (two
+  // elements per lane, rows contiguous in memory) and every lane then reads
+  // the 8 elements it needs; direct loads would return each element to all
+  // four lanes of a row (one per column of the block), and load data return
+  // is the sweep's other bottleneck next to the matrix cores. One wave writes
+  // and reads its slot, and LDS operations of one wave complete in order, so
+  // no barrier is needed.
+  float* st = sm.u.st[w];
+  unsigned soff[2];
+  int sdst[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int el = lane + 64 * h, r = el >> 5, e = el & 31;
+    const int s = e >> 4, a = (e >> 2) & 3, xx = e & 3;
+    int64_t ir = (int64_t)ti * kTile + 4 * wr + r;
+    ir = ir < t.na ? ir : t.na - 1;
+    soff[h] = (a < T && xx < T) ? (unsigned)((ir * slotT + s * TT + a * T + xx) * kEB) : abytes;
+    sdst[h] = r * kM4StRow + 4 * e;
+  }
 
   float3 wb[NB][2];  // column operands: element [s][b = pp][x] of sample j
+  float3 stg[2];     // staged row-operand elements in flight
   float3 va[2][4];   // row operand: elements [s][a][x] of sample i
   auto fetch_b = [&](int k) {
     const __amdgpu_buffer_rsrc_t r = site_rsrc(bbase + (int64_t)k * bstride, bbytes);
@@ -710,13 +736,24 @@ __device__ void run_tile_m4(const QkTask& t, int ti, int tj, M4Smem& sm, uint32_
 #pragma unroll
       for (int s = 0; s < 2; ++s) wb[y][s] = ld3(r, boff[y], s * TT * kEB);
   };
-  auto fetch_a = [&](int k) {
+  auto fetch_stage = [&](int k) {
     const __amdgpu_buffer_rsrc_t r = site_rsrc(abase + (int64_t)k * astride, abytes);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) stg[h] = ld3(r, soff[h]);
+  };
+  auto put_stage = [&]() {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      *reinterpret_cast<f4*>(st + sdst[h]) = f4{stg[h].x, stg[h].y, stg[h].z, 0.f};
+  };
+  auto read_a = [&]() {
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-        va[s][a] = a < T ? ld3(r, aoff, (s * TT + a * T) * kEB) : make_float3(0.f, 0.f, 0.f);
+      for (int a = 0; a < 4; ++a) {
+        const f4 v = *reinterpret_cast<const f4*>(st + pp * kM4StRow + 4 * (s * 16 + a * 4 + x));
+        va[s][a] = make_float3(v[0], v[1], v[2]);
+      }
   };
 
   // lane x of a block holds row a = x of the pair's E: e[c][b] = (Re, Im) E[x][b]
@@ -732,12 +769,19 @@ __device__ void run_tile_m4(const QkTask& t, int ti, int tj, M4Smem& sm, uint32_
   for (int y = 0; y < NB; ++y) expo[y] = 0;
 
   __builtin_amdgcn_s_waitcnt(0x0F70);  // drain the previous tile's stores (vmcnt(0))
-  fetch_b(0);
+  fetch_stage(0);
   __builtin_amdgcn_sched_barrier(0);
-  fetch_a(0);
+  fetch_b(0);
   __builtin_amdgcn_sched_barrier(0);
   for (int k = 0; k < nq; ++k) {
     const int kn = k + 1 < nq ? k + 1 : k;
+    // this site's row operand: staged elements to the slot, the next site's
+    // staging loads in flight over the whole site, the lane's 8 elements
+    // read back (their latency hidden behind step R)
+    put_stage();
+    fetch_stage(kn);
+    read_a();
+    __builtin_amdgcn_sched_barrier(0);
     f4 g[NB][2][2];
 #pragma unroll
     for (int y = 0; y < NB; ++y) {
@@ -768,7 +812,6 @@ __device__ void run_tile_m4(const QkTask& t, int ti, int tj, M4Smem& sm, uint32_
               en[y][cp] = __builtin_amdgcn_mfma_f32_4x4x1f32(g[y][s][cin][a],
                                                              lhat(va[s][a], cp, cin), en[y][cp],
                                                              0, 0, 0);
-    fetch_a(kn);  // in flight until the next step L
     if ((k % kRescaleEvery) == kRescaleEvery - 1) {
       // power-of-two rescale of each pair (a block's four lanes), at the same
       // sites for every pair, so that a pair's result does not depend on its
@@ -824,13 +867,13 @@ __device__ void run_tile_m4(const QkTask& t, int ti, int tj, M4Smem& sm, uint32_
           const int64_t c = tj0 + smp - 16;
           if (c < t.nb) v = t.xc[c * t.ld_xc + f0 + f];
         }
-        sm.xs[smp * kXStride + f] = v;
+        sm.u.xs[smp * kXStride + f] = v;
       }
       __syncthreads();
-      const double* xrow = sm.xs + (4 * wr + pp) * kXStride;
+      const double* xrow = sm.u.xs + (4 * wr + pp) * kXStride;
 #pragma unroll
       for (int y = 0; y < NB; ++y) {
-        const double* xcol = sm.xs + (16 + 4 * (wc0 + y) + qq) * kXStride;
+        const double* xcol = sm.u.xs + (16 + 4 * (wc0 + y) + qq) * kXStride;
         double acc = 0.0;
         for (int f = x; f < nf; f += 4) {
           const double df = xrow[f] - xcol[f];
