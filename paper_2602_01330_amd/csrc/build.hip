@@ -65,6 +65,15 @@ __device__ inline double group_sum(double v, int lg) {
   return v;
 }
 
+// Orders the LDS accesses of one wavefront's lanes: LDS operations of a wave
+// execute in issue order, so waiting for this lane's own and keeping the
+// compiler from moving memory accesses across suffices within a wave.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt untouched
+  __builtin_amdgcn_wave_barrier();
+  __asm__ volatile("" ::: "memory");
+}
+
 // One-sided Jacobi on the columns of X (R rows x C columns, column-major in
 // LDS with leading dimension LD), accumulating V (C x C, column-major, LD).
 // On return the columns of X are mutually orthogonal and X_in V = X_out.
@@ -148,6 +157,65 @@ __device__ bool jacobi_columns(double2* X, double2* V, int R, int C, double floo
           V[p * LD + row] = make_double2(c * vp.x - s * vq.x, c * vp.y - s * vq.y);
           V[q * LD + row] = make_double2(s * vp.x + c * vq.x, s * vp.y + c * vq.y);
         }
+      }
+      rotated |= do_rot ? 1 : 0;
+      __syncthreads();
+    }
+    if (!__any(rotated)) return true;
+  }
+  return false;
+}
+
+// The same one-sided Jacobi for the common full-bond case, an 8 x 8 X (chi
+// = 4 on both sides of the merged pair) in LDS with leading dimension 8:
+// lanes 0..31 rotate the columns of X and lanes 32..63 apply the same
+// rotation to V in the same instructions, 8 lanes (one per row) per pair of
+// the round-robin tournament. Both halves read the pair's X columns and
+// reduce them in the same order, so their rotation parameters are
+// bit-identical; rotation rule, tolerance and sweep limit are those of
+// jacobi_columns.
+__device__ bool jacobi_8x8(double2* X, double2* V, double floor2) {
+  constexpr int kC = 8, kPlayers = kC - 1;
+  const int lane = threadIdx.x;
+  const int half = lane >> 5, pair = (lane >> 3) & 3, row = lane & 7;
+  double2* Y = half ? V : X;  // the matrix this lane rotates
+  const double tol = 1e-14;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rotated = 0;
+    for (int r = 0; r < kPlayers; ++r) {
+      int p, q;
+      if (pair == 0) {
+        p = 0;
+        q = 1 + r;
+      } else {
+        int u = r + pair, v = r - pair + kPlayers;
+        if (u >= kPlayers) u -= kPlayers;
+        if (v >= kPlayers) v -= kPlayers;
+        p = 1 + u;
+        q = 1 + v;
+      }
+      const double2 xp = X[p * kC + row], xq = X[q * kC + row];
+      double al = xp.x * xp.x + xp.y * xp.y;
+      double be = xq.x * xq.x + xq.y * xq.y;
+      double gr = xp.x * xq.x + xp.y * xq.y;  // conj(xp) * xq
+      double gi = xp.x * xq.y - xp.y * xq.x;
+      al = group_sum(al, 3);
+      be = group_sum(be, 3);
+      gr = group_sum(gr, 3);
+      gi = group_sum(gi, 3);
+      const double gabs2 = gr * gr + gi * gi;
+      const bool do_rot = al > floor2 && be > floor2 && gabs2 > tol * tol * (al * be);
+      if (do_rot) {
+        const double inv_gabs = rsqrt(gabs2);
+        const double zeta = 0.5 * (be - al) * inv_gabs;
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = rsqrt(1.0 + t * t);
+        const double sn = c * t;
+        const double2 ph = make_double2(gr * inv_gabs, -gi * inv_gabs);
+        const double2 yp = Y[p * kC + row];
+        const double2 yq = cmul(ph, Y[q * kC + row]);
+        Y[p * kC + row] = make_double2(c * yp.x - sn * yq.x, c * yp.y - sn * yq.y);
+        Y[q * kC + row] = make_double2(sn * yp.x + c * yq.x, sn * yp.y + c * yq.y);
       }
       rotated |= do_rot ? 1 : 0;
       __syncthreads();
@@ -261,7 +329,9 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
       }
       __syncthreads();
       for (int off = 1; off < 64; off <<= 1) fro += __shfl_xor(fro, off, 64);
-      bool conv = jacobi_columns<D>(sm.X, sm.V, XR, XCe, 1e-30 * fro);
+      const bool conv = (D == 8 && XR == 8 && XCe == 8)
+                            ? jacobi_8x8(sm.X, sm.V, 1e-30 * fro)
+                            : jacobi_columns<D>(sm.X, sm.V, XR, XCe, 1e-30 * fro);
       if (!conv && lane == 0) atomicOr(status, QK_FLAG_NOCONV);
       // singular values = column norms; rank them (descending, stable)
       if (lane < XCe) {
@@ -346,6 +416,368 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
   if (lane == 0) atomicMax(status + 1, chi_seen);
 }
 
+// ---------------------------------------------------------------------------
+// The same TEBD build for padded bond dimensions W <= 4, eight samples per
+// wavefront: the eight lanes of a sample each hold one row of the merged
+// matrix X (at most 2W <= 8 rows) and one row of V in registers. A Jacobi
+// rotation of a column pair then touches only the lane's own registers, and
+// the column dot products are 8-lane DPP sums, so a round needs no LDS
+// traffic and no barrier; every lane computes the rotation parameters of its
+// sample. One wave advances eight samples per instruction, where the
+// one-sample-per-wave kernel kept most lanes idle and ran several waves per
+// SIMD, each waiting for issue.
+//
+// Per sample the two sites of a step sit in LDS (two padded W x W x 2
+// buffers). The site carried over from the previous step stays there; the
+// next fresh site is loaded from memory one step ahead. A site gets its
+// single-qubit gate G_k = RZ(2 x_k) H when it is first loaded in a layer:
+// gates on other sites commute with the entangler of the merged pair and are
+// unitaries on one side of its cut, so the singular values, and hence the
+// truncation, are those of the gate-first order. The rotation rule,
+// tolerance, sweep limit, cutoff, chi cap, renormalisation and status flags
+// are those of mps_build_kernel.
+constexpr int kB8Lanes = 8;      // lanes per sample
+constexpr int kB8Samples = 8;    // samples per 64-lane workgroup
+
+template <int W>
+struct Build8Smem {
+  static constexpr int kSlot = 2 * W * W;  // [s][a][b]
+  double2 site[kB8Samples][2][kSlot];
+};
+
+// round-robin tournament of nc columns: pair k of round r
+__device__ constexpr int rr_p(int r, int k, int players) {
+  return k == 0 ? 0 : 1 + (r + k) % players;
+}
+__device__ constexpr int rr_q(int r, int k, int players) {
+  return k == 0 ? 1 + r : 1 + (r - k + players) % players;
+}
+
+// One-sided Jacobi over the nc (even) columns of X, rows in the 8 lanes of
+// each sample (lane holds xr[col]); V rows likewise (vr[col]). Returns
+// whether the sweeps converged for this lane's sample.
+template <int D, int NC>
+__device__ bool jacobi_rows(double2 (&xr)[D], double2 (&vr)[D], double floor2) {
+  constexpr int P = NC - 1, NP = NC / 2;
+  const double tol = 1e-14;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rotated = 0;
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      double al[NP], be[NP], gr[NP], gi[NP];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        const double2 xp = xr[rr_p(r, k, P)], xq = xr[rr_q(r, k, P)];
+        al[k] = xp.x * xp.x + xp.y * xp.y;
+        be[k] = xq.x * xq.x + xq.y * xq.y;
+        gr[k] = xp.x * xq.x + xp.y * xq.y;  // conj(xp) * xq
+        gi[k] = xp.x * xq.y - xp.y * xq.x;
+      }
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        al[k] = group_sum(al[k], 3);
+        be[k] = group_sum(be[k], 3);
+        gr[k] = group_sum(gr[k], 3);
+        gi[k] = group_sum(gi[k], 3);
+      }
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        const int p = rr_p(r, k, P), q = rr_q(r, k, P);
+        const double gabs2 = gr[k] * gr[k] + gi[k] * gi[k];
+        const bool do_rot =
+            al[k] > floor2 && be[k] > floor2 && gabs2 > tol * tol * (al[k] * be[k]);
+        if (do_rot) {
+          const double inv_gabs = rsqrt(gabs2);
+          const double zeta = 0.5 * (be[k] - al[k]) * inv_gabs;
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = rsqrt(1.0 + t * t);
+          const double sn = c * t;
+          const double2 ph = make_double2(gr[k] * inv_gabs, -gi[k] * inv_gabs);
+          const double2 xp = xr[p], xq = cmul(ph, xr[q]);
+          xr[p] = make_double2(c * xp.x - sn * xq.x, c * xp.y - sn * xq.y);
+          xr[q] = make_double2(sn * xp.x + c * xq.x, sn * xp.y + c * xq.y);
+          const double2 vp = vr[p], vq = cmul(ph, vr[q]);
+          vr[p] = make_double2(c * vp.x - sn * vq.x, c * vp.y - sn * vq.y);
+          vr[q] = make_double2(sn * vp.x + c * vq.x, sn * vp.y + c * vq.y);
+          rotated = 1;
+        }
+      }
+    }
+    if (!__any(rotated)) return true;
+    if (sweep == 59) return !rotated;
+  }
+  return true;
+}
+
+template <int W>
+__global__ __launch_bounds__(64) void mps_build8_kernel(
+    const double* __restrict__ x, int64_t ld_x, int64_t N, int nq, int n_layers,
+    int chi_max, int entangle, double cutoff, double2* __restrict__ t64,
+    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status) {
+  constexpr int D = 2 * W, TT = W * W, slot = 2 * TT;
+  __shared__ Build8Smem<W> sm;
+  const int lane = threadIdx.x;
+  const int g = lane >> 3, r = lane & 7;
+  const int64_t i0 = (int64_t)blockIdx.x * kB8Samples + g;
+  const bool live = i0 < N;
+  const int64_t i = live ? i0 : N - 1;  // idle groups shadow the last sample, writing nothing
+  const double* xi = x + i * ld_x;
+  int32_t* chi = chi_tab + i * (int64_t)(nq + 1);
+  auto site = [&](int k) -> double2* { return t64 + ((int64_t)k * N + i) * slot; };
+  double2 (*buf)[slot] = sm.site[g];
+
+  int bad = 0;
+  for (int k = r; k < nq; k += kB8Lanes) bad |= !isfinite(xi[k]);
+  if (live && bad) atomicOr(status, QK_FLAG_NONFINITE);
+  if (live)
+    for (int b = r; b <= nq; b += kB8Lanes) chi[b] = 1;
+  __syncthreads();
+
+  const double inv_sqrt2 = 0.70710678118654752440;
+  // lane r holds elements e = r + 8 m (m < ceil(TT / 8)) of both s of a site
+  constexpr int kPer = (TT + kB8Lanes - 1) / kB8Lanes;
+  double2 fresh[2][kPer];
+  auto load_site = [&](int k, int layer) {
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = r + kB8Lanes * m;
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        double2 v = make_double2(0.0, 0.0);
+        if (e < TT) {
+          if (layer == 0) v = make_double2((s2 == 0 && e == 0) ? 1.0 : 0.0, 0.0);  // |0>
+          else v = site(k)[s2 * TT + e];
+        }
+        fresh[s2][m] = v;
+      }
+    }
+  };
+  // G_k on the loaded site, into buffer b
+  auto put_site = [&](int b, double xk) {
+    double sn, cs;
+    sincos(xk, &sn, &cs);
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = r + kB8Lanes * m;
+      if (e < TT) {
+        const double2 a0 = fresh[0][m], a1 = fresh[1][m];
+        const double2 u = cscale(cadd(a0, a1), inv_sqrt2);
+        const double2 v = cscale(make_double2(a0.x - a1.x, a0.y - a1.y), inv_sqrt2);
+        buf[b][e] = cmul(make_double2(cs, -sn), u);
+        buf[b][TT + e] = cmul(make_double2(cs, sn), v);
+      }
+    }
+  };
+
+  int chi_seen = 1, noconv = 0, over = 0;
+  for (int layer = 0; layer < n_layers; ++layer) {
+    const bool l2r = (layer % 2) == 0;
+    // bond dimension before this layer's step rewrote it (all 1 before the
+    // first layer; the boundary bonds are always 1)
+    auto old_chi = [&](int b) -> int { return (layer == 0 || b <= 0 || b >= nq) ? 1 : chi[b]; };
+    // buffer lb holds the step's left site, 1 - lb its right site
+    int lb = 0;
+    const int k0 = l2r ? 0 : nq - 2;
+    load_site(k0, layer);
+    put_site(0, xi[k0]);
+    load_site(k0 + 1, layer);
+    put_site(1, xi[k0 + 1]);
+    // bonds of a step: `carry` (the near side, rewritten by the previous
+    // step), `mid` (the merged bond) and `far`, both from the previous layer
+    int carry = 1;
+    int mid = old_chi(k0 + 1);
+    int far = old_chi(l2r ? k0 + 2 : k0);
+    double xl = xi[k0], xrr = xi[k0 + 1];  // features of the step's two sites
+    wave_lds_sync();
+    for (int step = 0; step < nq - 1; ++step) {
+      const int k = l2r ? step : (nq - 2 - step);
+      const bool more = step + 1 < nq - 1;
+      const int cl = l2r ? carry : far, cm = mid, cr = l2r ? far : carry;
+      // the next step's fresh site, its feature and its far bond load during
+      // this step
+      const int kf = l2r ? k + 2 : k - 1;
+      int far_next = 1;
+      double x_next = 0.0;
+      if (more) {
+        load_site(kf, layer);
+        x_next = xi[kf];
+        far_next = old_chi(l2r ? k + 3 : k - 1);
+      }
+      double theta = 0.0;
+      if (entangle) theta = 2.0 * (kPi - xl) * (kPi - xrr);
+      double sh, ch;
+      sincos(0.5 * theta, &sh, &ch);
+
+      double2* Lo = buf[lb];
+      double2* Ro = buf[1 - lb];
+      const int R = 2 * cl, C = 2 * cr;
+      const bool tr = C > R;  // factor Theta^dagger when it is wide
+      const int XR = tr ? C : R, XC = tr ? R : C;
+      // lane r forms row r of X: X = Theta, or X = Theta^dagger, where
+      // Theta[(s,a)][(t,c)] = phase(s,t) sum_b L[s][a][b] R[t][b][c]
+      double2 xr[D], vr[D];
+      double fro = 0.0;
+#pragma unroll
+      for (int col = 0; col < D; ++col) {
+        double2 acc = make_double2(0.0, 0.0);
+        if (r < XR && col < XC) {
+          const int rs = tr ? col : r, cs2 = tr ? r : col;  // Theta row, column
+          const int s = rs / cl, a = rs - s * cl, t = cs2 / cr, c = cs2 - t * cr;
+          (void)cm;  // entries past the merged bond are zero in the buffers
+#pragma unroll
+          for (int b = 0; b < W; ++b)
+            acc = cadd(acc, cmul(Lo[s * TT + a * W + b], Ro[t * TT + b * W + c]));
+          // exp(-i theta/2 sigma_s sigma_t)
+          acc = cmul((s == t) ? make_double2(ch, -sh) : make_double2(ch, sh), acc);
+          if (tr) acc.y = -acc.y;
+        }
+        xr[col] = acc;
+        fro += acc.x * acc.x + acc.y * acc.y;
+        vr[col] = make_double2((col == r && col < XC) ? 1.0 : 0.0, 0.0);
+      }
+      fro = group_sum(fro, 3);
+      // column count over the wave's samples, rounded to a compiled width
+      int nc = XC;
+      nc = max(nc, __shfl_xor(nc, 8, 64));
+      nc = max(nc, __shfl_xor(nc, 16, 64));
+      nc = max(nc, __shfl_xor(nc, 32, 64));
+      const double floor2 = 1e-30 * fro;
+      bool conv;
+      if (nc <= 2) conv = jacobi_rows<D, (D < 2 ? D : 2)>(xr, vr, floor2);
+      else if (nc <= 4 || D <= 4) conv = jacobi_rows<D, (D < 4 ? D : 4)>(xr, vr, floor2);
+      else if (nc <= 6 || D <= 6) conv = jacobi_rows<D, (D < 6 ? D : 6)>(xr, vr, floor2);
+      else conv = jacobi_rows<D, D>(xr, vr, floor2);
+      noconv |= conv ? 0 : 1;
+      // singular values = column norms (every lane); rank descending, stable
+      double S[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        S[j] = sqrt(group_sum(xr[j].x * xr[j].x + xr[j].y * xr[j].y, 3));
+      int rk[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        int ahead = 0;
+#pragma unroll
+        for (int o = 0; o < D; ++o) ahead += (S[o] > S[j]) || (S[o] == S[j] && o < j);
+        rk[j] = (j < XC) ? ahead : D;  // padding columns are never kept
+      }
+      double s_at[D];  // singular values in rank order
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) v = rk[j] == q ? S[j] : v;
+        s_at[q] = v;
+      }
+      const int kmax = XC < chi_max ? XC : chi_max;
+      int keep = 0;
+      double norm2 = 0.0;
+      bool run = true;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        if (run && q < kmax && (q == 0 || s_at[q] > cutoff * s_at[0])) {
+          ++keep;
+          norm2 += s_at[q] * s_at[q];
+        } else {
+          run = false;
+        }
+      }
+      if (keep > W) {
+        over = 1;
+        keep = W;
+        norm2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) norm2 += s_at[q] * s_at[q];
+      }
+      const double inv_norm = norm2 > 0.0 ? 1.0 / sqrt(norm2) : 0.0;
+      if (keep > chi_seen) chi_seen = keep;
+      // Factors back into the two buffers (padded layout), S absorbed to the
+      // right (l2r) or left, renormalised:
+      //   no transpose: Lf[:,j] = X[:,pj]/S_pj, Rf[j,:] = conj(V[:,pj])
+      //   transpose   : Lf[:,j] = V[:,pj],     Rf[j,:] = conj(X[:,pj])/S_pj
+      // Padding rows (a >= cl) of the left site and padding columns (c >= cr)
+      // of the right site are zeroed by the lane of that padded index.
+      if (r < D) {
+        const int sp = r / W, ap = r - sp * W;
+        if (ap >= cl)
+#pragma unroll
+          for (int j = 0; j < W; ++j) Lo[sp * TT + ap * W + j] = make_double2(0.0, 0.0);
+        if (ap >= cr)
+#pragma unroll
+          for (int j = 0; j < W; ++j) Ro[sp * TT + j * W + ap] = make_double2(0.0, 0.0);
+      }
+      if (r < R) {  // row r of Lf: lane r holds X row r (or V row r)
+        const int s = r / cl, a = r - s * cl;
+        double2* row = Lo + s * TT + a * W;
+        for (int j = keep; j < W; ++j) row[j] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const int j = rk[c];
+          if (j < keep) {
+            const double Sj = S[c];
+            double2 u;
+            if (!tr) u = Sj > 0.0 ? cscale(xr[c], 1.0 / Sj) : make_double2(0.0, 0.0);
+            else u = vr[c];
+            row[j] = l2r ? u : cscale(u, Sj * inv_norm);
+          }
+        }
+      }
+      if (r < C) {  // column r of Rf: lane r holds V row r (or X row r)
+        const int t = r / cr, c = r - t * cr;
+        double2* colp = Ro + t * TT + c;
+        for (int j = keep; j < W; ++j) colp[j * W] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int cc = 0; cc < D; ++cc) {
+          const int j = rk[cc];
+          if (j < keep) {
+            const double Sj = S[cc];
+            double2 h;
+            if (!tr) h = make_double2(vr[cc].x, -vr[cc].y);
+            else h = Sj > 0.0 ? make_double2(xr[cc].x / Sj, -xr[cc].y / Sj) : make_double2(0.0, 0.0);
+            colp[j * W] = l2r ? cscale(h, Sj * inv_norm) : h;
+          }
+        }
+      }
+      wave_lds_sync();
+      if (live) {  // both sites and the bond to memory
+        double2* gl = site(k);
+        double2* gr2 = site(k + 1);
+        for (int e = r; e < slot; e += kB8Lanes) {
+          gl[e] = Lo[e];
+          gr2[e] = Ro[e];
+        }
+        if (r == 0) chi[k + 1] = keep;
+      }
+      // Next step: the site factored on the near side stays; the fresh site
+      // (gated) replaces the finished one and becomes the other side.
+      if (more) {
+        if (l2r) {
+          put_site(lb, x_next);  // site k is done: fresh site k+2 in its buffer
+          lb = 1 - lb;           // site k+1 (old right) is the new left site
+          xl = xrr;
+          xrr = x_next;
+        } else {
+          put_site(1 - lb, x_next);  // site k+1 is done: fresh site k-1 there
+          lb = 1 - lb;               // ... as the new left; site k is the right one
+          xrr = xl;
+          xl = x_next;
+        }
+        carry = keep;
+        mid = far;
+        far = far_next;
+      }
+      wave_lds_sync();
+    }
+    // the next layer reads this layer's sites and bonds from memory
+    __syncthreads();
+  }
+  if (live && r == 0) {
+    if (noconv) atomicOr(status, QK_FLAG_NOCONV);
+    if (over) atomicOr(status, QK_FLAG_CHI_OVER);
+    atomicMax(status + 1, chi_seen);
+  }
+}
+
 // FP64 complex -> packed FP32 (-Im, Re, Im)
 __global__ void pack32_kernel(const double2* __restrict__ a, float* __restrict__ b,
                               int64_t count) {
@@ -368,6 +800,22 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
                            double cutoff, int chi_ws, int T, double2* t64,
                            int32_t* chi, int32_t* status, hipStream_t s) {
   if (n == 0) return hipSuccess;
+  if (nq >= 2 && (T == 1 || T == 2 || T == 4)) {
+    const dim3 grid8((unsigned)((n + kB8Samples - 1) / kB8Samples)), block8(64);
+#define QK_BUILD8_CASE(WV)                                                    \
+  case WV:                                                                    \
+    hipLaunchKernelGGL(mps_build8_kernel<WV>, grid8, block8, 0, s, x, ld_x,   \
+                       n, nq, n_layers, chi_max, entangle, cutoff, t64, chi,  \
+                       status);                                               \
+    break;
+    switch (T) {
+      QK_BUILD8_CASE(1)
+      QK_BUILD8_CASE(2)
+      QK_BUILD8_CASE(4)
+    }
+#undef QK_BUILD8_CASE
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)n), block(64);
 #define QK_BUILD_CASE(WV)                                                     \
   case WV:                                                                    \

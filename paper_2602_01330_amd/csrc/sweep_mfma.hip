@@ -2,48 +2,50 @@
 //
 // Per pair (i, j) and site k:  E' = sum_s A_i^{s dagger} E B_j^s  (E is 4 x 4
 // complex). Complex products are realified, [Re C | Im C] = [Re X | Im X] .
-// [[Re Y, Im Y], [-Im Y, Re Y]], and each site is two GEMM-shaped steps:
+// [[Re Y, Im Y], [-Im Y, Re Y]]. Two kernels:
 //
+// * FP32 (sweep_m4_kernel, further below): both steps of a site on the
+//   4 x 4 x 1 block MFMA, one block per pair, E and G kept in registers; see
+//   the comment above that kernel.
+//
+// * Split BF16 (sweep_mfma_kernel): each site is two GEMM-shaped steps on
+//   16 x 16 MFMAs,
 //   step R (right multiply, shared by the pairs of one column j):
 //     G[(p,a)][(s,c,b')] = sum_{(c_in,b)} E[(p,a)][(c_in,b)] Bhat_j[(c_in,b)][(s,c,b')]
-//     16 x 16 x 8 per column of four pairs -> two 16x16x4 MFMAs, every lane busy;
+//     16 x 16 x 8 per column of four pairs, every lane busy;
 //   step L (left multiply, shared by the pairs of one row i):
 //     E'[(c',a')][(q,b')] = sum_{(s,c_in,a)} Ahat_i[(c',a')][(s,c_in,a)] G[(s,c_in,a)][(q,b')]
-//     8 x 16 x 16 per row of four pairs -> four 16x16x4 MFMAs whose rows 8..15 are
-//     zero: chi = 4 gives only 8 realified output rows, so this step runs the
-//     matrix cores at half width (the ceiling of the whole sweep is 2/3 of
-//     the MFMA peak at chi = 4).
+//     8 x 16 x 16 per row of four pairs, whose rows 8..15 are zero: chi = 4
+//     gives only 8 realified output rows, so this step runs the matrix cores
+//     at half width (the ceiling of this kernel is 2/3 of the MFMA peak).
+//   A wavefront owns a 4 x 4 block of pairs and runs its whole chain of
+//   sites without workgroup barriers. Every lane loads its own operand values
+//   of the next site with buffer loads (prefetched one site ahead, straight
+//   into the operand registers; the 16 waves of a workgroup share the 16 row
+//   and 16 column samples of a 16 x 16 tile, so repeats hit the CU's L1). The
+//   two re-layouts between the steps (MFMA output -> operand of the other
+//   step) go through a per-wave LDS area. Every packed element holds z and
+//   i z (one extra float), each lane loads the form its output part needs,
+//   and E enters step R as (Im E, Re E) so that the one negated entry of the
+//   realified product falls on the i z form.
+//   The operands are split into BF16 pieces for v_mfma_f32_16x16x32_bf16
+//   with FP32 accumulation -- BF16x2: x = h + l with round-to-nearest pieces
+//   (|x - h - l| <= 2^-18 |x|), the products hh, hl, lh, ll; BF16x3:
+//   x = h + m + l exactly (8+8+8 bits), the products of total order <= 2 plus
+//   m*l and l*m (8 per real product). The split is folded into the
+//   contraction index, so one MFMA K of 32 covers four (BF16x2) or eight
+//   (BF16x3) products of each FP32 term.
 //
-// A wavefront owns a 4 x 4 block of pairs and runs its whole chain of sites
-// without workgroup barriers. Every lane loads its own operand values of the
-// next site with buffer loads (prefetched one site ahead, straight into the
-// operand registers; the 16 waves of a workgroup share the 16 row and 16
-// column samples of a 16 x 16 tile, so repeats hit the CU's L1). Offsets past
-// a site array's end read as zero in hardware, which pads bond blocks smaller
-// than 4 x 4 and the zero rows of step L without any per-element select. The
-// two re-layouts between the steps (MFMA output -> operand of the other step)
-// go through a per-wave LDS area. Each pair's E is scaled by an exact power
-// of two every kRescaleEvery sites (per-pair int32 exponent).
-//
-// On gfx950 plain VALU instructions do not overlap the FP32 MFMAs of the
-// same SIMD, so the loop keeps per-site VALU work small. The realified
-// operand forms need no arithmetic: every packed element holds z and i z
-// (one extra float), each lane loads the form its output part needs, and E
-// enters step R as (Im E, Re E) so that the one negated entry of the
-// realified product falls on the i z form. Addresses come from a per-site
-// buffer descriptor (scalar) plus constant per-lane offsets, and the rescale
-// reduces bit patterns with DPP.
-//
-// Forms: FP32 operands on v_mfma_f32_16x16x4f32; or split BF16 on
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation -- BF16x2: x = h + l with
-// round-to-nearest pieces (|x - h - l| <= 2^-18 |x|), the products hh, hl,
-// lh, ll; BF16x3: x = h + m + l exactly (8+8+8 bits), the
-// products of total order <= 2 plus m*l and l*m (8 per real product). The
-// split is folded into the contraction index, so one MFMA K of 32 covers four
-// (BF16x2) or eight (BF16x3) products of each FP32 term.
+// Common to both: addresses come from a per-site buffer descriptor (scalar)
+// plus constant per-lane offsets; offsets past a site array's end read as
+// zero in hardware, which pads bond blocks smaller than 4 x 4 without any
+// per-element select. On gfx950 plain VALU instructions do not overlap the
+// FP32 MFMAs of the same SIMD, so the site loops keep VALU work small. Each
+// pair's E is scaled by an exact power of two every kRescaleEvery sites
+// (per-pair int32 exponent), at the same sites for every pair.
 //
 // Reduced-precision forms mark every pair whose K_q exceeds a threshold;
-// the FP64 sweep (qk_launch_sweep_fp64 with the masks) recomputes the tiles
+// the FP64 sweep (the refinement pass with the masks) recomputes the tiles
 // holding marked pairs and writes exactly those pairs, so that entries near
 // 1 carry FP64 accuracy.
 #include <hip/hip_runtime.h>
@@ -55,7 +57,7 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-enum Form { kF32 = 0, kBF16x2 = 1, kBF16x3 = 2 };
+enum Form { kBF16x2 = 1, kBF16x3 = 2 };  // split-BF16 forms of the 16 x 16 kernel
 
 // A wave owns kColBlocks 4 x 4 pair blocks side by side (same four rows):
 // the row operands and their forms are loaded and built once for all of them.
@@ -169,59 +171,12 @@ __device__ constexpr int rhs_piece3(int t) {                        // 0 1 0 2 1
   return t == 0 ? 0 : t == 1 ? 1 : t == 2 ? 0 : t == 3 ? 2 : t == 4 ? 1 : t == 5 ? 0 : t == 6 ? 2 : 1;
 }
 
-// acc += sum over NC FP32 contraction chunks: a[c] (lane's A value) * b[c]
-// (lane's B value), in the 16x16x4 lane layout; for the split forms the
-// chunks and product terms are folded into 16x16x32 instructions.
-template <int F, int NC>
-__device__ inline f4 mma(const float* a, const float* b, f4 acc) {
-  if constexpr (F == kF32) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b[c], acc, 0, 0, 0);
-  } else if constexpr (F == kBF16x2) {
-    // 4 products per chunk -> 2 chunks per instruction
-#pragma unroll
-    for (int c0 = 0; c0 < NC; c0 += 2) {
-      bf8 va, vb;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        Split<kBF16x2> sa(a[c0 + h]), sb(b[c0 + h]);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          va[h * 4 + t] = sa.p[lhs_piece2(t)];
-          vb[h * 4 + t] = sb.p[rhs_piece2(t)];
-        }
-      }
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, acc, 0, 0, 0);
-    }
-  } else {
-    // 8 products per chunk -> one chunk per instruction
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      bf8 va, vb;
-      Split<kBF16x3> sa(a[c]), sb(b[c]);
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        va[t] = sa.p[lhs_piece3(t)];
-        vb[t] = sb.p[rhs_piece3(t)];
-      }
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, acc, 0, 0, 0);
-    }
-  }
-  return acc;
-}
-
 // acc[x] += sum over NC chunks of a[x][c] * b[x][c] for four independent
 // products x, issued chunk-major so consecutive MFMAs never depend on each
 // other.
 template <int F, int NC>
 __device__ inline void mma4(const float (*a)[NC], const float (*b)[NC], f4* acc) {
-  if constexpr (F == kF32) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-        acc[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x][c], b[x][c], acc[x], 0, 0, 0);
-  } else if constexpr (F == kBF16x2) {
+  if constexpr (F == kBF16x2) {
 #pragma unroll
     for (int c0 = 0; c0 < NC; c0 += 2) {
       bf8 va[4], vb[4];
