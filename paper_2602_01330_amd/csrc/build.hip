@@ -509,6 +509,108 @@ __device__ bool jacobi_rows(double2 (&xr)[D], double2 (&vr)[D], double floor2) {
   return true;
 }
 
+// Per step after X (rows in lanes) and V = I are formed: the Jacobi
+// rotations over the wave's NC columns, the singular values and their
+// descending stable order, the kept count (cutoff, chi cap, padded bound) and
+// the two factors written back into the padded LDS buffers Lo (left site
+// [s][a][j]) and Ro (right site [t][j][c]), S absorbed to the right (l2r) or
+// left and renormalised:
+//   no transpose: Lf[:,j] = X[:,pj]/S_pj, Rf[j,:] = conj(V[:,pj])
+//   transpose   : Lf[:,j] = V[:,pj],     Rf[j,:] = conj(X[:,pj])/S_pj
+// Returns the kept count.
+template <int W, int NC>
+__device__ int b8_factor(double2 (&xr)[2 * W], double2 (&vr)[2 * W], double floor2, int r,
+                         int XC, int cl, int cr, bool tr, bool l2r, int chi_max, double cutoff,
+                         double2* Lo, double2* Ro, int& noconv, int& over) {
+  constexpr int D = 2 * W, TT = W * W;
+  const bool conv = jacobi_rows<D, NC>(xr, vr, floor2);
+  noconv |= conv ? 0 : 1;
+  // singular values = column norms (every lane); rank descending, stable
+  double S[NC], inv_S[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    S[j] = sqrt(group_sum(xr[j].x * xr[j].x + xr[j].y * xr[j].y, 3));
+    inv_S[j] = S[j] > 0.0 ? 1.0 / S[j] : 0.0;
+  }
+  int rk[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    int ahead = 0;
+#pragma unroll
+    for (int o = 0; o < NC; ++o) ahead += (S[o] > S[j]) || (S[o] == S[j] && o < j);
+    rk[j] = (j < XC) ? ahead : D;  // padding columns are never kept
+  }
+  double s_at[NC];  // singular values in rank order
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) v = rk[j] == q ? S[j] : v;
+    s_at[q] = v;
+  }
+  const int kmax = XC < chi_max ? XC : chi_max;
+  int keep = 0;
+  double norm2 = 0.0;
+  bool run = true;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    if (run && q < kmax && (q == 0 || s_at[q] > cutoff * s_at[0])) {
+      ++keep;
+      norm2 += s_at[q] * s_at[q];
+    } else {
+      run = false;
+    }
+  }
+  if (keep > W) {
+    over = 1;
+    keep = W;
+    norm2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < (NC < W ? NC : W); ++q) norm2 += s_at[q] * s_at[q];
+  }
+  const double inv_norm = norm2 > 0.0 ? 1.0 / sqrt(norm2) : 0.0;
+  const int R = 2 * cl, C = 2 * cr;
+  // padding rows (a >= cl) of the left site and padding columns (c >= cr) of
+  // the right site, zeroed by the lane of that padded index
+  if (r < D) {
+    const int sp = r >= W ? 1 : 0, ap = r - sp * W;
+    if (ap >= cl)
+#pragma unroll
+      for (int j = 0; j < W; ++j) Lo[sp * TT + ap * W + j] = make_double2(0.0, 0.0);
+    if (ap >= cr)
+#pragma unroll
+      for (int j = 0; j < W; ++j) Ro[sp * TT + j * W + ap] = make_double2(0.0, 0.0);
+  }
+  if (r < R) {  // row r of Lf: lane r holds X row r (or V row r)
+    const int s = r >= cl ? 1 : 0, a = r - s * cl;
+    double2* row = Lo + s * TT + a * W;
+    for (int j = keep; j < W; ++j) row[j] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int j = rk[c];
+      if (j < keep) {
+        const double2 u = tr ? vr[c] : cscale(xr[c], inv_S[c]);
+        row[j] = l2r ? u : cscale(u, S[c] * inv_norm);
+      }
+    }
+  }
+  if (r < C) {  // column r of Rf: lane r holds V row r (or X row r)
+    const int t = r >= cr ? 1 : 0, c = r - t * cr;
+    double2* colp = Ro + t * TT + c;
+    for (int j = keep; j < W; ++j) colp[j * W] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      const int j = rk[cc];
+      if (j < keep) {
+        const double2 h = tr ? make_double2(xr[cc].x * inv_S[cc], -xr[cc].y * inv_S[cc])
+                             : make_double2(vr[cc].x, -vr[cc].y);
+        colp[j * W] = l2r ? cscale(h, S[cc] * inv_norm) : h;
+      }
+    }
+  }
+  return keep;
+}
+
 template <int W>
 __global__ __launch_bounds__(64) void mps_build8_kernel(
     const double* __restrict__ x, int64_t ld_x, int64_t N, int nq, int n_layers,
@@ -553,9 +655,7 @@ __global__ __launch_bounds__(64) void mps_build8_kernel(
     }
   };
   // G_k on the loaded site, into buffer b
-  auto put_site = [&](int b, double xk) {
-    double sn, cs;
-    sincos(xk, &sn, &cs);
+  auto put_site = [&](int b, double sn, double cs) {  // sincos of the site's feature
 #pragma unroll
     for (int m = 0; m < kPer; ++m) {
       const int e = r + kB8Lanes * m;
@@ -575,38 +675,52 @@ __global__ __launch_bounds__(64) void mps_build8_kernel(
     // bond dimension before this layer's step rewrote it (all 1 before the
     // first layer; the boundary bonds are always 1)
     auto old_chi = [&](int b) -> int { return (layer == 0 || b <= 0 || b >= nq) ? 1 : chi[b]; };
+    // the site that a step loads fresh, and its feature
+    auto fresh_of = [&](int k) -> int { return l2r ? k + 2 : k - 1; };
     // buffer lb holds the step's left site, 1 - lb its right site
     int lb = 0;
     const int k0 = l2r ? 0 : nq - 2;
-    load_site(k0, layer);
-    put_site(0, xi[k0]);
-    load_site(k0 + 1, layer);
-    put_site(1, xi[k0 + 1]);
+    double xl = xi[k0], xrr = xi[k0 + 1];  // features of the step's two sites
+    {
+      double sn, cs;
+      load_site(k0, layer);
+      sincos(xl, &sn, &cs);
+      put_site(0, sn, cs);
+      load_site(k0 + 1, layer);
+      sincos(xrr, &sn, &cs);
+      put_site(1, sn, cs);
+    }
     // bonds of a step: `carry` (the near side, rewritten by the previous
     // step), `mid` (the merged bond) and `far`, both from the previous layer
     int carry = 1;
     int mid = old_chi(k0 + 1);
     int far = old_chi(l2r ? k0 + 2 : k0);
-    double xl = xi[k0], xrr = xi[k0 + 1];  // features of the step's two sites
+    (void)mid;  // bond entries past the merged bond are zero in the buffers
+    // the entangler phase of a step and the feature of its fresh site are
+    // known a step ahead, so their sines and cosines overlap other work
+    double sh = 0.0, ch = 1.0;
+    if (entangle) sincos((kPi - xl) * (kPi - xrr), &sh, &ch);  // theta / 2
+    double xq = nq > 2 ? xi[fresh_of(k0)] : 0.0;
     wave_lds_sync();
     for (int step = 0; step < nq - 1; ++step) {
       const int k = l2r ? step : (nq - 2 - step);
       const bool more = step + 1 < nq - 1;
-      const int cl = l2r ? carry : far, cm = mid, cr = l2r ? far : carry;
-      // the next step's fresh site, its feature and its far bond load during
-      // this step
-      const int kf = l2r ? k + 2 : k - 1;
+      const int cl = l2r ? carry : far, cr = l2r ? far : carry;
+      // next step's fresh site (loaded during this step), its gate and the
+      // next entangler phase; the feature of the fresh site after that
+      const int kf = fresh_of(k);
       int far_next = 1;
-      double x_next = 0.0;
+      double g_sn = 0.0, g_cs = 1.0, n_sh = 0.0, n_ch = 1.0, xq_next = 0.0;
       if (more) {
         load_site(kf, layer);
-        x_next = xi[kf];
         far_next = old_chi(l2r ? k + 3 : k - 1);
+        if (step + 2 < nq - 1) xq_next = xi[fresh_of(l2r ? k + 1 : k - 1)];
+        sincos(xq, &g_sn, &g_cs);
+        if (entangle) {
+          const double xa = l2r ? xrr : xq, xb = l2r ? xq : xl;
+          sincos((kPi - xa) * (kPi - xb), &n_sh, &n_ch);
+        }
       }
-      double theta = 0.0;
-      if (entangle) theta = 2.0 * (kPi - xl) * (kPi - xrr);
-      double sh, ch;
-      sincos(0.5 * theta, &sh, &ch);
 
       double2* Lo = buf[lb];
       double2* Ro = buf[1 - lb];
@@ -614,7 +728,7 @@ __global__ __launch_bounds__(64) void mps_build8_kernel(
       const bool tr = C > R;  // factor Theta^dagger when it is wide
       const int XR = tr ? C : R, XC = tr ? R : C;
       // lane r forms row r of X: X = Theta, or X = Theta^dagger, where
-      // Theta[(s,a)][(t,c)] = phase(s,t) sum_b L[s][a][b] R[t][b][c]
+      // Theta[(s,a)][(t,c)] = exp(-i theta/2 sigma_s sigma_t) sum_b L[s][a][b] R[t][b][c]
       double2 xr[D], vr[D];
       double fro = 0.0;
 #pragma unroll
@@ -622,12 +736,11 @@ __global__ __launch_bounds__(64) void mps_build8_kernel(
         double2 acc = make_double2(0.0, 0.0);
         if (r < XR && col < XC) {
           const int rs = tr ? col : r, cs2 = tr ? r : col;  // Theta row, column
-          const int s = rs / cl, a = rs - s * cl, t = cs2 / cr, c = cs2 - t * cr;
-          (void)cm;  // entries past the merged bond are zero in the buffers
+          const int s = rs >= cl ? 1 : 0, a = rs - s * cl;
+          const int t = cs2 >= cr ? 1 : 0, c = cs2 - t * cr;
 #pragma unroll
           for (int b = 0; b < W; ++b)
             acc = cadd(acc, cmul(Lo[s * TT + a * W + b], Ro[t * TT + b * W + c]));
-          // exp(-i theta/2 sigma_s sigma_t)
           acc = cmul((s == t) ? make_double2(ch, -sh) : make_double2(ch, sh), acc);
           if (tr) acc.y = -acc.y;
         }
@@ -642,129 +755,63 @@ __global__ __launch_bounds__(64) void mps_build8_kernel(
       nc = max(nc, __shfl_xor(nc, 16, 64));
       nc = max(nc, __shfl_xor(nc, 32, 64));
       const double floor2 = 1e-30 * fro;
-      bool conv;
-      if (nc <= 2) conv = jacobi_rows<D, (D < 2 ? D : 2)>(xr, vr, floor2);
-      else if (nc <= 4 || D <= 4) conv = jacobi_rows<D, (D < 4 ? D : 4)>(xr, vr, floor2);
-      else if (nc <= 6 || D <= 6) conv = jacobi_rows<D, (D < 6 ? D : 6)>(xr, vr, floor2);
-      else conv = jacobi_rows<D, D>(xr, vr, floor2);
-      noconv |= conv ? 0 : 1;
-      // singular values = column norms (every lane); rank descending, stable
-      double S[D];
-#pragma unroll
-      for (int j = 0; j < D; ++j)
-        S[j] = sqrt(group_sum(xr[j].x * xr[j].x + xr[j].y * xr[j].y, 3));
-      int rk[D];
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        int ahead = 0;
-#pragma unroll
-        for (int o = 0; o < D; ++o) ahead += (S[o] > S[j]) || (S[o] == S[j] && o < j);
-        rk[j] = (j < XC) ? ahead : D;  // padding columns are never kept
-      }
-      double s_at[D];  // singular values in rank order
-#pragma unroll
-      for (int q = 0; q < D; ++q) {
-        double v = 0.0;
-#pragma unroll
-        for (int j = 0; j < D; ++j) v = rk[j] == q ? S[j] : v;
-        s_at[q] = v;
-      }
-      const int kmax = XC < chi_max ? XC : chi_max;
-      int keep = 0;
-      double norm2 = 0.0;
-      bool run = true;
-#pragma unroll
-      for (int q = 0; q < D; ++q) {
-        if (run && q < kmax && (q == 0 || s_at[q] > cutoff * s_at[0])) {
-          ++keep;
-          norm2 += s_at[q] * s_at[q];
-        } else {
-          run = false;
-        }
-      }
-      if (keep > W) {
-        over = 1;
-        keep = W;
-        norm2 = 0.0;
-#pragma unroll
-        for (int q = 0; q < W; ++q) norm2 += s_at[q] * s_at[q];
-      }
-      const double inv_norm = norm2 > 0.0 ? 1.0 / sqrt(norm2) : 0.0;
+      int keep;
+      if (nc <= 2)
+        keep = b8_factor<W, 2>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over);
+      else if (nc <= 4 || D <= 4)
+        keep = b8_factor<W, (D < 4 ? D : 4)>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over);
+      else if (nc <= 6 || D <= 6)
+        keep = b8_factor<W, (D < 6 ? D : 6)>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over);
+      else
+        keep = b8_factor<W, D>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over);
       if (keep > chi_seen) chi_seen = keep;
-      // Factors back into the two buffers (padded layout), S absorbed to the
-      // right (l2r) or left, renormalised:
-      //   no transpose: Lf[:,j] = X[:,pj]/S_pj, Rf[j,:] = conj(V[:,pj])
-      //   transpose   : Lf[:,j] = V[:,pj],     Rf[j,:] = conj(X[:,pj])/S_pj
-      // Padding rows (a >= cl) of the left site and padding columns (c >= cr)
-      // of the right site are zeroed by the lane of that padded index.
-      if (r < D) {
-        const int sp = r / W, ap = r - sp * W;
-        if (ap >= cl)
+      wave_lds_sync();
+      // The finished site goes to memory (the carried one too on the layer's
+      // last step). Its LDS values are read first, then the fresh site takes
+      // its buffer, then the stores issue: waiting for the fresh site's loads
+      // never has to wait for stores.
+      const int kdone = l2r ? k : k + 1;
+      const double2* done = l2r ? Lo : Ro;
+      const double2* kept = l2r ? Ro : Lo;
+      constexpr int kOut = (slot + kB8Lanes - 1) / kB8Lanes;
+      double2 vd[kOut], vk[kOut];
 #pragma unroll
-          for (int j = 0; j < W; ++j) Lo[sp * TT + ap * W + j] = make_double2(0.0, 0.0);
-        if (ap >= cr)
-#pragma unroll
-          for (int j = 0; j < W; ++j) Ro[sp * TT + j * W + ap] = make_double2(0.0, 0.0);
-      }
-      if (r < R) {  // row r of Lf: lane r holds X row r (or V row r)
-        const int s = r / cl, a = r - s * cl;
-        double2* row = Lo + s * TT + a * W;
-        for (int j = keep; j < W; ++j) row[j] = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-          const int j = rk[c];
-          if (j < keep) {
-            const double Sj = S[c];
-            double2 u;
-            if (!tr) u = Sj > 0.0 ? cscale(xr[c], 1.0 / Sj) : make_double2(0.0, 0.0);
-            else u = vr[c];
-            row[j] = l2r ? u : cscale(u, Sj * inv_norm);
-          }
-        }
-      }
-      if (r < C) {  // column r of Rf: lane r holds V row r (or X row r)
-        const int t = r / cr, c = r - t * cr;
-        double2* colp = Ro + t * TT + c;
-        for (int j = keep; j < W; ++j) colp[j * W] = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int cc = 0; cc < D; ++cc) {
-          const int j = rk[cc];
-          if (j < keep) {
-            const double Sj = S[cc];
-            double2 h;
-            if (!tr) h = make_double2(vr[cc].x, -vr[cc].y);
-            else h = Sj > 0.0 ? make_double2(xr[cc].x / Sj, -xr[cc].y / Sj) : make_double2(0.0, 0.0);
-            colp[j * W] = l2r ? cscale(h, Sj * inv_norm) : h;
-          }
-        }
+      for (int m = 0; m < kOut; ++m) {
+        const int e = r + kB8Lanes * m;
+        vd[m] = e < slot ? done[e] : make_double2(0.0, 0.0);
+        vk[m] = (!more && e < slot) ? kept[e] : make_double2(0.0, 0.0);
       }
       wave_lds_sync();
-      if (live) {  // both sites and the bond to memory
-        double2* gl = site(k);
-        double2* gr2 = site(k + 1);
-        for (int e = r; e < slot; e += kB8Lanes) {
-          gl[e] = Lo[e];
-          gr2[e] = Ro[e];
-        }
-        if (r == 0) chi[k + 1] = keep;
-      }
-      // Next step: the site factored on the near side stays; the fresh site
-      // (gated) replaces the finished one and becomes the other side.
       if (more) {
         if (l2r) {
-          put_site(lb, x_next);  // site k is done: fresh site k+2 in its buffer
-          lb = 1 - lb;           // site k+1 (old right) is the new left site
+          put_site(lb, g_sn, g_cs);  // site k is done: fresh site k+2 in its buffer
+          lb = 1 - lb;               // site k+1 (old right) is the new left site
           xl = xrr;
-          xrr = x_next;
+          xrr = xq;
         } else {
-          put_site(1 - lb, x_next);  // site k+1 is done: fresh site k-1 there
-          lb = 1 - lb;               // ... as the new left; site k is the right one
+          put_site(1 - lb, g_sn, g_cs);  // site k+1 is done: fresh site k-1 there
+          lb = 1 - lb;                   // ... as the new left; site k is the right one
           xrr = xl;
-          xl = x_next;
+          xl = xq;
         }
         carry = keep;
-        mid = far;
         far = far_next;
+        sh = n_sh;
+        ch = n_ch;
+        xq = xq_next;
+      }
+      if (live) {
+        double2* gd = site(kdone);
+        double2* gk = site(l2r ? k + 1 : k);
+#pragma unroll
+        for (int m = 0; m < kOut; ++m) {
+          const int e = r + kB8Lanes * m;
+          if (e < slot) {
+            gd[e] = vd[m];
+            if (!more) gk[e] = vk[m];
+          }
+        }
+        if (r == 0) chi[k + 1] = keep;
       }
       wave_lds_sync();
     }
