@@ -58,6 +58,26 @@ __device__ inline float pow2(float, int e) {  // 2^e for -126 <= e <= 127
 }
 
 
+// The two accumulation steps of a site, as explicit FMA sequences: the tile
+// kernel and the pair-level refinement both use them, so a refined pair
+// carries the tile kernel's FP64 value bit for bit.
+//   G[a][b'] += E[a][b] B^s[b][b']            (complex)
+//   E'[a'][b'] += conj(A^s[a][a']) G[a][b']   (complex)
+template <typename R, typename C>
+__device__ inline void g_acc(R& gr, R& gi, R er, R ei, C bv) {
+  gr = fma(er, (R)bv.x, gr);
+  gr = fma(-ei, (R)bv.y, gr);
+  gi = fma(er, (R)bv.y, gi);
+  gi = fma(ei, (R)bv.x, gi);
+}
+template <typename R, typename C>
+__device__ inline void e_acc(R& nr, R& ni, C av, R gr, R gi) {
+  nr = fma((R)av.x, gr, nr);
+  nr = fma((R)av.y, gi, nr);
+  ni = fma((R)av.x, gi, ni);
+  ni = fma(-(R)av.y, gr, ni);
+}
+
 template <typename R, int T>
 struct SweepSmem {
   using C = typename Cx<R>::V;
@@ -161,10 +181,7 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, SweepSmem<R, T>& sm,
         for (int bb = 0; bb < T; ++bb) {
           C bv = Bs[s * T * T + b * T + bb];
 #pragma unroll
-          for (int a = 0; a < T; ++a) {
-            gr[a][bb] += er[a][b] * bv.x - ei[a][b] * bv.y;
-            gi[a][bb] += er[a][b] * bv.y + ei[a][b] * bv.x;
-          }
+          for (int a = 0; a < T; ++a) g_acc(gr[a][bb], gi[a][bb], er[a][b], ei[a][b], bv);
         }
 #pragma unroll
       for (int a = 0; a < T; ++a)
@@ -172,10 +189,7 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, SweepSmem<R, T>& sm,
         for (int aa = 0; aa < T; ++aa) {
           C av = As[s * T * T + a * T + aa];  // A^s[a][aa]; dagger -> conj
 #pragma unroll
-          for (int bb = 0; bb < T; ++bb) {
-            nr[aa][bb] += av.x * gr[a][bb] + av.y * gi[a][bb];
-            ni[aa][bb] += av.x * gi[a][bb] - av.y * gr[a][bb];
-          }
+          for (int bb = 0; bb < T; ++bb) e_acc(nr[aa][bb], ni[aa][bb], av, gr[a][bb], gi[a][bb]);
         }
     }
     // exact power-of-two rescale
@@ -306,15 +320,190 @@ __global__ void compact_marked_kernel(const uint32_t* __restrict__ mask, int64_t
   if (any) list[atomicAdd(count, 1)] = (int32_t)q;
 }
 
-__global__ __launch_bounds__(kThreads) void sweep_refine_kernel(QkTaskTable tt,
+// Pair-level FP64 refinement: only the marked pairs of a marked tile are
+// recomputed, 16 lanes per pair (lane (a', b') owns entry E[a'][b']) and 16
+// pairs per 256-thread workgroup at a time. A site of a pair is staged in
+// LDS by its own 16 lanes; G^s (lane (a, b') computes G^s[a][b'] from row a
+// of E) and the new E (lane (a', b') from column b' of G^s) pass through the
+// pair's LDS area. The 16 lanes of a pair sit in one wavefront, whose LDS
+// operations complete in issue order, so no workgroup barrier is needed.
+// Every entry follows the tile kernel's operation order (g_acc over b
+// ascending, e_acc over s then a ascending, the same power-of-two rescale:
+// a maximum is independent of the order it is taken in), so the refined
+// value equals the tile kernel's bit for bit; a diagonal tile costs one pass
+// of 16 pairs instead of 256.
+constexpr int kRefPairs = kThreads / 16;
+
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt untouched
+  __builtin_amdgcn_wave_barrier();
+  __asm__ volatile("" ::: "memory");
+}
+
+// Per-pair areas sized for the largest bond dimension (4), whatever the
+// tile's: the waves of a workgroup move on to the next listed tile without a
+// barrier, and in a ragged launch that tile may have another bond dimension,
+// so a pair's area must not move with it.
+struct RefSmem {
+  static constexpr int kSlotMax = 2 * 4 * 4, kTTMax = 4 * 4;
+  double2 ab[2][kRefPairs][2][kSlotMax];  // [buffer][pair][A, B][s][a][b]
+  double2 g[kRefPairs][2][kTTMax];        // G^s[a][b']
+  double2 e[kRefPairs][kTTMax];           // E[a][b]
+};
+
+// max over the 16 lanes of a pair (aligned lane groups of 16)
+__device__ inline double max16(double v) {
+  v = fmax(v, __shfl_xor(v, 1, 64));
+  v = fmax(v, __shfl_xor(v, 2, 64));
+  v = fmax(v, __shfl_xor(v, 4, 64));
+  v = fmax(v, __shfl_xor(v, 8, 64));
+  return v;
+}
+
+template <int T>
+__device__ void refine_tile_pairs(const QkTask& t, int ti, int tj, const uint32_t* mi,
+                                  RefSmem& sm) {
+  constexpr int TT = T * T, kSlot = 2 * TT;
+  const int tid = threadIdx.x;
+  const int p = tid >> 4, l = tid & 15, aa = l >> 2, bb = l & 3;
+  const bool on = aa < T && bb < T;
+  const double* ta = static_cast<const double*>(t.ta64);
+  const double* tb = static_cast<const double*>(t.tb64);
+  const int nq = t.nq;
+  int total = 0;
+  for (int wd = 0; wd < kQkMaskWords; ++wd) total += __popc(mi[wd]);
+  for (int base = 0; base < total; base += kRefPairs) {
+    // this pair slot takes the (base + p)-th marked bit of the tile
+    int want = base + p, bit = -1;
+    for (int wd = 0; wd < kQkMaskWords && bit < 0; ++wd) {
+      unsigned m = mi[wd];
+      const int cnt = __popc(m);
+      if (want < cnt) {
+        for (int q = 0; q < want; ++q) m &= m - 1;  // drop the lower set bits
+        bit = wd * 32 + __ffs(m) - 1;
+      } else {
+        want -= cnt;
+      }
+    }
+    const bool have = bit >= 0;
+    const int64_t i = (int64_t)ti * kTile + (have ? bit / kTile : 0);
+    const int64_t j = (int64_t)tj * kTile + (have ? bit % kTile : 0);
+    auto load = [&](int k, double2 (&v)[2][2]) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int e = l + 16 * h;
+        v[h][0] = e < kSlot ? load_c(ta, ((int64_t)k * t.na + i) * kSlot + e) : make_double2(0, 0);
+        v[h][1] = e < kSlot ? load_c(tb, ((int64_t)k * t.nb + j) * kSlot + e) : make_double2(0, 0);
+      }
+    };
+    auto stage = [&](int buf, const double2 (&v)[2][2]) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int e = l + 16 * h;
+        if (e < kSlot) {
+          sm.ab[buf][p][0][e] = v[h][0];
+          sm.ab[buf][p][1][e] = v[h][1];
+        }
+      }
+    };
+    double er = (aa == 0 && bb == 0) ? 1.0 : 0.0, ei = 0.0;
+    int expo = 0;
+    if (on) sm.e[p][aa * T + bb] = make_double2(er, ei);
+    double2 nxt[2][2];
+    load(0, nxt);
+    stage(0, nxt);
+    wave_lds_sync();
+    for (int k = 0; k < nq; ++k) {
+      const int buf = k & 1;
+      if (k + 1 < nq) load(k + 1, nxt);
+      const double2* As = sm.ab[buf][p][0];
+      const double2* Bs = sm.ab[buf][p][1];
+      // G^s[a][b'] for a = aa, b' = bb
+      if (on) {
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+          double gr = 0.0, gi = 0.0;
+#pragma unroll
+          for (int b = 0; b < T; ++b) {
+            const double2 ev = sm.e[p][aa * T + b];
+            g_acc(gr, gi, ev.x, ev.y, Bs[s2 * TT + b * T + bb]);
+          }
+          sm.g[p][s2][aa * T + bb] = make_double2(gr, gi);
+        }
+      }
+      wave_lds_sync();
+      // E'[a'][b'] for a' = aa, b' = bb
+      double nr = 0.0, ni = 0.0;
+      if (on) {
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+          for (int a = 0; a < T; ++a) {
+            const double2 gv = sm.g[p][s2][a * T + bb];
+            e_acc(nr, ni, As[s2 * TT + a * T + aa], gv.x, gv.y);
+          }
+      }
+      const double m = max16(fmax(fabs(nr), fabs(ni)));
+      const int e = m > 0.0 ? frexp_exp(m) : 0;
+      const double sc = pow2(0.0, -e);
+      expo += e;
+      er = nr * sc;
+      ei = ni * sc;
+      if (on) sm.e[p][aa * T + bb] = make_double2(er, ei);
+      if (k + 1 < nq) stage(buf ^ 1, nxt);
+      wave_lds_sync();
+    }
+    // epilogue on lane (0, 0) of the pair, as in the tile kernel
+    if (have && l == 0) {
+      const double mag2 = er * er + ei * ei;
+      const double lnk = mag2 > 0.0 ? log(mag2) + 2.0 * (double)expo * 0.69314718055994530942
+                                    : -INFINITY;
+      const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
+      auto put = [&](double* ptr, int64_t ld, double v) {
+        if (!ptr) return;
+        ptr[i * ld + j] = v;
+        if (t.symmetric && j != i) ptr[j * ld + i] = v;
+      };
+      put(t.kq, t.ld_kq, kq);
+      put(t.lnkq, t.ld_ln, lnk);
+      if (t.fuse) {
+        const double* xr = t.xr + i * t.ld_xr;
+        const double* xc = t.xc + j * t.ld_xc;
+        double d2 = 0.0;
+        for (int f = 0; f < nq; ++f) {
+          double df = xr[f] - xc[f];
+          d2 += df * df;
+        }
+        const double kc = exp(-t.gamma * d2);
+        const double w = t.w_rows ? t.w_rows[i] : t.w;
+        put(t.kc, t.ld_kc, kc);
+        put(t.k, t.ld_k, w * kq + (1.0 - w) * kc);
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void refine_pairs_kernel(QkTaskTable tt,
                                                                 const uint32_t* mask_in,
                                                                 const int32_t* list,
                                                                 const int32_t* count) {
-  __shared__ SweepSmem<double, MaxT<double>::v> sm4;
-  __shared__ unsigned tile_mask[kQkMaskWords];
+  __shared__ RefSmem sm;
   const int n = *count;
-  for (int x = blockIdx.x; x < n; x += gridDim.x)
-    sweep_one_tile<double>(tt, list[x], mask_in, nullptr, 0.0, sm4, tile_mask);
+  for (int x = blockIdx.x; x < n; x += gridDim.x) {
+    const int64_t q = list[x];
+    int k = 0;
+    while (k + 1 < tt.n_tasks && tt.t[k + 1].tile_begin <= q) ++k;
+    const QkTask& t = tt.t[k];
+    int ti, tj;
+    qk_tile_coords(t, q - t.tile_begin, ti, tj);
+    const uint32_t* mi = mask_in + q * kQkMaskWords;
+    switch (t.T) {
+      case 1: refine_tile_pairs<1>(t, ti, tj, mi, sm); break;
+      case 2: refine_tile_pairs<2>(t, ti, tj, mi, sm); break;
+      default: refine_tile_pairs<4>(t, ti, tj, mi, sm); break;
+    }
+  }
 }
 
 }  // namespace
@@ -348,7 +537,7 @@ hipError_t qk_launch_refine_fp64(const QkTaskTable& tt, int grid, const uint32_t
   const int64_t blocks = (tt.total_tiles + 255) / 256;
   hipLaunchKernelGGL(compact_marked_kernel, dim3((unsigned)blocks), dim3(256), 0, s, mask,
                      tt.total_tiles, list, count);
-  hipLaunchKernelGGL(sweep_refine_kernel, dim3(grid), dim3(kThreads), 0, s, tt, mask,
+  hipLaunchKernelGGL(refine_pairs_kernel, dim3(grid), dim3(kThreads), 0, s, tt, mask,
                      (const int32_t*)list, (const int32_t*)count);
   return hipGetLastError();
 }
