@@ -350,14 +350,12 @@ def run(args):
     out_te = {k: torch.empty((nte, ntr), **f64) for k in ("kq", "ln", "kc", "k")}
     stream = torch.cuda.current_stream()
 
-    side = torch.cuda.Stream()  # default priority
 
     def one_step(prec, timing=None):
         store = qk.QK_STORE_FP64 if prec == "fp64" else qk.QK_STORE_ALL
-        # the two independent builds overlap on two streams (the test build
-        # alone fills one wave per SIMD); the gram call waits for both
-        btr = qk.qk_mps_build(xtr, 2, 64, 1e-10, store=store)
-        bte = qk.qk_mps_build(xte, 2, 64, 1e-10, store=store, stream=side)
+        # both builds in one launch (as two launches on two streams, the
+        # second one ran a third slower than alone)
+        btr, bte = qk.qk_mps_build_many([xtr, xte], 2, 64, 1e-10, store=store)
         tasks = [
             {"rows": btr, "cols": btr, "symmetric": True, "kq": out["kq"], "lnkq": out["ln"],
              "fuse": {"x_rows": xtr, "x_cols": xtr, "gamma": 1.0 / d, "w": 0.5,
@@ -374,10 +372,7 @@ def run(args):
         qk.qk_overlap_gram_multi(tasks, prec)
         if timing is not None:
             e1.record(stream)
-            # the library's own HIP events around the sweep launch and the
-            # FP64 refinement pass, on the launch stream
-            kernel_ms, refine_ms = qk.qk_last_launch_ms()
-            timing.append((e0, e1, kernel_ms, refine_ms))
+            timing.append((e0, e1))
         return btr, bte
 
     def measure(prec, steps, warmup):
@@ -392,15 +387,22 @@ def run(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(steps):
+            # Batches stay alive until the loop ends (3.5 GB per step): a
+            # release drains the device, which would idle it between steps
+            # while the host enqueues the next one; long runs release every
+            # 16 steps.
+            if len(keep) == 16:
+                keep.clear()
             keep.append(one_step(prec, timing))
-            if len(keep) > 1:
-                keep.pop(0)  # release the previous step's batches
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        # the library's own HIP events around the last step's sweep launch
+        # and FP64 refinement pass (read after the loop: the query waits)
+        kernel_last, refine_last = qk.qk_last_launch_ms()
         qk.qk_set_launch_timing(False)
         sweep_ms = [t[0].elapsed_time(t[1]) for t in timing]
-        kernel_ms = [t[2] for t in timing]
-        refine_ms = [t[3] for t in timing]
+        kernel_ms = [kernel_last]
+        refine_ms = [refine_last]
         btr, bte = keep[-1]
         chi_tr = qk.qk_mps_chi(btr)
         chi_te = qk.qk_mps_chi(bte)

@@ -91,8 +91,9 @@ typedef struct qk_mps_batch qk_mps_batch; /* opaque, device-resident, library-ow
 
 /*
  * qk_mps_build -- one MPS per sample (Eq. (6)).
- * Time-evolving block decimation in FP64 on the device, one wavefront per
- * sample: per layer, the single-qubit gates, then the RZZ chain as two-site
+ * Time-evolving block decimation in FP64 on the device (eight samples per
+ * wavefront for chi_pad <= 4, one per wavefront above): per layer, the
+ * single-qubit gates, then the RZZ chain as two-site
  * steps (merge, phase, one-sided Jacobi SVD, truncate at s_j > cutoff*s_0 and
  * chi_max, renormalise), sweeping left to right on odd and right to left on
  * even layers. Then the tensors are packed for the overlap sweep.
@@ -111,6 +112,22 @@ typedef struct qk_mps_batch qk_mps_batch; /* opaque, device-resident, library-ow
 QK_API qk_status qk_mps_build(const qk_circuit_desc* c, const double* x_dev,
                        int64_t n_samples, int64_t ld_x, uint32_t store,
                        void* hip_stream, qk_mps_batch** out);
+
+/*
+ * qk_mps_build_many -- qk_mps_build for n_inputs feature matrices of the
+ * same circuit (for example a training and a test set) in one device launch
+ * where chi_pad <= 4, so the builds share the GPU without one launch
+ * waiting behind the other. Input k: x_devs[k] (n_samples[k] x n_qubits
+ * FP64, leading dimension ld_x[k]); out[k] receives its batch, the same
+ * batch qk_mps_build would return for that input alone. 1 <= n_inputs <= 8;
+ * x_devs, n_samples, ld_x and out are host arrays of n_inputs entries.
+ * On error no batch is returned (every out[k] is NULL).
+ * Errors as qk_mps_build; INVALID_ARG also for n_inputs outside [1, 8].
+ */
+QK_API qk_status qk_mps_build_many(const qk_circuit_desc* c, int32_t n_inputs,
+                                   const double* const* x_devs, const int64_t* n_samples,
+                                   const int64_t* ld_x, uint32_t store, void* hip_stream,
+                                   qk_mps_batch** out);
 
 /*
  * qk_mps_import -- test hook: upload MPS built elsewhere (e.g. on the host).

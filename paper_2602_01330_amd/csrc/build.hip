@@ -611,16 +611,30 @@ __device__ int b8_factor(double2 (&xr)[2 * W], double2 (&vr)[2 * W], double floo
   return keep;
 }
 
+// The parts of one launch: part p takes workgroups [wg_begin[p], wg_begin[p+1]).
+struct B8Table {
+  QkBuildPart p[QK_MAX_BUILD_PARTS];
+  int64_t wg_begin[QK_MAX_BUILD_PARTS + 1];
+  int n_parts;
+};
+
 template <int W>
-__global__ __launch_bounds__(64) void mps_build8_kernel(
-    const double* __restrict__ x, int64_t ld_x, int64_t N, int nq, int n_layers,
-    int chi_max, int entangle, double cutoff, double2* __restrict__ t64,
-    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status) {
+__global__ __launch_bounds__(64) void mps_build8_kernel(B8Table tab, int nq, int n_layers,
+                                                        int chi_max, int entangle,
+                                                        double cutoff) {
   constexpr int D = 2 * W, TT = W * W, slot = 2 * TT;
   __shared__ Build8Smem<W> sm;
+  int part = 0;
+  while (part + 1 < tab.n_parts && tab.wg_begin[part + 1] <= (int64_t)blockIdx.x) ++part;
+  const QkBuildPart& P = tab.p[part];
+  const double* __restrict__ x = P.x;
+  const int64_t ld_x = P.ld_x, N = P.n;
+  double2* __restrict__ t64 = P.t64;
+  int32_t* __restrict__ chi_tab = P.chi;
+  int32_t* __restrict__ status = P.status;
   const int lane = threadIdx.x;
   const int g = lane >> 3, r = lane & 7;
-  const int64_t i0 = (int64_t)blockIdx.x * kB8Samples + g;
+  const int64_t i0 = ((int64_t)blockIdx.x - tab.wg_begin[part]) * kB8Samples + g;
   const bool live = i0 < N;
   const int64_t i = live ? i0 : N - 1;  // idle groups shadow the last sample, writing nothing
   const double* xi = x + i * ld_x;
@@ -848,20 +862,8 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
                            int32_t* chi, int32_t* status, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (nq >= 2 && (T == 1 || T == 2 || T == 4)) {
-    const dim3 grid8((unsigned)((n + kB8Samples - 1) / kB8Samples)), block8(64);
-#define QK_BUILD8_CASE(WV)                                                    \
-  case WV:                                                                    \
-    hipLaunchKernelGGL(mps_build8_kernel<WV>, grid8, block8, 0, s, x, ld_x,   \
-                       n, nq, n_layers, chi_max, entangle, cutoff, t64, chi,  \
-                       status);                                               \
-    break;
-    switch (T) {
-      QK_BUILD8_CASE(1)
-      QK_BUILD8_CASE(2)
-      QK_BUILD8_CASE(4)
-    }
-#undef QK_BUILD8_CASE
-    return hipGetLastError();
+    const QkBuildPart part{x, ld_x, n, t64, chi, status};
+    return qk_launch_build_many(&part, 1, nq, n_layers, chi_max, entangle, cutoff, chi_ws, T, s);
   }
   dim3 grid((unsigned)n), block(64);
 #define QK_BUILD_CASE(WV)                                                     \
@@ -880,6 +882,49 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
       return hipErrorInvalidValue;
   }
 #undef QK_BUILD_CASE
+  return hipGetLastError();
+}
+
+hipError_t qk_launch_build_many(const QkBuildPart* parts, int n_parts, int nq, int n_layers,
+                                int chi_max, int entangle, double cutoff, int chi_ws, int T,
+                                hipStream_t s) {
+  if (n_parts < 1 || n_parts > QK_MAX_BUILD_PARTS) return hipErrorInvalidValue;
+  if (nq < 2 || !(T == 1 || T == 2 || T == 4)) {
+    // one launch per part with the one-sample-per-wave kernel
+    for (int k = 0; k < n_parts; ++k) {
+      const QkBuildPart& p = parts[k];
+      const hipError_t e = qk_launch_build(p.x, p.ld_x, p.n, nq, n_layers, chi_max, entangle,
+                                           cutoff, chi_ws, T, p.t64, p.chi, p.status, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  B8Table tab{};
+  int64_t wg = 0;
+  int m = 0;
+  for (int k = 0; k < n_parts; ++k) {
+    if (parts[k].n == 0) continue;
+    tab.p[m] = parts[k];
+    tab.wg_begin[m] = wg;
+    wg += (parts[k].n + kB8Samples - 1) / kB8Samples;
+    ++m;
+  }
+  tab.wg_begin[m] = wg;
+  tab.n_parts = m;
+  if (wg == 0) return hipSuccess;
+  const dim3 grid8((unsigned)wg), block8(64);
+  switch (T) {
+    case 1:
+      hipLaunchKernelGGL(mps_build8_kernel<1>, grid8, block8, 0, s, tab, nq, n_layers, chi_max, entangle, cutoff);
+      break;
+    case 2:
+      hipLaunchKernelGGL(mps_build8_kernel<2>, grid8, block8, 0, s, tab, nq, n_layers, chi_max, entangle, cutoff);
+      break;
+    default:
+      hipLaunchKernelGGL(mps_build8_kernel<4>, grid8, block8, 0, s, tab, nq, n_layers, chi_max, entangle, cutoff);
+      break;
+  }
+  (void)chi_ws;
   return hipGetLastError();
 }
 

@@ -407,6 +407,59 @@ qk_status qk_mps_build(const qk_circuit_desc* c, const double* x_dev,
   return QK_OK;
 }
 
+qk_status qk_mps_build_many(const qk_circuit_desc* c, int32_t n_inputs,
+                            const double* const* x_devs, const int64_t* n_samples,
+                            const int64_t* ld_x, uint32_t store, void* hip_stream,
+                            qk_mps_batch** out) {
+  qk_status st = check_desc(c);
+  if (st != QK_OK) return st;
+  if (n_inputs < 1 || n_inputs > QK_MAX_BUILD_PARTS)
+    return fail(QK_ERR_INVALID_ARG, "n_inputs must be in [1, 8]");
+  if (!x_devs || !n_samples || !ld_x || !out) return fail(QK_ERR_INVALID_ARG, "NULL argument");
+  for (int k = 0; k < n_inputs; ++k) out[k] = nullptr;
+  for (int k = 0; k < n_inputs; ++k) {
+    if (n_samples[k] < 0) return fail(QK_ERR_INVALID_ARG, "n_samples < 0");
+    if (n_samples[k] > 0 && !x_devs[k]) return fail(QK_ERR_INVALID_ARG, "x_dev is NULL");
+    if (ld_x[k] < c->n_qubits) return fail(QK_ERR_INVALID_ARG, "ld_x < n_qubits");
+  }
+  if (store == 0 || (store & ~(uint32_t)QK_STORE_ALL))
+    return fail(QK_ERR_INVALID_ARG, "store must be a non-empty QK_STORE_* mask");
+  const int ws = chi_bound(c);
+  const int T = pow2_ceil(ws);
+  if (T > 16) return fail(QK_ERR_UNSUPPORTED, "bond bound above 16 is not supported by the build");
+  hipStream_t s = (hipStream_t)hip_stream;
+  qk_mps_batch* b[QK_MAX_BUILD_PARTS] = {};
+  QkBuildPart parts[QK_MAX_BUILD_PARTS];
+  auto release_all = [&]() {
+    for (int k = 0; k < n_inputs; ++k)
+      if (b[k]) qk_mps_release(b[k]);
+  };
+  for (int k = 0; k < n_inputs; ++k) {
+    st = alloc_batch(c, n_samples[k], T, store, s, &b[k]);
+    if (st != QK_OK) {
+      release_all();
+      return st;
+    }
+    b[k]->chi_ws = ws;
+    parts[k] = QkBuildPart{x_devs[k], ld_x[k], n_samples[k], b[k]->t64, b[k]->chi, b[k]->status};
+  }
+  hipError_t e = qk_launch_build_many(parts, n_inputs, c->n_qubits, c->n_layers, c->chi_max,
+                                      c->entangle, c->cutoff_rel, ws, T, s);
+  if (e != hipSuccess) {
+    release_all();
+    return hip_fail(e, "build launch");
+  }
+  for (int k = 0; k < n_inputs; ++k) {
+    st = finish_batch(b[k], store);
+    if (st != QK_OK) {
+      release_all();
+      return st;
+    }
+  }
+  for (int k = 0; k < n_inputs; ++k) out[k] = b[k];
+  return QK_OK;
+}
+
 qk_status qk_mps_import(const qk_circuit_desc* c, int64_t n_samples,
                         int32_t chi_pad, const int32_t* chi_host,
                         const double* tensors_host, uint32_t store,

@@ -47,6 +47,20 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
                            int n_layers, int chi_max, int entangle,
                            double cutoff, int chi_ws, int T, double2* t64,
                            int32_t* chi, int32_t* status, hipStream_t s);
+// Several feature matrices of one circuit built in one launch (bond bound
+// up to 4): one part per batch.
+struct QkBuildPart {
+  const double* x;
+  int64_t ld_x;
+  int64_t n;
+  double2* t64;
+  int32_t* chi;
+  int32_t* status;
+};
+constexpr int QK_MAX_BUILD_PARTS = 8;
+hipError_t qk_launch_build_many(const QkBuildPart* parts, int n_parts, int nq, int n_layers,
+                                int chi_max, int entangle, double cutoff, int chi_ws, int T,
+                                hipStream_t s);
 hipError_t qk_launch_pack32(const double2* t64, float* t32, int64_t count,
                             hipStream_t s);
 

@@ -66,6 +66,9 @@ class qk_gram_task(C.Structure):
 _P = C.c_void_p
 _lib.qk_mps_build.argtypes = [C.POINTER(qk_circuit_desc), _P, C.c_int64, C.c_int64,
                               C.c_uint32, _P, C.POINTER(_P)]
+_lib.qk_mps_build_many.argtypes = [C.POINTER(qk_circuit_desc), C.c_int32, C.POINTER(_P),
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_uint32, _P,
+                                   C.POINTER(_P)]
 _lib.qk_mps_import.argtypes = [C.POINTER(qk_circuit_desc), C.c_int64, C.c_int32, _P, _P,
                                C.c_uint32, _P, C.POINTER(_P)]
 _lib.qk_mps_info.argtypes = [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
@@ -94,8 +97,8 @@ for _f in ("qk_autotune", "qk_tune_export", "qk_tune_import"):
 _lib.qk_status_string.restype = C.c_char_p
 _lib.qk_status_string.argtypes = [C.c_int]
 _lib.qk_last_error.restype = C.c_char_p
-for _f in ("qk_mps_build", "qk_mps_import", "qk_mps_info", "qk_mps_chi", "qk_mps_release",
-           "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
+for _f in ("qk_mps_build", "qk_mps_build_many", "qk_mps_import", "qk_mps_info", "qk_mps_chi",
+           "qk_mps_release", "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
            "qk_resolve_precision", "qk_set_refine_threshold"):
     getattr(_lib, _f).restype = C.c_int
 
@@ -125,8 +128,8 @@ QK_REQ_QUEUED, QK_REQ_RUNNING, QK_REQ_DONE, QK_REQ_FAILED, QK_REQ_CANCELLED = 0,
 EXPORTED = ["qk_server_create", "qk_server_load_support", "qk_server_submit",
             "qk_server_poll", "qk_server_wait", "qk_server_cancel", "qk_server_request_times",
             "qk_server_stats", "qk_server_destroy",
-            "qk_mps_build", "qk_mps_import", "qk_mps_info", "qk_mps_chi", "qk_mps_release",
-            "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
+            "qk_mps_build", "qk_mps_build_many", "qk_mps_import", "qk_mps_info", "qk_mps_chi",
+            "qk_mps_release", "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
             "qk_resolve_precision", "qk_set_refine_threshold", "qk_autotune",
             "qk_tune_export", "qk_tune_import", "qk_status_string",
             "qk_last_error", "qk_set_launch_timing", "qk_last_launch_ms"]
@@ -201,6 +204,23 @@ def qk_mps_build(x, n_layers, chi_max, cutoff=1e-10, entangle=True, store=QK_STO
     _check(_lib.qk_mps_build(C.byref(desc), xp, x.shape[0], ld, store, _stream(stream),
                              C.byref(h)))
     return MpsBatch(h, x.shape[1], keepalive=x)
+
+
+def qk_mps_build_many(xs, n_layers, chi_max, cutoff=1e-10, entangle=True, store=QK_STORE_ALL,
+                      stream=None) -> list:
+    """Build the MPS of several feature matrices (same width) in one launch."""
+    d = xs[0].shape[1]
+    if any(x.shape[1] != d for x in xs):
+        raise ValueError("all feature matrices need the same number of columns")
+    k = len(xs)
+    ptrs, ns, lds = (_P * k)(), (C.c_int64 * k)(), (C.c_int64 * k)()
+    for m, x in enumerate(xs):
+        xp, ld = _mat(x, "x")
+        ptrs[m], ns[m], lds[m] = xp.value, x.shape[0], ld
+    desc = circuit(d, n_layers, chi_max, cutoff, entangle)
+    out = (_P * k)()
+    _check(_lib.qk_mps_build_many(C.byref(desc), k, ptrs, ns, lds, store, _stream(stream), out))
+    return [MpsBatch(C.c_void_p(out[m]), d, keepalive=xs[m]) for m in range(k)]
 
 
 def qk_mps_import(chi, tensors, n_layers, chi_max, cutoff=1e-10, entangle=True,

@@ -249,3 +249,24 @@ def test_refinement_restores_fp64_on_large_entries(qk):
     assert np.array_equal(a["ln"][big], b["ln"][big])
     small = b["kq"] < 0.1 * qk.REFINE_DEFAULT["bf16x2"]
     assert not np.array_equal(a["ln"][small], b["ln"][small])
+
+
+def test_build_many_equals_separate_builds(qk):
+    # two feature matrices of one circuit in one launch give the same MPS as
+    # two separate builds (bond tables equal, FP64 overlaps bit-identical)
+    X, _ = gen_clusters(37, 64, 9)
+    Y, _ = gen_clusters(20, 64, 10)
+    xd, yd = dev(X), dev(Y)
+    bx, by = qk.qk_mps_build_many([xd, yd], 2, 64)
+    sx, sy = qk.qk_mps_build(xd, 2, 64), qk.qk_mps_build(yd, 2, 64)
+    assert np.array_equal(qk.qk_mps_chi(bx), qk.qk_mps_chi(sx))
+    assert np.array_equal(qk.qk_mps_chi(by), qk.qk_mps_chi(sy))
+    outs = []
+    for a, b in ((by, bx), (sy, sx)):
+        ln = torch.full((20, 37), float("nan"), dtype=torch.float64, device="cuda")
+        qk.qk_overlap_gram(a, b, False, "fp64", None, ln)
+        torch.cuda.synchronize()
+        outs.append(ln.cpu().numpy())
+    assert np.all(np.isfinite(outs[0])) and np.array_equal(outs[0], outs[1])
+    with pytest.raises(qk.QkError):
+        qk.qk_mps_build_many([xd] * 9, 2, 64)
