@@ -134,7 +134,8 @@ QK_API qk_status qk_mps_build_many(const qk_circuit_desc* c, int32_t n_inputs,
  *   chi_host     n_samples x (n_qubits+1) bond dimensions (chi_0 = chi_n = 1).
  *   tensors_host complex FP64 (re, im interleaved), layout
  *                [site k][sample i][s][a][b], a, b < chi_pad, zero outside
- *                the realized (chi_k, chi_{k+1}) block; chi_pad a power of 2.
+ *                the realized (chi_k, chi_{k+1}) block; chi_pad a power of 2,
+ *                at most 64.
  * The copy is synchronous. Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.
  */
 QK_API qk_status qk_mps_import(const qk_circuit_desc* c, int64_t n_samples,
@@ -193,6 +194,9 @@ typedef struct {
  *   symmetric    1: rows == cols; only j >= i is contracted and both
  *                triangles are written (train x train); 0: full rectangle.
  *   prec         QK_PREC_*; QK_PREC_FP64 needs QK_STORE_FP64 in both batches.
+ *                chi_pad 1, 2, 4: every form (tile kernels); chi_pad 8..64:
+ *                QK_PREC_FP64 only (one workgroup per pair) and AUTO
+ *                resolves to it.
  *   kq_dev       FP64 rows->n_samples x cols->n_samples output, ld_kq (may be
  *                NULL if lnkq_dev is given).
  *   lnkq_dev     FP64 ln K_q output, ld_ln (NULL to skip).

@@ -205,6 +205,7 @@ qk_status fill_task(QkTask& t, const qk_mps_batch* rows, const qk_mps_batch* col
 bool supported_T(qk_precision p, int T) {
   switch (p) {
     case QK_PREC_FP64:
+      return T == 1 || T == 2 || T == 4 || qk_sweep_big_supports(T);
     case QK_PREC_FP32:
       return T == 1 || T == 2 || T == 4;
     default:
@@ -232,8 +233,12 @@ void timing_mark(int which, hipStream_t s) {
   if (g_timing.enabled) (void)hipEventRecord(g_timing.ev[which], s);
 }
 
-qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, hipStream_t s,
+qk_status run_tasks(std::vector<QkTask>& tasks_in, qk_precision prec, double tau, hipStream_t s,
                     int64_t max_tiles = -1) {
+  // complex-FP64 tasks with bonds above 4 go to the large-bond kernel (one
+  // workgroup per pair); the tile kernels take the others
+  std::vector<QkTask> tasks, big;
+  for (const QkTask& t : tasks_in) (prec == QK_PREC_FP64 && t.T > 4 ? big : tasks).push_back(t);
   // longest-processing-time order: per-tile cost ~ nq * T^3
   std::stable_sort(tasks.begin(), tasks.end(), [](const QkTask& a, const QkTask& b) {
     return (double)a.nq * a.T * a.T * a.T > (double)b.nq * b.T * b.T * b.T;
@@ -252,15 +257,24 @@ qk_status run_tasks(std::vector<QkTask>& tasks, qk_precision prec, double tau, h
   std::lock_guard<std::mutex> tlk(g_timing.mu);
   g_timing.recorded = false;  // set once this call's events are all recorded
   g_timing.refined = false;
-  if (acc == 0) return QK_OK;
+  if (acc == 0 && big.empty()) return QK_OK;
   // persistent workgroups per CU: from the tuning table, else per form
   QkTuneEntry te;
-  const bool tuned = qk_tune_lookup(tasks[0].T, tasks[0].nq, &te) && te.form == prec;
+  const bool tuned =
+      !tasks.empty() && qk_tune_lookup(tasks[0].T, tasks[0].nq, &te) && te.form == prec;
   const int grid64 = (int)std::min<int64_t>(
       acc, (int64_t)device_cus() * (tuned && prec == QK_PREC_FP64 ? te.wg_per_cu : 2));
   timing_mark(0, s);
   if (prec == QK_PREC_FP64) {
-    QK_HIP(qk_launch_sweep_fp64(tt, grid64, nullptr, s), "sweep launch");
+    if (acc > 0) QK_HIP(qk_launch_sweep_fp64(tt, grid64, nullptr, s), "sweep launch");
+    for (int T : {64, 32, 16, 8}) {  // one launch per bond dimension, largest first
+      std::vector<QkTask> group;
+      for (const QkTask& t : big)
+        if (t.T == T) group.push_back(t);
+      if (!group.empty())
+        QK_HIP(qk_launch_sweep_big(group.data(), (int)group.size(), device_cus(), s),
+               "large-bond sweep launch");
+    }
     timing_mark(1, s);
     timing_mark(2, s);
     g_timing.recorded = g_timing.enabled;
@@ -469,8 +483,8 @@ qk_status qk_mps_import(const qk_circuit_desc* c, int64_t n_samples,
   if (!out) return fail(QK_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (n_samples < 0) return fail(QK_ERR_INVALID_ARG, "n_samples < 0");
-  if (chi_pad < 1 || chi_pad > 16 || (chi_pad & (chi_pad - 1)))
-    return fail(QK_ERR_INVALID_ARG, "chi_pad must be a power of two <= 16");
+  if (chi_pad < 1 || chi_pad > 64 || (chi_pad & (chi_pad - 1)))
+    return fail(QK_ERR_INVALID_ARG, "chi_pad must be a power of two <= 64");
   if (n_samples > 0 && (!chi_host || !tensors_host))
     return fail(QK_ERR_INVALID_ARG, "host arrays are NULL");
   if (store == 0 || (store & ~(uint32_t)QK_STORE_ALL))

@@ -160,6 +160,11 @@ struct QkTaskTable {
 // writes, per tile, a 256-bit mask (8 words) of the pairs whose K_q exceeds
 // the refinement threshold (bit (i % 16) * 16 + (j % 16)); the FP64 pass then
 // visits only tiles with a set bit and writes only those pairs.
+// Complex-FP64 sweep for padded bond dimensions 8..64 (sweep_big.hip): one
+// launch per bond dimension, every pair of the given tasks.
+bool qk_sweep_big_supports(int T);
+hipError_t qk_launch_sweep_big(const QkTask* tasks, int n_tasks, int cus, hipStream_t s);
+
 constexpr int kQkMaskWords = 8;
 hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, const uint32_t* mask_in,
                                 hipStream_t s);

@@ -1,0 +1,220 @@
+// Complex-FP64 overlap sweep for padded bond dimensions 8..64 (circuits
+// whose bonds exceed 4: more layers, or the truncating chi_max = 64 regime).
+//
+// Per pair (i, j) and site k:  E' = sum_s A_i^{s dagger} E B_j^s, E is
+// T x T complex (Eqs. (7), (9), (10): the transfer-matrix form of the
+// overlap <psi(x_i)|psi(x_j)>), with an exact power-of-two rescale every
+// site and an int32 exponent, as in the other sweep forms.
+//
+// One 256-thread workgroup per pair (a flat list of the pairs of every
+// task; symmetric tasks list the upper triangle). E and the intermediate
+// G^s = E B^s sit in LDS (2 T^2 complex: 128 KB at T = 64). A thread owns
+// the entries (a, b') with b' = tid mod T and a = tid / T + (256 / T) m, so
+// that at T = 64 the lanes of a wavefront share a and read the B row they
+// need as one coalesced access, and in the left multiply share a' and read
+// A^s[a][a'] as one broadcast. Every entry follows the operation order of
+// the FP64 tile kernel (G over b ascending, E' over s then a ascending).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "qk_internal.h"
+#include "qk_sweep_ops.h"
+
+namespace {
+
+constexpr int kBigThreads = 256;
+
+struct BigTable {
+  QkTask t[QK_MAX_TASKS];
+  int64_t pair_begin[QK_MAX_TASKS + 1];
+  int n_tasks;
+};
+
+template <int T>
+struct BigSmem {
+  double2 e[T * T];
+  double2 g[T * T];
+  double red[kBigThreads / 64];
+  int rede[kBigThreads / 64];
+};
+
+// (i, j) of local pair l: row-major over na x nb, or the upper triangle
+// (j >= i) of n x n row by row
+__device__ inline void pair_of(const QkTask& t, int64_t l, int64_t& i, int64_t& j) {
+  if (!t.symmetric) {
+    i = l / t.nb;
+    j = l - i * t.nb;
+    return;
+  }
+  const int64_t n = t.na;
+  // rows before row i: i n - i (i - 1) / 2
+  const double b2 = 2.0 * (double)n + 1.0;
+  int64_t r = (int64_t)((b2 - sqrt(b2 * b2 - 8.0 * (double)l)) * 0.5);
+  if (r < 0) r = 0;
+  if (r > n - 1) r = n - 1;
+  auto before = [&](int64_t q) { return q * n - q * (q - 1) / 2; };
+  while (r > 0 && before(r) > l) --r;
+  while (r + 1 < n && before(r + 1) <= l) ++r;
+  i = r;
+  j = r + (l - before(r));
+}
+
+__device__ inline double wave_max(double v) {
+  for (int off = 1; off < 64; off <<= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ inline double wave_sum(double v) {
+  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int T>
+__device__ void sweep_pair(const QkTask& t, int64_t i, int64_t j, BigSmem<T>& sm) {
+  constexpr int TT = T * T, kSlot = 2 * TT;
+  constexpr int kRows = kBigThreads / T > 0 ? kBigThreads / T : 1;  // rows per pass
+  constexpr int kPer = (TT + kBigThreads - 1) / kBigThreads;        // entries per thread
+  const int tid = threadIdx.x;
+  const int bp = tid % T, a0 = tid / T;
+  const double* ta = static_cast<const double*>(t.ta);
+  const double* tb = static_cast<const double*>(t.tb);
+  const int nq = t.nq;
+  for (int e = tid; e < TT; e += kBigThreads)
+    sm.e[e] = make_double2(e == 0 ? 1.0 : 0.0, 0.0);
+  int expo = 0;
+  __syncthreads();
+  for (int k = 0; k < nq; ++k) {
+    const double2* A = reinterpret_cast<const double2*>(ta) + ((int64_t)k * t.na + i) * kSlot;
+    const double2* B = reinterpret_cast<const double2*>(tb) + ((int64_t)k * t.nb + j) * kSlot;
+    double nr[kPer], ni[kPer];
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) nr[m] = ni[m] = 0.0;
+    for (int s = 0; s < 2; ++s) {
+      // G^s[a][b'] = sum_b E[a][b] B^s[b][b']
+#pragma unroll
+      for (int m = 0; m < kPer; ++m) {
+        const int a = a0 + kRows * m;
+        if (a < T) {
+          double gr = 0.0, gi = 0.0;
+          for (int b = 0; b < T; ++b) {
+            const double2 ev = sm.e[a * T + b];
+            g_acc(gr, gi, ev.x, ev.y, B[s * TT + b * T + bp]);
+          }
+          sm.g[a * T + bp] = make_double2(gr, gi);
+        }
+      }
+      __syncthreads();
+      // E'[a'][b'] += sum_a conj(A^s[a][a']) G^s[a][b']
+#pragma unroll
+      for (int m = 0; m < kPer; ++m) {
+        const int ap = a0 + kRows * m;
+        if (ap < T) {
+          for (int a = 0; a < T; ++a) {
+            const double2 gv = sm.g[a * T + bp];
+            e_acc(nr[m], ni[m], A[s * TT + a * T + ap], gv.x, gv.y);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // exact power-of-two rescale: the exponent of the largest |entry|
+    double mx = 0.0;
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) mx = fmax(mx, fmax(fabs(nr[m]), fabs(ni[m])));
+    mx = wave_max(mx);
+    if ((tid & 63) == 0) sm.red[tid >> 6] = mx;
+    __syncthreads();
+    mx = sm.red[0];
+    for (int w = 1; w < kBigThreads / 64; ++w) mx = fmax(mx, sm.red[w]);
+    const int ex = mx > 0.0 ? (int)((__double_as_longlong(mx) >> 52) & 0x7ff) - 1022 : 0;
+    const double sc = __longlong_as_double((long long)(1023 - ex) << 52);
+    expo += ex;
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int ap = a0 + kRows * m;
+      if (ap < T) sm.e[ap * T + bp] = make_double2(nr[m] * sc, ni[m] * sc);
+    }
+    __syncthreads();
+  }
+  // epilogue: ln K_q = 2 (ln|E[0][0]| + expo ln 2), K_q, fused RBF and mix
+  double d2 = 0.0;
+  if (t.fuse) {
+    const double* xr = t.xr + i * t.ld_xr;
+    const double* xc = t.xc + j * t.ld_xc;
+    for (int f = tid; f < nq; f += kBigThreads) {
+      const double df = xr[f] - xc[f];
+      d2 = fma(df, df, d2);
+    }
+    d2 = wave_sum(d2);
+    if ((tid & 63) == 0) sm.red[tid >> 6] = d2;
+    __syncthreads();
+    d2 = 0.0;
+    for (int w = 0; w < kBigThreads / 64; ++w) d2 += sm.red[w];
+  }
+  if (tid == 0) {
+    const double re = sm.e[0].x, im = sm.e[0].y;
+    const double mag2 = re * re + im * im;
+    const double lnk = mag2 > 0.0 ? log(mag2) + 2.0 * (double)expo * 0.69314718055994530942
+                                  : -INFINITY;
+    const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
+    auto put = [&](double* ptr, int64_t ld, double v) {
+      if (!ptr) return;
+      ptr[i * ld + j] = v;
+      if (t.symmetric && j != i) ptr[j * ld + i] = v;
+    };
+    put(t.kq, t.ld_kq, kq);
+    put(t.lnkq, t.ld_ln, lnk);
+    if (t.fuse) {
+      const double kc = exp(-t.gamma * d2);
+      const double w = t.w_rows ? t.w_rows[i] : t.w;
+      put(t.kc, t.ld_kc, kc);
+      put(t.k, t.ld_k, w * kq + (1.0 - w) * kc);
+    }
+  }
+  __syncthreads();  // E and the reduction slots are reused by the next pair
+}
+
+template <int T>
+__global__ __launch_bounds__(kBigThreads) void sweep_big_kernel(BigTable tab) {
+  __shared__ BigSmem<T> sm;
+  const int64_t total = tab.pair_begin[tab.n_tasks];
+  for (int64_t p = blockIdx.x; p < total; p += gridDim.x) {
+    int k = 0;
+    while (k + 1 < tab.n_tasks && tab.pair_begin[k + 1] <= p) ++k;
+    const QkTask& t = tab.t[k];
+    int64_t i, j;
+    pair_of(t, p - tab.pair_begin[k], i, j);
+    sweep_pair<T>(t, i, j, sm);
+  }
+}
+
+}  // namespace
+
+bool qk_sweep_big_supports(int T) { return T == 8 || T == 16 || T == 32 || T == 64; }
+
+hipError_t qk_launch_sweep_big(const QkTask* tasks, int n_tasks, int cus, hipStream_t s) {
+  if (n_tasks < 1 || n_tasks > QK_MAX_TASKS) return hipErrorInvalidValue;
+  const int T = tasks[0].T;
+  BigTable tab{};
+  int64_t acc = 0;
+  for (int k = 0; k < n_tasks; ++k) {
+    if (tasks[k].T != T) return hipErrorInvalidValue;  // one launch per bond dimension
+    tab.t[k] = tasks[k];
+    tab.pair_begin[k] = acc;
+    acc += tasks[k].symmetric ? tasks[k].na * (tasks[k].na + 1) / 2 : tasks[k].na * tasks[k].nb;
+  }
+  tab.pair_begin[n_tasks] = acc;
+  tab.n_tasks = n_tasks;
+  if (acc == 0) return hipSuccess;
+  // LDS per workgroup 2 T^2 x 16 B: one workgroup per CU at T = 64
+  const int per_cu = T == 64 ? 1 : (T == 32 ? 4 : 8);
+  const int grid = (int)std::min<int64_t>(acc, (int64_t)cus * per_cu);
+  switch (T) {
+    case 8: hipLaunchKernelGGL(sweep_big_kernel<8>, dim3(grid), dim3(kBigThreads), 0, s, tab); break;
+    case 16: hipLaunchKernelGGL(sweep_big_kernel<16>, dim3(grid), dim3(kBigThreads), 0, s, tab); break;
+    case 32: hipLaunchKernelGGL(sweep_big_kernel<32>, dim3(grid), dim3(kBigThreads), 0, s, tab); break;
+    case 64: hipLaunchKernelGGL(sweep_big_kernel<64>, dim3(grid), dim3(kBigThreads), 0, s, tab); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}

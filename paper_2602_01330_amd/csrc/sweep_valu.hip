@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include "qk_internal.h"
+#include "qk_sweep_ops.h"
 
 namespace {
 
@@ -57,26 +58,6 @@ __device__ inline float pow2(float, int e) {  // 2^e for -126 <= e <= 127
   return __uint_as_float((unsigned)(e + 127) << 23);
 }
 
-
-// The two accumulation steps of a site, as explicit FMA sequences: the tile
-// kernel and the pair-level refinement both use them, so a refined pair
-// carries the tile kernel's FP64 value bit for bit.
-//   G[a][b'] += E[a][b] B^s[b][b']            (complex)
-//   E'[a'][b'] += conj(A^s[a][a']) G[a][b']   (complex)
-template <typename R, typename C>
-__device__ inline void g_acc(R& gr, R& gi, R er, R ei, C bv) {
-  gr = fma(er, (R)bv.x, gr);
-  gr = fma(-ei, (R)bv.y, gr);
-  gi = fma(er, (R)bv.y, gi);
-  gi = fma(ei, (R)bv.x, gi);
-}
-template <typename R, typename C>
-__device__ inline void e_acc(R& nr, R& ni, C av, R gr, R gi) {
-  nr = fma((R)av.x, gr, nr);
-  nr = fma((R)av.y, gi, nr);
-  ni = fma((R)av.x, gi, ni);
-  ni = fma(-(R)av.y, gr, ni);
-}
 
 template <typename R, int T>
 struct SweepSmem {

@@ -270,3 +270,31 @@ def test_build_many_equals_separate_builds(qk):
     assert np.all(np.isfinite(outs[0])) and np.array_equal(outs[0], outs[1])
     with pytest.raises(qk.QkError):
         qk.qk_mps_build_many([xd] * 9, 2, 64)
+
+
+@pytest.mark.parametrize("d,L,chi_max,T", [(8, 3, 64, 8), (10, 4, 64, 16), (12, 5, 64, 32),
+                                           (14, 8, 64, 64)])
+def test_large_bond_sweep_on_oracle_mps(qk, d, L, chi_max, T):
+    """Bonds above 4 (more layers; the last case truncates at chi_max = 64):
+    oracle-built MPS uploaded and swept by the large-bond FP64 kernel, every
+    pair, symmetric and rectangular, against the oracle's own sweep."""
+    X, _ = gen_clusters(9, d, 300 + d)
+    Y, _ = gen_clusters(5, d, 400 + d)
+    MX, MY = mps.build_batch(X, L, chi_max), mps.build_batch(Y, L, chi_max)
+    assert max(max(t.shape[2] for t in m) for m in MX) > T // 2  # really uses chi_pad = T
+    cx, tx = oracle_import_layout(MX, T)
+    cy, ty = oracle_import_layout(MY, T)
+    bx = qk.qk_mps_import(cx, tx, L, chi_max)
+    by = qk.qk_mps_import(cy, ty, L, chi_max)
+    print(f"[large bond] d={d} L={L} chi_pad={T}", flush=True)
+    ln_s = torch.full((9, 9), float("nan"), dtype=torch.float64, device="cuda")
+    qk.qk_overlap_gram(bx, bx, True, "auto", None, ln_s)
+    ln_r = torch.full((5, 9), float("nan"), dtype=torch.float64, device="cuda")
+    qk.qk_overlap_gram(by, bx, False, "fp64", None, ln_r)
+    torch.cuda.synchronize()
+    _, LN = mps.gram(mps.pad_batch(MX), mps.pad_batch(MX), symmetric=True)
+    _, LN2 = mps.gram(mps.pad_batch(MY), mps.pad_batch(MX))
+    assert np.abs(ln_s.cpu().numpy() - LN).max() < 1e-8
+    assert np.abs(ln_r.cpu().numpy() - LN2).max() < 1e-8
+    with pytest.raises(qk.QkError):  # the reduced forms stop at chi_pad 4
+        qk.qk_overlap_gram(bx, bx, True, "fp32_mfma", None, ln_s)
