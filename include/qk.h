@@ -101,13 +101,15 @@ typedef struct qk_mps_batch qk_mps_batch; /* opaque, device-resident, library-ow
  *            min(chi_max, 2^min(n_layers, floor(n_qubits/2))) (1 when
  *            entangle = 0), the exact bond bound of this circuit family;
  *            tensors are padded to chi_pad = the power of two >= chi_ws;
- *            chi_ws <= 16 is supported.
+ *            chi_ws <= 64 is supported (from 32 on, the build holds each
+ *            sample's merged matrix in a temporary device workspace of
+ *            about 0.8 MB per sample at 64).
  *   x_dev    n_samples x n_qubits FP64 features, row-major, leading dim ld_x.
  *            Must be finite (checked on the device, reported by qk_mps_info).
  *   store    QK_STORE_* mask of packed forms to keep.
  *   out      receives a new batch; release it with qk_mps_release.
  * Errors: INVALID_ARG (bad desc, null pointers, ld_x < n_qubits),
- *         UNSUPPORTED (chi_ws > 16), OUT_OF_MEMORY, HIP.
+ *         UNSUPPORTED (chi_ws > 64), OUT_OF_MEMORY, HIP.
  */
 QK_API qk_status qk_mps_build(const qk_circuit_desc* c, const double* x_dev,
                        int64_t n_samples, int64_t ld_x, uint32_t store,

@@ -13,6 +13,8 @@
 // so the FP64 sweep reads the build's output directly.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "qk_internal.h"
 
 namespace {
@@ -236,16 +238,40 @@ struct BuildSmem {
   double S[D];
   int perm[D];
 };
+// From W = 32 on, X, V and the two site copies (192 KB at W = 32, 768 KB at
+// W = 64) exceed LDS and live in a per-sample global workspace of
+// kBuildWsPerSample<W> complex; only the singular values and their order
+// stay in LDS.
+template <int W>
+constexpr int64_t kBuildWsPerSample = W >= 32 ? (int64_t)2 * (2 * W) * (2 * W) + 4 * W * W : 0;
+template <int W>
+struct BuildSmemSmall {
+  double S[2 * W];
+  int perm[2 * W];
+};
 
 template <int W>
 __global__ __launch_bounds__(64) void mps_build_kernel(
     const double* __restrict__ x, int64_t ld_x, int64_t N, int nq, int n_layers,
     int chi_max, int entangle, double cutoff, double2* __restrict__ t64,
-    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status) {
+    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status, double2* __restrict__ ws) {
   constexpr int D = 2 * W;
-  __shared__ BuildSmem<W> sm;
+  constexpr bool kGlobal = W >= 32;
+  __shared__ std::conditional_t<kGlobal, BuildSmemSmall<W>, BuildSmem<W>> sm;
   const int64_t i = blockIdx.x;
   const int lane = threadIdx.x;
+  double2 *X, *V, *sa, *sb;
+  if constexpr (kGlobal) {
+    X = ws + i * kBuildWsPerSample<W>;
+    V = X + D * D;
+    sa = V + D * D;
+    sb = sa + 2 * W * W;
+  } else {
+    X = sm.X;
+    V = sm.V;
+    sa = sm.sa;
+    sb = sm.sb;
+  }
   // the packed bond block is W x W (W is the batch's padded bond dimension),
   // so every layout index below is a compile-time shift or mask
   constexpr int T = W, TT = W * W, slot = 2 * TT;
@@ -292,8 +318,8 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
       // stage the two sites (realized blocks) in LDS, W x W padded
       for (int e = lane; e < 2 * W * W; e += 64) {
         int s = e / (W * W), r = e % (W * W), a = r / W, b = r % W;
-        sm.sa[e] = (a < T && b < T) ? site(k)[s * TT + a * T + b] : make_double2(0, 0);
-        sm.sb[e] = (a < T && b < T) ? site(k + 1)[s * TT + a * T + b] : make_double2(0, 0);
+        sa[e] = (a < T && b < T) ? site(k)[s * TT + a * T + b] : make_double2(0, 0);
+        sb[e] = (a < T && b < T) ? site(k + 1)[s * TT + a * T + b] : make_double2(0, 0);
       }
       __syncthreads();
       // Theta[(s,a)][(t,c)], rows s*cl + a, cols t*cr + c
@@ -313,44 +339,44 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
         const int row = s * cl + a, col = t * cr + c;
         double2 acc = make_double2(0, 0);
         for (int b = 0; b < cm; ++b)
-          acc = cadd(acc, cmul(sm.sa[s * W * W + a * W + b], sm.sb[t * W * W + b * W + c]));
+          acc = cadd(acc, cmul(sa[s * W * W + a * W + b], sb[t * W * W + b * W + c]));
         // exp(-i theta/2 sigma_s sigma_t)
         double2 ph = (s == t) ? make_double2(ch, -sh) : make_double2(ch, sh);
         acc = cmul(ph, acc);
         fro += acc.x * acc.x + acc.y * acc.y;
-        if (!transpose) sm.X[col * D + row] = acc;
-        else sm.X[row * D + col] = make_double2(acc.x, -acc.y);
+        if (!transpose) X[col * D + row] = acc;
+        else X[row * D + col] = make_double2(acc.x, -acc.y);
       }
       const int XCe = XC + (XC & 1);  // even column count
       for (int e = lane; e < D * D; e += 64) {
         int col = e / D, row = e % D;
-        if (col >= XC && col < XCe) sm.X[e] = make_double2(0, 0);
-        sm.V[e] = make_double2((col == row && col < XCe) ? 1.0 : 0.0, 0.0);
+        if (col >= XC && col < XCe) X[e] = make_double2(0, 0);
+        V[e] = make_double2((col == row && col < XCe) ? 1.0 : 0.0, 0.0);
       }
       __syncthreads();
       for (int off = 1; off < 64; off <<= 1) fro += __shfl_xor(fro, off, 64);
       const bool conv = (D == 8 && XR == 8 && XCe == 8)
-                            ? jacobi_8x8(sm.X, sm.V, 1e-30 * fro)
-                            : jacobi_columns<D>(sm.X, sm.V, XR, XCe, 1e-30 * fro);
+                            ? jacobi_8x8(X, V, 1e-30 * fro)
+                            : jacobi_columns<D>(X, V, XR, XCe, 1e-30 * fro);
       if (!conv && lane == 0) atomicOr(status, QK_FLAG_NOCONV);
       // singular values = column norms; rank them (descending, stable)
-      if (lane < XCe) {
+      for (int cc = lane; cc < XCe; cc += 64) {
         double s2 = 0.0;
         for (int row = 0; row < XR; ++row) {
-          double2 v = sm.X[lane * D + row];
+          double2 v = X[cc * D + row];
           s2 += v.x * v.x + v.y * v.y;
         }
-        sm.S[lane] = sqrt(s2);
+        sm.S[cc] = sqrt(s2);
       }
       __syncthreads();
-      if (lane < XCe) {
-        double mine = sm.S[lane];
+      for (int cc = lane; cc < XCe; cc += 64) {
+        double mine = sm.S[cc];
         int rank = 0;
         for (int j = 0; j < XCe; ++j) {
           double o = sm.S[j];
-          rank += (o > mine) || (o == mine && j < lane);
+          rank += (o > mine) || (o == mine && j < cc);
         }
-        sm.perm[rank] = lane;
+        sm.perm[rank] = cc;
       }
       __syncthreads();
       const double s0 = sm.S[sm.perm[0]];
@@ -385,8 +411,8 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
           int pj = sm.perm[j], row = s * cl + a;
           double Sj = sm.S[pj];
           double2 u;
-          if (!transpose) u = Sj > 0.0 ? cscale(sm.X[pj * D + row], 1.0 / Sj) : make_double2(0, 0);
-          else u = sm.V[pj * D + row];
+          if (!transpose) u = Sj > 0.0 ? cscale(X[pj * D + row], 1.0 / Sj) : make_double2(0, 0);
+          else u = V[pj * D + row];
           v = l2r ? u : cscale(u, Sj * inv_norm);
         }
         site(k)[e] = v;
@@ -399,10 +425,10 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
           double Sj = sm.S[pj];
           double2 h;
           if (!transpose) {
-            double2 q = sm.V[pj * D + col];
+            double2 q = V[pj * D + col];
             h = make_double2(q.x, -q.y);
           } else {
-            double2 q = sm.X[pj * D + col];
+            double2 q = X[pj * D + col];
             h = Sj > 0.0 ? make_double2(q.x / Sj, -q.y / Sj) : make_double2(0, 0);
           }
           v = l2r ? cscale(h, Sj * inv_norm) : h;
@@ -865,12 +891,20 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
     const QkBuildPart part{x, ld_x, n, t64, chi, status};
     return qk_launch_build_many(&part, 1, nq, n_layers, chi_max, entangle, cutoff, chi_ws, T, s);
   }
+  // bond bounds of 32 and 64: X, V and the site copies of each sample in a
+  // stream-ordered global workspace for the duration of the build
+  double2* ws = nullptr;
+  if (T >= 32) {
+    const int64_t per = T == 32 ? kBuildWsPerSample<32> : kBuildWsPerSample<64>;
+    const hipError_t ea = hipMallocAsync((void**)&ws, n * per * sizeof(double2), s);
+    if (ea != hipSuccess) return ea;
+  }
   dim3 grid((unsigned)n), block(64);
 #define QK_BUILD_CASE(WV)                                                     \
   case WV:                                                                    \
     hipLaunchKernelGGL(mps_build_kernel<WV>, grid, block, 0, s, x, ld_x, n,   \
                        nq, n_layers, chi_max, entangle, cutoff, t64, chi,     \
-                       status);                                               \
+                       status, ws);                                           \
     break;
   switch (T) {
     QK_BUILD_CASE(1)
@@ -878,11 +912,15 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
     QK_BUILD_CASE(4)
     QK_BUILD_CASE(8)
     QK_BUILD_CASE(16)
+    QK_BUILD_CASE(32)
+    QK_BUILD_CASE(64)
     default:
       return hipErrorInvalidValue;
   }
 #undef QK_BUILD_CASE
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  if (ws) (void)hipFreeAsync(ws, s);  // stream-ordered: after the build
+  return e;
 }
 
 hipError_t qk_launch_build_many(const QkBuildPart* parts, int n_parts, int nq, int n_layers,

@@ -399,7 +399,7 @@ qk_status qk_mps_build(const qk_circuit_desc* c, const double* x_dev,
     return fail(QK_ERR_INVALID_ARG, "store must be a non-empty QK_STORE_* mask");
   const int ws = chi_bound(c);
   const int T = pow2_ceil(ws);
-  if (T > 16) return fail(QK_ERR_UNSUPPORTED, "bond bound above 16 is not supported by the build");
+  if (T > 64) return fail(QK_ERR_UNSUPPORTED, "bond bound above 64 is not supported by the build");
   hipStream_t s = (hipStream_t)hip_stream;
   qk_mps_batch* b = nullptr;
   st = alloc_batch(c, n_samples, T, store, s, &b);
@@ -440,7 +440,7 @@ qk_status qk_mps_build_many(const qk_circuit_desc* c, int32_t n_inputs,
     return fail(QK_ERR_INVALID_ARG, "store must be a non-empty QK_STORE_* mask");
   const int ws = chi_bound(c);
   const int T = pow2_ceil(ws);
-  if (T > 16) return fail(QK_ERR_UNSUPPORTED, "bond bound above 16 is not supported by the build");
+  if (T > 64) return fail(QK_ERR_UNSUPPORTED, "bond bound above 64 is not supported by the build");
   hipStream_t s = (hipStream_t)hip_stream;
   qk_mps_batch* b[QK_MAX_BUILD_PARTS] = {};
   QkBuildPart parts[QK_MAX_BUILD_PARTS];

@@ -298,3 +298,23 @@ def test_large_bond_sweep_on_oracle_mps(qk, d, L, chi_max, T):
     assert np.abs(ln_r.cpu().numpy() - LN2).max() < 1e-8
     with pytest.raises(qk.QkError):  # the reduced forms stop at chi_pad 4
         qk.qk_overlap_gram(bx, bx, True, "fp32_mfma", None, ln_s)
+
+
+@pytest.mark.parametrize("d,L,chi_max,tol", [(10, 5, 64, 1e-8), (16, 8, 64, None)])
+def test_large_bond_build(qk, d, L, chi_max, tol):
+    """Device build with bond bounds of 32 (exact regime) and 64 (truncating
+    at chi_max = 64: L = 8 allows 2^8): bond tables equal the oracle's, and
+    the FP64 overlaps match the oracle's MPS route (to rounding in the exact
+    regime; to the stated gates where truncation keeps 64 of up to 128
+    singular values)."""
+    X, _ = gen_clusters(9, d, 500 + d)
+    print(f"[large bond build] d={d} L={L} chi_max={chi_max}", flush=True)
+    g = gpu_gram(qk, X, L, chi_max, "fp64", True)
+    assert np.array_equal(g["chi"], oracle_chis(X, L, chi_max))
+    K, LN = oracle_gram(X, L, chi_max, symmetric=True)
+    dmax = np.abs(g["ln"] - LN).max()
+    print(f"[large bond build] max |d lnK| = {dmax:.3e}, chi_pad {g['info']['chi_pad']}", flush=True)
+    if tol is not None:
+        assert dmax < tol
+    ok, info = gates("fp64", g["kq"], K, g["ln"], LN)
+    assert ok, info
