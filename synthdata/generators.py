@@ -124,6 +124,9 @@ CONFIGS = {
     # serving: 5000 support samples per d, Poisson requests.
     "C5": Config("C5", "clusters", 5000, 0, 0, 2, 64, 1e-10, seed=5,
                  extra={"dims": C5_DIMS, "rate": 200.0, "stream_seed": 55}),
+    # truncating regime: 1000 train + 250 test images, 8 layers, chi_max 64
+    # (the bonds would reach 2^8 without the cap).
+    "S1": Config("S1", "images", 1000, 250, 784, 8, 64, 1e-10, seed=6),
 }
 
 
