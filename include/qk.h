@@ -264,7 +264,9 @@ QK_API qk_status qk_dual_mix(const double* kq_dev, int64_t ld_kq, const double* 
  * After such a sweep every pair whose K_q exceeds tau is recomputed by the
  * FP64 sweep (this needs QK_STORE_FP64 in the batches). The decision depends
  * only on that pair's own value, so a pair's result does not depend on which
- * other samples share its launch.
+ * other samples share its launch. Padded bond dimensions above 4 (the
+ * per-pair matrix-core sweep of QK_PREC_FP32_MFMA) are refined the same way,
+ * pair by pair, by the large-bond FP64 sweep.
  * Defaults: tau = 1e-2 (FP32-class forms), 1e-3 (BF16X2). tau <= 0
  * disables refinement for that form. Process-wide setting.
  */

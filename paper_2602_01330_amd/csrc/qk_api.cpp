@@ -208,6 +208,8 @@ bool supported_T(qk_precision p, int T) {
       return T == 1 || T == 2 || T == 4 || qk_sweep_big_supports(T);
     case QK_PREC_FP32:
       return T == 1 || T == 2 || T == 4;
+    case QK_PREC_FP32_MFMA:
+      return qk_mfma_supports(p, T) || qk_sweep_wide_supports(T);
     default:
       return qk_mfma_supports(p, T);
   }
@@ -235,10 +237,11 @@ void timing_mark(int which, hipStream_t s) {
 
 qk_status run_tasks(std::vector<QkTask>& tasks_in, qk_precision prec, double tau, hipStream_t s,
                     int64_t max_tiles = -1) {
-  // complex-FP64 tasks with bonds above 4 go to the large-bond kernel (one
-  // workgroup per pair); the tile kernels take the others
+  // tasks with bonds above 4 go to the per-pair kernels (one workgroup per
+  // pair: complex FP64 on VALU, or complex FP32 on the matrix cores); the
+  // tile kernels take the others
   std::vector<QkTask> tasks, big;
-  for (const QkTask& t : tasks_in) (prec == QK_PREC_FP64 && t.T > 4 ? big : tasks).push_back(t);
+  for (const QkTask& t : tasks_in) (t.T > 4 ? big : tasks).push_back(t);
   // longest-processing-time order: per-tile cost ~ nq * T^3
   std::stable_sort(tasks.begin(), tasks.end(), [](const QkTask& a, const QkTask& b) {
     return (double)a.nq * a.T * a.T * a.T > (double)b.nq * b.T * b.T * b.T;
@@ -265,16 +268,24 @@ qk_status run_tasks(std::vector<QkTask>& tasks_in, qk_precision prec, double tau
   const int grid64 = (int)std::min<int64_t>(
       acc, (int64_t)device_cus() * (tuned && prec == QK_PREC_FP64 ? te.wg_per_cu : 2));
   timing_mark(0, s);
-  if (prec == QK_PREC_FP64) {
-    if (acc > 0) QK_HIP(qk_launch_sweep_fp64(tt, grid64, nullptr, s), "sweep launch");
-    for (int T : {64, 32, 16, 8}) {  // one launch per bond dimension, largest first
-      std::vector<QkTask> group;
-      for (const QkTask& t : big)
-        if (t.T == T) group.push_back(t);
-      if (!group.empty())
-        QK_HIP(qk_launch_sweep_big(group.data(), (int)group.size(), device_cus(), s),
-               "large-bond sweep launch");
-    }
+  for (int T : {64, 32, 16, 8}) {  // one launch per bond dimension, largest first
+    std::vector<QkTask> group;
+    for (const QkTask& t : big)
+      if (t.T == T) group.push_back(t);
+    if (group.empty()) continue;
+    if (prec == QK_PREC_FP64)
+      QK_HIP(qk_launch_sweep_big(group.data(), (int)group.size(), device_cus(), s),
+             "large-bond sweep launch");
+    else if (prec == QK_PREC_FP32_MFMA)
+      QK_HIP(qk_launch_sweep_wide(group.data(), (int)group.size(), device_cus(),
+                                  tau > 0.0 ? std::log(tau) : 0.0, tau > 0.0, s),
+             "large-bond matrix-core sweep launch");
+    else
+      return fail(QK_ERR_UNSUPPORTED, "no sweep of this form for bonds above 4");
+  }
+  if (prec == QK_PREC_FP64 || acc == 0) {
+    if (prec == QK_PREC_FP64 && acc > 0)
+      QK_HIP(qk_launch_sweep_fp64(tt, grid64, nullptr, s), "sweep launch");
     timing_mark(1, s);
     timing_mark(2, s);
     g_timing.recorded = g_timing.enabled;

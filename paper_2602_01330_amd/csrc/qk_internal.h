@@ -164,6 +164,18 @@ struct QkTaskTable {
 // launch per bond dimension, every pair of the given tasks.
 bool qk_sweep_big_supports(int T);
 hipError_t qk_launch_sweep_big(const QkTask* tasks, int n_tasks, int cus, hipStream_t s);
+// The same FP64 sweep over only the listed pairs: list[0 .. *count) holds
+// global pair numbers of the table made from `tasks` (whose ta/tb must be
+// the FP64 tensors); the count is read on the device.
+hipError_t qk_launch_sweep_big_list(const QkTask* tasks, int n_tasks, const int64_t* list,
+                                    const int32_t* count, int cus, hipStream_t s);
+// Complex-FP32 matrix-core sweep for the same bond dimensions (sweep_wide.hip):
+// packed FP32 tensors, one launch per bond dimension, every pair. With
+// `refine`, pairs whose ln K_q >= ln_tau are then recomputed by the FP64
+// list sweep from the tasks' ta64/tb64.
+bool qk_sweep_wide_supports(int T);
+hipError_t qk_launch_sweep_wide(const QkTask* tasks, int n_tasks, int cus, double ln_tau,
+                                bool refine, hipStream_t s);
 
 constexpr int kQkMaskWords = 8;
 hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, const uint32_t* mask_in,

@@ -19,17 +19,12 @@
 #include <algorithm>
 
 #include "qk_internal.h"
+#include "qk_pairs.h"
 #include "qk_sweep_ops.h"
 
 namespace {
 
 constexpr int kBigThreads = 256;
-
-struct BigTable {
-  QkTask t[QK_MAX_TASKS];
-  int64_t pair_begin[QK_MAX_TASKS + 1];
-  int n_tasks;
-};
 
 template <int T>
 struct BigSmem {
@@ -38,27 +33,6 @@ struct BigSmem {
   double red[kBigThreads / 64];
   int rede[kBigThreads / 64];
 };
-
-// (i, j) of local pair l: row-major over na x nb, or the upper triangle
-// (j >= i) of n x n row by row
-__device__ inline void pair_of(const QkTask& t, int64_t l, int64_t& i, int64_t& j) {
-  if (!t.symmetric) {
-    i = l / t.nb;
-    j = l - i * t.nb;
-    return;
-  }
-  const int64_t n = t.na;
-  // rows before row i: i n - i (i - 1) / 2
-  const double b2 = 2.0 * (double)n + 1.0;
-  int64_t r = (int64_t)((b2 - sqrt(b2 * b2 - 8.0 * (double)l)) * 0.5);
-  if (r < 0) r = 0;
-  if (r > n - 1) r = n - 1;
-  auto before = [&](int64_t q) { return q * n - q * (q - 1) / 2; };
-  while (r > 0 && before(r) > l) --r;
-  while (r + 1 < n && before(r + 1) <= l) ++r;
-  i = r;
-  j = r + (l - before(r));
-}
 
 __device__ inline double wave_max(double v) {
   for (int off = 1; off < 64; off <<= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -157,33 +131,38 @@ __device__ void sweep_pair(const QkTask& t, int64_t i, int64_t j, BigSmem<T>& sm
     const double lnk = mag2 > 0.0 ? log(mag2) + 2.0 * (double)expo * 0.69314718055994530942
                                   : -INFINITY;
     const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
-    auto put = [&](double* ptr, int64_t ld, double v) {
-      if (!ptr) return;
-      ptr[i * ld + j] = v;
-      if (t.symmetric && j != i) ptr[j * ld + i] = v;
-    };
-    put(t.kq, t.ld_kq, kq);
-    put(t.lnkq, t.ld_ln, lnk);
+    qk_pair_put(t, t.kq, t.ld_kq, i, j, kq);
+    qk_pair_put(t, t.lnkq, t.ld_ln, i, j, lnk);
     if (t.fuse) {
       const double kc = exp(-t.gamma * d2);
       const double w = t.w_rows ? t.w_rows[i] : t.w;
-      put(t.kc, t.ld_kc, kc);
-      put(t.k, t.ld_k, w * kq + (1.0 - w) * kc);
+      qk_pair_put(t, t.kc, t.ld_kc, i, j, kc);
+      qk_pair_put(t, t.k, t.ld_k, i, j, w * kq + (1.0 - w) * kc);
     }
   }
   __syncthreads();  // E and the reduction slots are reused by the next pair
 }
 
 template <int T>
-__global__ __launch_bounds__(kBigThreads) void sweep_big_kernel(BigTable tab) {
+__global__ __launch_bounds__(kBigThreads) void sweep_big_kernel(QkPairTable tab) {
   __shared__ BigSmem<T> sm;
   const int64_t total = tab.pair_begin[tab.n_tasks];
   for (int64_t p = blockIdx.x; p < total; p += gridDim.x) {
-    int k = 0;
-    while (k + 1 < tab.n_tasks && tab.pair_begin[k + 1] <= p) ++k;
-    const QkTask& t = tab.t[k];
     int64_t i, j;
-    pair_of(t, p - tab.pair_begin[k], i, j);
+    const QkTask& t = qk_pair_lookup(tab, p, i, j);
+    sweep_pair<T>(t, i, j, sm);
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(kBigThreads) void sweep_big_list_kernel(QkPairTable tab,
+                                                                      const int64_t* list,
+                                                                      const int32_t* count) {
+  __shared__ BigSmem<T> sm;
+  const int32_t total = *count;
+  for (int32_t q = blockIdx.x; q < total; q += gridDim.x) {
+    int64_t i, j;
+    const QkTask& t = qk_pair_lookup(tab, list[q], i, j);
     sweep_pair<T>(t, i, j, sm);
   }
 }
@@ -193,18 +172,11 @@ __global__ __launch_bounds__(kBigThreads) void sweep_big_kernel(BigTable tab) {
 bool qk_sweep_big_supports(int T) { return T == 8 || T == 16 || T == 32 || T == 64; }
 
 hipError_t qk_launch_sweep_big(const QkTask* tasks, int n_tasks, int cus, hipStream_t s) {
-  if (n_tasks < 1 || n_tasks > QK_MAX_TASKS) return hipErrorInvalidValue;
-  const int T = tasks[0].T;
-  BigTable tab{};
-  int64_t acc = 0;
-  for (int k = 0; k < n_tasks; ++k) {
-    if (tasks[k].T != T) return hipErrorInvalidValue;  // one launch per bond dimension
-    tab.t[k] = tasks[k];
-    tab.pair_begin[k] = acc;
-    acc += tasks[k].symmetric ? tasks[k].na * (tasks[k].na + 1) / 2 : tasks[k].na * tasks[k].nb;
-  }
-  tab.pair_begin[n_tasks] = acc;
-  tab.n_tasks = n_tasks;
+  if (n_tasks < 1) return hipErrorInvalidValue;
+  const int T = tasks[0].T;  // one launch per bond dimension
+  QkPairTable tab{};
+  const int64_t acc = qk_pair_table_fill(tasks, n_tasks, T, tab);
+  if (acc < 0) return hipErrorInvalidValue;
   if (acc == 0) return hipSuccess;
   // LDS per workgroup 2 T^2 x 16 B: one workgroup per CU at T = 64
   const int per_cu = T == 64 ? 1 : (T == 32 ? 4 : 8);
@@ -214,6 +186,23 @@ hipError_t qk_launch_sweep_big(const QkTask* tasks, int n_tasks, int cus, hipStr
     case 16: hipLaunchKernelGGL(sweep_big_kernel<16>, dim3(grid), dim3(kBigThreads), 0, s, tab); break;
     case 32: hipLaunchKernelGGL(sweep_big_kernel<32>, dim3(grid), dim3(kBigThreads), 0, s, tab); break;
     case 64: hipLaunchKernelGGL(sweep_big_kernel<64>, dim3(grid), dim3(kBigThreads), 0, s, tab); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t qk_launch_sweep_big_list(const QkTask* tasks, int n_tasks, const int64_t* list,
+                                    const int32_t* count, int cus, hipStream_t s) {
+  if (n_tasks < 1) return hipErrorInvalidValue;
+  const int T = tasks[0].T;
+  QkPairTable tab{};
+  if (qk_pair_table_fill(tasks, n_tasks, T, tab) < 0) return hipErrorInvalidValue;
+  const int grid = cus * (T == 64 ? 1 : (T == 32 ? 4 : 8));
+  switch (T) {
+    case 8: hipLaunchKernelGGL(sweep_big_list_kernel<8>, dim3(grid), dim3(kBigThreads), 0, s, tab, list, count); break;
+    case 16: hipLaunchKernelGGL(sweep_big_list_kernel<16>, dim3(grid), dim3(kBigThreads), 0, s, tab, list, count); break;
+    case 32: hipLaunchKernelGGL(sweep_big_list_kernel<32>, dim3(grid), dim3(kBigThreads), 0, s, tab, list, count); break;
+    case 64: hipLaunchKernelGGL(sweep_big_list_kernel<64>, dim3(grid), dim3(kBigThreads), 0, s, tab, list, count); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -296,8 +296,53 @@ def test_large_bond_sweep_on_oracle_mps(qk, d, L, chi_max, T):
     _, LN2 = mps.gram(mps.pad_batch(MY), mps.pad_batch(MX))
     assert np.abs(ln_s.cpu().numpy() - LN).max() < 1e-8
     assert np.abs(ln_r.cpu().numpy() - LN2).max() < 1e-8
-    with pytest.raises(qk.QkError):  # the reduced forms stop at chi_pad 4
-        qk.qk_overlap_gram(bx, bx, True, "fp32_mfma", None, ln_s)
+    for form in ("fp32", "bf16x3"):  # the VALU FP32 and split-BF16 forms stop at chi_pad 4
+        with pytest.raises(qk.QkError):
+            qk.qk_overlap_gram(bx, bx, True, form, None, ln_s)
+
+
+@pytest.mark.parametrize("d,L,chi_max,T", [(8, 3, 64, 8), (10, 4, 64, 16), (12, 5, 64, 32),
+                                           (14, 8, 64, 64), (40, 8, 64, 64)])
+def test_large_bond_mfma_sweep_on_oracle_mps(qk, d, L, chi_max, T):
+    """The complex-FP32 matrix-core sweep at bonds above 4 on oracle-built MPS
+    (entries above the refinement threshold redone in FP64): symmetric (with
+    the fused RBF and mix) and rectangular Gram blocks within the stated gates
+    of the oracle's FP64 sweep, K(x, x) = 1, and every pair's bits independent
+    of where it sits in the launch."""
+    X, _ = gen_clusters(9, d, 300 + d)
+    Y, _ = gen_clusters(5, d, 400 + d)
+    MX, MY = mps.build_batch(X, L, chi_max), mps.build_batch(Y, L, chi_max)
+    assert max(max(t.shape[2] for t in m) for m in MX) > T // 2
+    cx, tx = oracle_import_layout(MX, T)
+    cy, ty = oracle_import_layout(MY, T)
+    bx = qk.qk_mps_import(cx, tx, L, chi_max)
+    by = qk.qk_mps_import(cy, ty, L, chi_max)
+    print(f"[large bond mfma] d={d} L={L} chi_pad={T}", flush=True)
+    xd, yd = dev(X), dev(Y)
+    kq = torch.full((9, 9), float("nan"), dtype=torch.float64, device="cuda")
+    ln_s = torch.full_like(kq, float("nan"))
+    fuse = {"x_rows": xd, "x_cols": xd, "gamma": 1.0 / d, "w": 0.3,
+            "kc": torch.full_like(kq, float("nan")), "k": torch.full_like(kq, float("nan"))}
+    qk.qk_overlap_gram(bx, bx, True, "fp32_mfma", kq, ln_s, fuse)
+    ln_r = torch.full((5, 9), float("nan"), dtype=torch.float64, device="cuda")
+    qk.qk_overlap_gram(by, bx, False, "fp32_mfma", None, ln_r)
+    ln_f = torch.full((9, 9), float("nan"), dtype=torch.float64, device="cuda")
+    qk.qk_overlap_gram(bx, bx, False, "fp32_mfma", None, ln_f)  # all 81 pairs, other slots
+    torch.cuda.synchronize()
+    K, LN = mps.gram(mps.pad_batch(MX), mps.pad_batch(MX), symmetric=True)
+    K2, LN2 = mps.gram(mps.pad_batch(MY), mps.pad_batch(MX))
+    ok, info = gates("fp32_mfma", kq.cpu().numpy(), K, ln_s.cpu().numpy(), LN)
+    print(f"[large bond mfma] symmetric (max|dK|, rel, max|dlnK|) = {info}", flush=True)
+    assert ok, info
+    ok, info = gates("fp32_mfma", np.exp(ln_r.cpu().numpy()), K2, ln_r.cpu().numpy(), LN2)
+    print(f"[large bond mfma] rectangular = {info}", flush=True)
+    assert ok, info
+    assert np.abs(np.diag(kq.cpu().numpy()) - 1.0).max() < 1e-5
+    kc = classical.rbf_gram(X, X, 1.0 / d)
+    assert checks.gate_a(fuse["kc"].cpu().numpy(), kc)[0]
+    assert checks.gate_a(fuse["k"].cpu().numpy(), classical.mix(K, kc, 0.3))[0]
+    up = np.triu_indices(9)
+    assert np.array_equal(ln_f.cpu().numpy()[up], ln_s.cpu().numpy()[up])
 
 
 @pytest.mark.parametrize("d,L,chi_max,tol", [(10, 5, 64, 1e-8), (16, 8, 64, None)])
