@@ -329,6 +329,66 @@ def small_configs(args):
     return out
 
 
+def chi64_sweep(args):
+    """The sweep at the truncating regime's shape: 784 sites with every
+    interior bond at 64 (bonds 1, 2, 4, ..., 64, ..., 4, 2, 1), on random
+    left-canonical MPS (seeded; the device build of such deep circuits is not
+    part of this leg), 32 row x 64 column samples = 2048 pairs, inputs
+    resident. The complex-FP32 matrix-core sweep over all pairs against the
+    complex-FP64 sweep over the first 8 rows (512 pairs)."""
+    import numpy as np
+    import torch
+
+    import paper_2602_01330_amd.qk as qk
+    from synthdata import gen_isometry_mps
+
+    nq, T, nr, nc, nsub = 784, 64, 32, 64, 8
+    log("bench: chi64 leg: generating random left-canonical MPS")
+    cr, tr = gen_isometry_mps(nr, nq, T, seed=71)
+    cc, tc = gen_isometry_mps(nc, nq, T, seed=72)
+    br = qk.qk_mps_import(cr, tr, 8, T)
+    bs = qk.qk_mps_import(cr[:nsub], tr[:, :nsub], 8, T, store=qk.QK_STORE_FP64)
+    bc = qk.qk_mps_import(cc, tc, 8, T)
+    del tr, tc
+    flop_pair = algorithmic_flops(cr[:1], cc[:1], False)
+    ln = torch.empty((nr, nc), dtype=torch.float64, device="cuda")
+
+    def timed(rows, form, reps):
+        qk.qk_set_launch_timing(True)
+        ms = []
+        for _ in range(reps):
+            qk.qk_overlap_gram(rows, bc, False, form, None, ln[:qk.qk_mps_info(rows)["n_samples"]])
+            ms.append(qk.qk_last_launch_ms()[0])
+        qk.qk_set_launch_timing(False)
+        return float(np.median(ms))
+
+    timed(br, "fp32_mfma", 1)  # warmup
+    ms32 = timed(br, "fp32_mfma", 3)
+    refined = int((ln >= math.log(1e-2)).sum().item())
+    ms64 = timed(bs, "fp64", 1)
+    pairs32, pairs64 = nr * nc, nsub * nc
+    tf32 = pairs32 * flop_pair / (ms32 / 1e3) / 1e12
+    res = {
+        "workload": f"{nq} sites, bonds up to {T} (chi_pad {T}), random left-canonical MPS, "
+                    f"{nr} x {nc} pairs",
+        "form": "fp32_mfma", "kernel": "sweep_wide_kernel<64> (+ FP64 list pass, "
+                                       f"{refined} pairs refined)",
+        "kernel_ms": ms32, "entries_per_s": pairs32 / (ms32 / 1e3),
+        "algorithmic_flop_per_pair": flop_pair,
+        "roofline": {"bound": "mfma", "achieved": tf32, "peak": 157.3, "unit": "TFLOP/s",
+                     "frac": tf32 / 157.3},
+        "plain_fp64": {"pairs": pairs64, "kernel_ms": ms64,
+                       "entries_per_s": pairs64 / (ms64 / 1e3),
+                       "achieved_tflops": pairs64 * flop_pair / (ms64 / 1e3) / 1e12},
+    }
+    res["speedup_vs_plain_fp64"] = res["entries_per_s"] / res["plain_fp64"]["entries_per_s"]
+    log(f"bench: chi64 leg: fp32_mfma {ms32:.1f} ms for {pairs32} pairs ({tf32:.1f} TF/s), "
+        f"fp64 {ms64:.1f} ms for {pairs64} pairs")
+    for b in (br, bs, bc):
+        b.close()
+    return res
+
+
 def run(args):
     import numpy as np
     import torch
@@ -453,6 +513,8 @@ def run(args):
         line["plain_fp64"] = {"value": pairs / (p["ms_per_step"] / 1e3),
                               "ms_per_step": p["ms_per_step"], "sweep_ms": p["sweep_ms"]}
         line["speedup_vs_plain_fp64"] = value / line["plain_fp64"]["value"]
+    if not args.no_chi64:
+        line["chi64_sweep"] = chi64_sweep(args)
     if not args.no_ragged:
         log("bench: ragged multi-d run")
         line["ragged"] = ragged(args)
@@ -479,6 +541,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-ragged", action="store_true", help="skip the ten-d ragged run")
+    ap.add_argument("--no-chi64", action="store_true",
+                    help="skip the 784-site bond-64 sweep leg")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the two smaller whole-job configurations")
     ap.add_argument("--serve-seconds", type=float, default=20.0,

@@ -9,6 +9,7 @@ from .generators import (  # noqa: F401
     CONFIGS,
     gen_clusters,
     gen_images,
+    gen_isometry_mps,
     gen_requests,
     config_inputs,
 )

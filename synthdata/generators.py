@@ -88,6 +88,46 @@ def gen_requests(seed, rate_per_s: float, duration_s: float,
     return out
 
 
+def gen_isometry_mps(n: int, nq: int, chi_max: int, seed, distinct_interior: int = 16):
+    """Random left-canonical MPS with the widest bond profile a chi_max cap
+    allows: chi_k = min(2^k, 2^(nq - k), chi_max). Timing and invariant
+    inputs for the overlap sweep at large bond dimensions; they stand for no
+    circuit.
+
+    Returns (chi, tensors) in the library's import layout: chi int32
+    (n, nq + 1), tensors complex128 [nq][n][2][T][T] with T = chi_max and
+    tensors[k, i, s, a, b] = A_i^s[a][b] of site k. Each site tensor is the Q
+    factor of a complex Gaussian (2 chi_l) x chi_r matrix, row s chi_l + a
+    holding A^s[a][:], so sum_s A^{s dagger} A^s = I and every state has
+    unit norm. Sites with chi_l = chi_r = chi_max cycle through
+    ``distinct_interior`` draws per sample (saves host time at nq = 784).
+    Draw order: per sample, the distinct interior draws, then every other
+    site left to right.
+    """
+    rng = np.random.default_rng(seed)
+    T = chi_max
+    chi = np.array([min(2 ** min(k, 30), 2 ** min(nq - k, 30), chi_max)
+                    for k in range(nq + 1)], dtype=np.int32)
+
+    def draw(cl, cr):
+        m = rng.standard_normal((2 * cl, cr)) + 1j * rng.standard_normal((2 * cl, cr))
+        q, _ = np.linalg.qr(m)
+        return q.reshape(2, cl, cr)
+
+    tens = np.zeros((nq, n, 2, T, T), dtype=np.complex128)
+    for i in range(n):
+        inner = [draw(T, T) for _ in range(distinct_interior)]
+        u = 0
+        for k in range(nq):
+            cl, cr = int(chi[k]), int(chi[k + 1])
+            if cl == T and cr == T:
+                tens[k, i] = inner[u % distinct_interior]
+                u += 1
+            else:
+                tens[k, i, :, :cl, :cr] = draw(cl, cr)
+    return np.tile(chi, (n, 1)), tens
+
+
 @dataclass(frozen=True)
 class Config:
     name: str

@@ -27,3 +27,11 @@ def oracle_gram(X, L, chi_max, symmetric=False, Y=None):
 
 def oracle_chis(X, L, chi_max):
     return np.array([mps.build_mps(x, L, chi_max)[1] for x in X], dtype=np.int32)
+
+
+def import_layout_to_oracle(chi, ten):
+    """Inverse of oracle_import_layout: per sample, the list of (l, s, r)
+    site tensors of its own bond dimensions."""
+    nq, n = ten.shape[0], ten.shape[1]
+    return [[np.ascontiguousarray(ten[k, i, :, :chi[i, k], :chi[i, k + 1]].transpose(1, 0, 2))
+             for k in range(nq)] for i in range(n)]

@@ -68,3 +68,46 @@ def test_c3_full_gram_sampled(prec, ln_tol):
     assert kq.min() >= 0.0 and kq.max() <= 1.0 + 1e-5
     kc = A["kc"].cpu().numpy()
     assert np.array_equal(np.diag(kc), np.ones(4000))
+
+
+def test_chi64_sweep_784_sites_sampled():
+    """The sweep at the truncating regime's full shape: 784 sites with every
+    interior bond at 64 (random left-canonical MPS, 4 row and 8 column
+    samples). The matrix-core FP32 form and the FP64 form against the
+    oracle's sweep on sampled pairs; the symmetric block's diagonal is 1
+    (FP64-refined) and the rectangular block is bitwise the same as the
+    matching entries of a launch that also holds other pairs."""
+    import paper_2602_01330_amd.qk as qk
+    from oracle import mps
+    from synthdata import gen_isometry_mps
+    from tests._util import import_layout_to_oracle
+
+    print("[chi64 784] generating", flush=True)
+    cr, tr = gen_isometry_mps(4, 784, 64, seed=31)
+    cc, tc = gen_isometry_mps(8, 784, 64, seed=32)
+    br = qk.qk_mps_import(cr, tr, 8, 64)
+    bc = qk.qk_mps_import(cc, tc, 8, 64)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    ln32 = torch.full((4, 8), float("nan"), **f64)
+    ln64 = torch.full((4, 8), float("nan"), **f64)
+    lns = torch.full((8, 8), float("nan"), **f64)
+    print("[chi64 784] sweeping", flush=True)
+    qk.qk_overlap_gram(br, bc, False, "fp32_mfma", None, ln32)
+    qk.qk_overlap_gram(br, bc, False, "fp64", None, ln64)
+    qk.qk_overlap_gram(bc, bc, True, "fp32_mfma", None, lns)
+    torch.cuda.synchronize()
+    ln32, ln64, lns = ln32.cpu().numpy(), ln64.cpu().numpy(), lns.cpu().numpy()
+    assert np.all(np.isfinite(ln32)) and np.all(ln32 < -50)  # distinct random states
+    assert np.abs(np.diag(lns)).max() < 1e-8
+    pairs = [(0, 0), (1, 5), (2, 3), (3, 7)]
+    print("[chi64 784] oracle on 4 pairs", flush=True)
+    PA = mps.pad_batch(import_layout_to_oracle(cr, tr))
+    PB = mps.pad_batch(import_layout_to_oracle(cc, tc))
+    ref = mps.ln_kernel_pairs(PA, PB, pairs)
+    got32 = np.array([ln32[i, j] for i, j in pairs])
+    got64 = np.array([ln64[i, j] for i, j in pairs])
+    print(f"[chi64 784] max |d lnK| fp32_mfma {np.abs(got32 - ref).max():.3e}, "
+          f"fp64 {np.abs(got64 - ref).max():.3e}", flush=True)
+    assert checks.gate_b(got32, ref, tol=1e-3)[0]
+    assert np.abs(got64 - ref).max() < 1e-8
+    assert checks.gate_b(ln32, ln64, tol=1e-3)[0]

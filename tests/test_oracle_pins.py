@@ -9,7 +9,9 @@ Each test names what fixes the expected value:
 * the exact bond-dimension bound 2^L of this circuit family;
 * the truncation error bound (discarded weight) on up to 14 qubits;
 * scipy's cdist for the RBF of Eq. (3); the endpoints of Eq. (11);
-* Gram-matrix invariants (unit diagonal, symmetry, range, PSD).
+* Gram-matrix invariants (unit diagonal, symmetry, range, PSD);
+* brute-force statevector overlaps of random left-canonical MPS (bonds up
+  to 8, not made by the circuit).
 """
 import math
 
@@ -18,7 +20,8 @@ import pytest
 
 from oracle import checks, circuit, classical, closed_form, mps, pathsum
 from oracle import statevector as sv
-from synthdata import config_inputs, gen_clusters
+from synthdata import config_inputs, gen_clusters, gen_isometry_mps
+from tests._util import import_layout_to_oracle
 
 
 def _rand(n, seed):
@@ -219,3 +222,22 @@ def test_tolerance_gates():
     assert not ok
     ok, _ = checks.gate_b(np.array([-np.inf]), np.array([-np.inf]))
     assert ok
+
+
+def test_sweep_on_random_isometries_vs_statevector():
+    """The transfer-matrix sweep (Eqs. (9), (10)) on MPS that no circuit made:
+    random left-canonical tensors with bonds 1, 2, 4, 8, ..., 8, 4, 2, 1 over
+    11 sites. Each state has unit norm, and every overlap equals
+    |<psi_i|psi_j>|^2 of the dense vectors."""
+    chi, ten = gen_isometry_mps(5, 11, 8, seed=21)
+    M = import_layout_to_oracle(chi, ten)
+    V = np.stack([mps.to_state(m) for m in M])
+    assert np.allclose(np.linalg.norm(V, axis=1), 1.0, atol=1e-12)
+    for t in M[0]:  # left-canonical: sum_s A^s dagger A^s = I
+        g = np.einsum("lsr,lsq->rq", t.conj(), t)
+        assert np.allclose(g, np.eye(t.shape[2]), atol=1e-12)
+    P = mps.pad_batch(M)
+    K, _ = mps.gram(P, P)
+    ref = np.abs(V.conj() @ V.T) ** 2
+    assert np.allclose(K, ref, rtol=1e-10, atol=1e-15)
+    assert np.allclose(np.diag(K), 1.0, atol=1e-12)
