@@ -549,7 +549,12 @@ def main():
                     help="measured seconds of the serving run (0 skips it)")
     ap.add_argument("--serve-warmup", type=float, default=3.0)
     ap.add_argument("--serve-rate", type=float, default=200.0, help="requests per second")
+    ap.add_argument("--chi64-only", action="store_true",
+                    help="run only the 784-site bond-64 sweep leg and print its JSON")
     args = ap.parse_args()
+    if args.chi64_only:
+        print(json.dumps(chi64_sweep(args)), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the Gram tiles shard across GPUs without "
               "communication in the sweep, but multi-GPU execution is not implemented; "

@@ -45,23 +45,23 @@ struct WideShape {
 
 template <int T>
 struct WideSmem {
-  static constexpr int NB = WideShape<T>::NB;
-  float2 g[2][NB][NB][4][64];  // [s][row block of G][column block][register][lane]
+  static constexpr int NB = WideShape<T>::NB, TP = WideShape<T>::TP;
+  // B^s rows padded by 4 elements: the four row groups of an operand read
+  // fall on alternate halves of the banks
+  static constexpr int kPitch = TP + 4;
+  float2 g[NB][NB][4][64];  // G^s: [row block][column block][register][lane]
+  float2 b[TP][kPitch];     // B^s as (Re, Im); zero outside T x T
   float red[NB];
   double d2[NB];
 };
 
-struct Pk {
-  float m, re, im;  // (-Im, Re, Im) of one packed element
-};
-
-// Element (row, col) of one s-slice of a packed site tensor; zero in the
-// padding of T = 8.
+// Element (row, col) of one s-slice of a packed site tensor, as (-Im, Re,
+// Im); zero in the padding of T = 8.
 template <int T>
-__device__ inline Pk ld_pk(const float* slice, int row, int col) {
-  if (T < 16 && (row >= T || col >= T)) return Pk{0.f, 0.f, 0.f};
+__device__ inline float3 ld_pk(const float* slice, int row, int col) {
+  if (T < 16 && (row >= T || col >= T)) return make_float3(0.f, 0.f, 0.f);
   const float* p = slice + ((int64_t)row * T + col) * kQkPackFloats;
-  return Pk{p[0], p[1], p[2]};
+  return make_float3(p[0], p[1], p[2]);
 }
 
 __device__ inline f4 mma(float a, float b, f4 c) {
@@ -76,6 +76,32 @@ __device__ inline double wave_dsum(double v) {
   for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+
+// The workgroup's share of one B^s slice: (Re, Im) of elements
+// tid + kThreads m, row-major over T x T.
+template <int T>
+struct BStage {
+  static constexpr int kThreads = WideShape<T>::kThreads;
+  static constexpr int kPer = (T * T + kThreads - 1) / kThreads;
+  float2 v[kPer];
+  __device__ void load(const float* slice) {
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = threadIdx.x + kThreads * m;
+      if (T * T % kThreads == 0 || e < T * T) {
+        const float* p = slice + (int64_t)e * kQkPackFloats;
+        v[m] = make_float2(p[1], p[2]);
+      }
+    }
+  }
+  __device__ void store(WideSmem<T>& sm) const {
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = threadIdx.x + kThreads * m;
+      if (T * T % kThreads == 0 || e < T * T) sm.b[e / T][e % T] = v[m];
+    }
+  }
+};
 
 template <int T>
 __device__ void wide_pair(const QkTask& t, int64_t i, int64_t j, WideSmem<T>& sm,
@@ -95,16 +121,32 @@ __device__ void wide_pair(const QkTask& t, int64_t i, int64_t j, WideSmem<T>& sm
   const float* ta = static_cast<const float*>(t.ta);
   const float* tb = static_cast<const float*>(t.tb);
   const int nq = t.nq;
+  constexpr int64_t kS = (int64_t)T * T * kQkPackFloats;  // floats per s-slice
+  auto bslice = [&](int k, int s) { return tb + ((int64_t)k * t.nb + j) * S::kSlotFloats + s * kS; };
+  BStage<T> pf;
+  pf.load(bslice(0, 0));
   for (int k = 0; k < nq; ++k) {
     const float* A = ta + ((int64_t)k * t.na + i) * S::kSlotFloats;
-    const float* B = tb + ((int64_t)k * t.nb + j) * S::kSlotFloats;
     f4 nr[NB], ni[NB];  // E'^T tiles (column block q of E', rows a' of this wavefront)
 #pragma unroll
     for (int q = 0; q < NB; ++q) nr[q] = ni[q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      const float* Bs = B + (int64_t)s * T * T * kQkPackFloats;
-      const float* As = A + (int64_t)s * T * T * kQkPackFloats;
+      // B^s to LDS; the barrier also ends every wavefront's reads of G^{s-1}
+      pf.store(sm);
+      __syncthreads();
+      if (s == 0) {
+        pf.load(bslice(k, 1));
+      } else if (k + 1 < nq) {
+        pf.load(bslice(k + 1, 0));
+      }
+      if (s == 0 && k > 0 && k % kWideRescaleEvery == 0) {
+        // the wavefront maxima of E_k, posted at the end of the previous site
+        float mx = sm.red[0];
+#pragma unroll
+        for (int v = 1; v < NB; ++v) mx = fmaxf(mx, sm.red[v]);
+        ex_pend = mx > 0.f ? (int)((__float_as_uint(mx) >> 23) & 0xff) - 126 : 0;
+      }
       // R: rows a of this wavefront of G^s, every column block q
       f4 gr[NB], gi[NB];
 #pragma unroll
@@ -114,48 +156,42 @@ __device__ void wide_pair(const QkTask& t, int64_t i, int64_t j, WideSmem<T>& sm
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * kb + 4 * g + r;
-          Pk p[NB];
+          float2 bv[NB];
 #pragma unroll
-          for (int q = 0; q < NB; ++q) p[q] = ld_pk<T>(Bs, row, 16 * q + c);
+          for (int q = 0; q < NB; ++q) bv[q] = sm.b[row][16 * q + c];
           const float xr = er[kb][r], xi = ei[kb][r];
 #pragma unroll
-          for (int q = 0; q < NB; ++q) gr[q] = mma(xr, p[q].re, gr[q]);
+          for (int q = 0; q < NB; ++q) gr[q] = mma(xr, bv[q].x, gr[q]);
 #pragma unroll
-          for (int q = 0; q < NB; ++q) gi[q] = mma(xr, p[q].im, gi[q]);
+          for (int q = 0; q < NB; ++q) gi[q] = mma(xr, bv[q].y, gi[q]);
 #pragma unroll
-          for (int q = 0; q < NB; ++q) gr[q] = mma(xi, p[q].m, gr[q]);
+          for (int q = 0; q < NB; ++q) gr[q] = mma(xi, -bv[q].y, gr[q]);
 #pragma unroll
-          for (int q = 0; q < NB; ++q) gi[q] = mma(xi, p[q].re, gi[q]);
+          for (int q = 0; q < NB; ++q) gi[q] = mma(xi, bv[q].x, gi[q]);
         }
 #pragma unroll
       for (int q = 0; q < NB; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sm.g[s][w][q][r][lane] = make_float2(gr[q][r], gi[q][r]);
-      __syncthreads();
-      if (s == 0 && k > 0 && k % kWideRescaleEvery == 0) {
-        // the wavefront maxima of E_k, posted at the end of the previous site
-        float mx = sm.red[0];
-#pragma unroll
-        for (int v = 1; v < NB; ++v) mx = fmaxf(mx, sm.red[v]);
-        ex_pend = mx > 0.f ? (int)((__float_as_uint(mx) >> 23) & 0xff) - 126 : 0;
-      }
+        for (int r = 0; r < 4; ++r) sm.g[w][q][r][lane] = make_float2(gr[q][r], gi[q][r]);
+      __syncthreads();  // G^s visible; every wavefront is done reading B^s
       // L: E'^T += G^{s T} conj(A^s), a' in this wavefront's block
+      const float* As = A + s * kS;
 #pragma unroll
       for (int kb = 0; kb < NB; ++kb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const Pk p = ld_pk<T>(As, 16 * kb + 4 * g + r, 16 * w + c);
+          const float3 p = ld_pk<T>(As, 16 * kb + 4 * g + r, 16 * w + c);
           float2 gv[NB];
 #pragma unroll
-          for (int q = 0; q < NB; ++q) gv[q] = sm.g[s][kb][q][r][lane];
+          for (int q = 0; q < NB; ++q) gv[q] = sm.g[kb][q][r][lane];
 #pragma unroll
-          for (int q = 0; q < NB; ++q) nr[q] = mma(gv[q].x, p.re, nr[q]);
+          for (int q = 0; q < NB; ++q) nr[q] = mma(gv[q].x, p.y, nr[q]);
 #pragma unroll
-          for (int q = 0; q < NB; ++q) ni[q] = mma(gv[q].y, p.re, ni[q]);
+          for (int q = 0; q < NB; ++q) ni[q] = mma(gv[q].y, p.y, ni[q]);
 #pragma unroll
-          for (int q = 0; q < NB; ++q) nr[q] = mma(gv[q].y, p.im, nr[q]);
+          for (int q = 0; q < NB; ++q) nr[q] = mma(gv[q].y, p.z, nr[q]);
 #pragma unroll
-          for (int q = 0; q < NB; ++q) ni[q] = mma(gv[q].x, p.m, ni[q]);
+          for (int q = 0; q < NB; ++q) ni[q] = mma(gv[q].x, p.x, ni[q]);
         }
     }
     // E_{k+1}; the exponent found from E_k scales it exactly (the map is linear)
@@ -212,11 +248,15 @@ __device__ void wide_pair(const QkTask& t, int64_t i, int64_t j, WideSmem<T>& sm
 }
 
 template <int T>
-__global__ __launch_bounds__(WideShape<T>::kThreads) void sweep_wide_kernel(QkPairTable tab,
+__global__ __launch_bounds__(WideShape<T>::kThreads, 2) void sweep_wide_kernel(QkPairTable tab,
                                                                            double ln_tau,
                                                                            int64_t* list,
                                                                            int32_t* count) {
   __shared__ WideSmem<T> sm;
+  if (T < 16) {  // the staging writes only the T x T corner of B^s
+    for (int e = threadIdx.x; e < WideShape<T>::TP * WideSmem<T>::kPitch; e += blockDim.x)
+      (&sm.b[0][0])[e] = make_float2(0.f, 0.f);
+  }
   const int64_t total = tab.pair_begin[tab.n_tasks];
   for (int64_t p = blockIdx.x; p < total; p += gridDim.x) {
     int64_t i, j;
