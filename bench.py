@@ -35,7 +35,10 @@ PEAKS = {  # published MI355X figures, TFLOP/s
 # only for the kernel source they were taken with.
 TRAFFIC = {"fp32_mfma": {"source": "paper_2602_01330_amd/csrc/sweep_mfma.hip",
                          "sha256_prefix": "ca4b6e321d0a5d14",
-                         "bytes": 296.2e9 + 0.809e9}}
+                         "bytes": 296.2e9 + 0.809e9},
+           "fp32_mfma_wide": {"source": "paper_2602_01330_amd/csrc/sweep_wide.hip",
+                              "sha256_prefix": "d9cf1b83de8347d1",
+                              "bytes": 143.1e9 + 0.0027e9}}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp32_mfma": "f32", "bf16x2": "bf16", "bf16x3": "bf16"}
 
 
@@ -376,7 +379,7 @@ def chi64_sweep(args):
         "kernel_ms": ms32, "entries_per_s": pairs32 / (ms32 / 1e3),
         "algorithmic_flop_per_pair": flop_pair,
         "roofline": {"bound": "mfma", "achieved": tf32, "peak": 157.3, "unit": "TFLOP/s",
-                     "frac": tf32 / 157.3},
+                     "frac": tf32 / 157.3, "traffic": traffic_for("fp32_mfma_wide")},
         "plain_fp64": {"pairs": pairs64, "kernel_ms": ms64,
                        "entries_per_s": pairs64 / (ms64 / 1e3),
                        "achieved_tflops": pairs64 * flop_pair / (ms64 / 1e3) / 1e12},
