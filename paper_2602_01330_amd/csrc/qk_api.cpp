@@ -202,6 +202,13 @@ qk_status fill_task(QkTask& t, const qk_mps_batch* rows, const qk_mps_batch* col
   return QK_OK;
 }
 
+// The matrix-core sweep for padded bonds 8..64 (sweep_wide.hip) is switched
+// off: a GPU memory fault or hung queue ended a run of the whole GPU test
+// suite plus the benchmark in which it ran, and no cause has been shown
+// (each of its tests had passed when run on their own). Until one is, FP32
+// MFMA at bonds above 4 reports QK_ERR_UNSUPPORTED; complex FP64 serves them.
+constexpr bool kWideMfmaEnabled = false;
+
 bool supported_T(qk_precision p, int T) {
   switch (p) {
     case QK_PREC_FP64:
@@ -209,7 +216,7 @@ bool supported_T(qk_precision p, int T) {
     case QK_PREC_FP32:
       return T == 1 || T == 2 || T == 4;
     case QK_PREC_FP32_MFMA:
-      return qk_mfma_supports(p, T) || qk_sweep_wide_supports(T);
+      return qk_mfma_supports(p, T) || (kWideMfmaEnabled && qk_sweep_wide_supports(T));
     default:
       return qk_mfma_supports(p, T);
   }
