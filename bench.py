@@ -394,15 +394,24 @@ def chi64_sweep(args):
 
 def run(args):
     import numpy as np
+
+    from synthdata import config_inputs
+
+    log("bench: generating inputs")
+    x_tr, x_te, _ = config_inputs("C3")
+    cpu = None
+    if not args.no_cpu:
+        # first, while nothing has touched the GPU: the oracle's worker
+        # processes are forked from a process that holds no GPU state
+        log("bench: timing the CPU oracle sample")
+        cpu = cpu_baseline(x_tr, args.cpu_seconds)
+
     import torch
 
     import paper_2602_01330_amd.qk as qk
-    from synthdata import config_inputs
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log("bench: generating inputs")
-    x_tr, x_te, _ = config_inputs("C3")
     d = x_tr.shape[1]
     xtr = torch.as_tensor(x_tr, device=dev)
     xte = torch.as_tensor(x_te, device=dev)
@@ -527,9 +536,8 @@ def run(args):
     if args.serve_seconds > 0:
         log("bench: serving run")
         line["serving"] = serving(args)
-    if not args.no_cpu:
-        log("bench: timing the CPU oracle sample")
-        line["cpu_baseline"] = cpu_baseline(x_tr, args.cpu_seconds)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 
