@@ -62,7 +62,7 @@ typedef enum {
   QK_PREC_BF16X2 = 2,    /* split BF16 (hi+lo, 3 products) on MFMA, FP32 acc */
   QK_PREC_BF16X3 = 3,    /* split BF16 (3 pieces, 6 products) on MFMA       */
   QK_PREC_AUTO = 4,      /* fastest form that meets the stated tolerance    */
-  QK_PREC_FP32_MFMA = 5  /* complex FP32 on v_mfma_f32_16x16x4f32           */
+  QK_PREC_FP32_MFMA = 5  /* complex FP32 on v_mfma_f32_4x4x1_16b_f32       */
 } qk_precision;
 
 /* Which packed forms a batch keeps after qk_mps_build (bit mask). */
@@ -264,9 +264,7 @@ QK_API qk_status qk_dual_mix(const double* kq_dev, int64_t ld_kq, const double* 
  * After such a sweep every pair whose K_q exceeds tau is recomputed by the
  * FP64 sweep (this needs QK_STORE_FP64 in the batches). The decision depends
  * only on that pair's own value, so a pair's result does not depend on which
- * other samples share its launch. Padded bond dimensions above 4 (the
- * per-pair matrix-core sweep of QK_PREC_FP32_MFMA) are refined the same way,
- * pair by pair, by the large-bond FP64 sweep.
+ * other samples share its launch.
  * Defaults: tau = 1e-2 (FP32-class forms), 1e-3 (BF16X2). tau <= 0
  * disables refinement for that form. Process-wide setting.
  */
