@@ -13,8 +13,6 @@
 // so the FP64 sweep reads the build's output directly.
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
 #include "qk_internal.h"
 
 namespace {
@@ -238,40 +236,19 @@ struct BuildSmem {
   double S[D];
   int perm[D];
 };
-// From W = 32 on, X, V and the two site copies (192 KB at W = 32, 768 KB at
-// W = 64) exceed LDS and live in a per-sample global workspace of
-// kBuildWsPerSample<W> complex; only the singular values and their order
-// stay in LDS.
-template <int W>
-constexpr int64_t kBuildWsPerSample = W >= 32 ? (int64_t)2 * (2 * W) * (2 * W) + 4 * W * W : 0;
-template <int W>
-struct BuildSmemSmall {
-  double S[2 * W];
-  int perm[2 * W];
-};
-
 template <int W>
 __global__ __launch_bounds__(64) void mps_build_kernel(
     const double* __restrict__ x, int64_t ld_x, int64_t N, int nq, int n_layers,
     int chi_max, int entangle, double cutoff, double2* __restrict__ t64,
-    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status, double2* __restrict__ ws) {
+    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status) {
   constexpr int D = 2 * W;
-  constexpr bool kGlobal = W >= 32;
-  __shared__ std::conditional_t<kGlobal, BuildSmemSmall<W>, BuildSmem<W>> sm;
+  __shared__ BuildSmem<W> sm;
   const int64_t i = blockIdx.x;
   const int lane = threadIdx.x;
-  double2 *X, *V, *sa, *sb;
-  if constexpr (kGlobal) {
-    X = ws + i * kBuildWsPerSample<W>;
-    V = X + D * D;
-    sa = V + D * D;
-    sb = sa + 2 * W * W;
-  } else {
-    X = sm.X;
-    V = sm.V;
-    sa = sm.sa;
-    sb = sm.sb;
-  }
+  double2* X = sm.X;
+  double2* V = sm.V;
+  double2* sa = sm.sa;
+  double2* sb = sm.sb;
   // the packed bond block is W x W (W is the batch's padded bond dimension),
   // so every layout index below is a compile-time shift or mask
   constexpr int T = W, TT = W * W, slot = 2 * TT;
@@ -440,6 +417,340 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
     }
   }
   if (lane == 0) atomicMax(status + 1, chi_seen);
+}
+
+// ---------------------------------------------------------------------------
+// The TEBD build for bond bounds 32 and 64 (deep, truncating circuits): one
+// workgroup of 8 W threads per sample. The merged matrix X = Theta (R = 2
+// chi_l rows, C = 2 chi_r columns, up to 2W x 2W complex: 256 KB at W = 64)
+// lives in registers: column pair slot p (C / 2 of them) is held by the 8
+// threads 8p .. 8p + 7, thread `sub` holding rows sub + 8i of both columns.
+// A one-sided Jacobi round rotates every slot's pair with 8-lane sums and
+// then moves the columns one place along a round-robin tournament through
+// LDS (column 0 stays in slot 0; the others circulate), so that in C - 1
+// rounds every pair of columns meets once and the columns return to their
+// starting slots. V is not accumulated: with U the normalised kept columns
+// of X V = U S, the right factor S V^dagger is U^dagger Theta, formed from a
+// copy of Theta kept in a per-sample global workspace. Rotation rule,
+// tolerance, sweep limit, cutoff, chi cap, renormalisation and status flags
+// are those of mps_build_kernel.
+template <int W>
+struct BuildWgShape {
+  static constexpr int D = 2 * W;               // largest Theta dimension
+  static constexpr int kSub = 8;                // threads per column pair
+  static constexpr int kThreads = kSub * W;     // W column pairs
+  static constexpr int kRows = D / kSub;        // rows per thread
+  static constexpr int kHalf = kRows / 2;       // rows moved per exchange phase
+  static constexpr int kPitch = W + 1;          // staged site row pitch
+};
+
+template <int W>
+struct BuildWgSmem {
+  using S = BuildWgShape<W>;
+  union {
+    double2 site[2 * W * S::kPitch];                   // site k: [s][a][b], pitch W + 1
+    double2 xb[2 * S::kHalf * W * S::kSub];            // exchange: [side][row][slot][sub]
+    double2 u[S::D * W];                               // kept left vectors: [row][rank]
+  };
+  double sv[S::D];     // column norms
+  int rnk[S::D];       // rank of column c
+  int perm[S::D];      // column of rank j
+  double red[S::kThreads / 64];
+};
+
+template <int W>
+constexpr int64_t kBuildWgWsPerSample = (int64_t)(2 * W) * (2 * W);  // Theta, row-major
+
+template <int W>
+__global__ __launch_bounds__(BuildWgShape<W>::kThreads) void mps_build_wg_kernel(
+    const double* __restrict__ x, int64_t ld_x, int64_t N, int nq, int n_layers,
+    int chi_max, int entangle, double cutoff, double2* __restrict__ t64,
+    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status, double2* __restrict__ ws) {
+  using Sh = BuildWgShape<W>;
+  constexpr int D = Sh::D, kR = Sh::kRows, kH = Sh::kHalf, kP = Sh::kPitch;
+  constexpr int T = W, TT = W * W, slot = 2 * TT;
+  __shared__ BuildWgSmem<W> sm;
+  const int64_t i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int ps = tid >> 3, sub = tid & 7;  // column-pair slot, row group
+  const double* xi = x + i * ld_x;
+  int32_t* chi = chi_tab + i * (int64_t)(nq + 1);
+  double2* th = ws + i * kBuildWgWsPerSample<W>;
+  auto site = [&](int k) -> double2* { return t64 + ((int64_t)k * N + i) * slot; };
+
+  // product state |0...0>, every bond 1; reject non-finite features
+  int bad = 0;
+  for (int k = tid; k < nq; k += Sh::kThreads) bad |= !isfinite(xi[k]);
+  if (__syncthreads_or(bad) && tid == 0) atomicOr(status, QK_FLAG_NONFINITE);
+  for (int64_t e = tid; e < (int64_t)nq * slot; e += Sh::kThreads) {
+    const int k = (int)(e / slot), r = (int)(e % slot);
+    site(k)[r] = make_double2(r == 0 ? 1.0 : 0.0, 0.0);
+  }
+  for (int b = tid; b <= nq; b += Sh::kThreads) chi[b] = 1;
+  __syncthreads();
+
+  const double inv_sqrt2 = 0.70710678118654752440;
+  int chi_seen = 1;
+  for (int layer = 0; layer < n_layers; ++layer) {
+    // 1. single-qubit layer on the realized blocks:
+    //    A'[0] = e^{-ix}(A0 + A1)/sqrt2, A'[1] = e^{ix}(A0 - A1)/sqrt2
+    for (int64_t e = tid; e < (int64_t)nq * TT; e += Sh::kThreads) {
+      const int k = (int)(e / TT), r = (int)(e % TT), a = r / T, b = r % T;
+      if (a >= chi[k] || b >= chi[k + 1]) continue;
+      double sn, cs;
+      sincos(xi[k], &sn, &cs);
+      double2* A = site(k);
+      const double2 a0 = A[r], a1 = A[TT + r];
+      const double2 uu = cscale(cadd(a0, a1), inv_sqrt2);
+      const double2 vv = cscale(make_double2(a0.x - a1.x, a0.y - a1.y), inv_sqrt2);
+      A[r] = cmul(make_double2(cs, -sn), uu);
+      A[TT + r] = cmul(make_double2(cs, sn), vv);
+    }
+    __syncthreads();
+    if (nq == 1) continue;
+
+    // 2. entangler chain
+    const bool l2r = (layer % 2) == 0;
+    for (int step = 0; step < nq - 1; ++step) {
+      const int k = l2r ? step : (nq - 2 - step);
+      const int cl = chi[k], cm = chi[k + 1], cr = chi[k + 2];
+      const int R = 2 * cl, C = 2 * cr, P = cr;  // rows, columns, column pairs
+      const bool live = ps < P;
+      double theta = 0.0;
+      if (entangle) theta = 2.0 * (kPi - xi[k]) * (kPi - xi[k + 1]);
+      double sh, ch;
+      sincos(0.5 * theta, &sh, &ch);
+      // stage site k (realized block) in LDS, rows padded to W + 1
+      for (int e = tid; e < 2 * TT; e += Sh::kThreads) {
+        const int s = e / TT, r = e % TT, a = r / T, b = r % T;
+        if (a < cl && b < cm) sm.site[(s * W + a) * kP + b] = site(k)[e];
+      }
+      __syncthreads();
+      // Theta[(s,a)][(t,c)] = ph(s,t) sum_b A_k^s[a][b] A_{k+1}^t[b][c], rows
+      // s cl + a, columns t cr + c; this slot's columns are p = ps, q = C-1-ps
+      double2 xp[kR], xq[kR];
+      int rs[kR], ra[kR];
+#pragma unroll
+      for (int m = 0; m < kR; ++m) {
+        xp[m] = xq[m] = make_double2(0.0, 0.0);
+        const int row = sub + 8 * m;
+        rs[m] = row < R ? row / cl : 0;
+        ra[m] = row < R ? row - rs[m] * cl : 0;
+      }
+      const int colp = ps, colq = C - 1 - ps;
+      const int tp = live ? colp / cr : 0, cp = live ? colp - tp * cr : 0;
+      const int tq = live ? colq / cr : 0, cq = live ? colq - tq * cr : 0;
+      if (live) {
+        const double2* B = site(k + 1);
+        for (int b = 0; b < cm; ++b) {
+          const double2 bp = B[tp * TT + b * T + cp];
+          const double2 bq = B[tq * TT + b * T + cq];
+#pragma unroll
+          for (int m = 0; m < kR; ++m) {
+            if (sub + 8 * m < R) {
+              const double2 av = sm.site[(rs[m] * W + ra[m]) * kP + b];
+              xp[m] = cadd(xp[m], cmul(av, bp));
+              xq[m] = cadd(xq[m], cmul(av, bq));
+            }
+          }
+        }
+      }
+      double fro = 0.0;
+#pragma unroll
+      for (int m = 0; m < kR; ++m) {
+        const int row = sub + 8 * m;
+        if (live && row < R) {
+          // exp(-i theta/2 sigma_s sigma_t)
+          xp[m] = cmul(rs[m] == tp ? make_double2(ch, -sh) : make_double2(ch, sh), xp[m]);
+          xq[m] = cmul(rs[m] == tq ? make_double2(ch, -sh) : make_double2(ch, sh), xq[m]);
+          th[row * D + colp] = xp[m];
+          th[row * D + colq] = xq[m];
+          fro += xp[m].x * xp[m].x + xp[m].y * xp[m].y + xq[m].x * xq[m].x + xq[m].y * xq[m].y;
+        }
+      }
+      for (int off = 1; off < 64; off <<= 1) fro += __shfl_xor(fro, off, 64);
+      if ((tid & 63) == 0) sm.red[tid >> 6] = fro;
+      __syncthreads();  // also: every thread is done reading the staged site
+      fro = 0.0;
+#pragma unroll
+      for (int v = 0; v < Sh::kThreads / 64; ++v) fro += sm.red[v];
+      const double floor2 = 1e-30 * fro;
+
+      // one-sided Jacobi over the C columns
+      const double tol = 1e-14;
+      bool conv = false;
+      for (int sweep = 0; sweep < 60; ++sweep) {
+        int rotated = 0;
+        for (int rnd = 0; rnd < C - 1; ++rnd) {
+          double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+          for (int m = 0; m < kR; ++m) {
+            al += xp[m].x * xp[m].x + xp[m].y * xp[m].y;
+            be += xq[m].x * xq[m].x + xq[m].y * xq[m].y;
+            gr += xp[m].x * xq[m].x + xp[m].y * xq[m].y;  // conj(xp) * xq
+            gi += xp[m].x * xq[m].y - xp[m].y * xq[m].x;
+          }
+          al = group_sum(al, 3);
+          be = group_sum(be, 3);
+          gr = group_sum(gr, 3);
+          gi = group_sum(gi, 3);
+          const double gabs2 = gr * gr + gi * gi;
+          const bool do_rot = live && al > floor2 && be > floor2 && gabs2 > tol * tol * (al * be);
+          if (do_rot) {
+            const double inv_gabs = rsqrt(gabs2);
+            const double zeta = 0.5 * (be - al) * inv_gabs;
+            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = rsqrt(1.0 + tt * tt);
+            const double s = c * tt;
+            // e^{-i phi} = conj(gamma) / |gamma|
+            const double2 ph = make_double2(gr * inv_gabs, -gi * inv_gabs);
+#pragma unroll
+            for (int m = 0; m < kR; ++m) {
+              const double2 a0 = xp[m];
+              const double2 b0 = cmul(ph, xq[m]);
+              xp[m] = make_double2(c * a0.x - s * b0.x, c * a0.y - s * b0.y);
+              xq[m] = make_double2(s * a0.x + c * b0.x, s * a0.y + c * b0.y);
+            }
+          }
+          rotated |= do_rot ? 1 : 0;
+          if (P < 2) continue;  // a single pair: nothing moves
+          // tournament move, half of the rows at a time: slot 1 takes slot
+          // 0's q column, slots p >= 2 take slot p-1's p column; slots p <
+          // P-1 take slot p+1's q column, slot P-1 its own p column
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            if (live) {
+#pragma unroll
+              for (int m = 0; m < kH; ++m) {
+                sm.xb[((0 * kH + m) * W + ps) * 8 + sub] = xp[h * kH + m];
+                sm.xb[((1 * kH + m) * W + ps) * 8 + sub] = xq[h * kH + m];
+              }
+            }
+            __syncthreads();
+            if (live) {
+              const int srcp_side = ps == 1 ? 1 : 0, srcp = ps == 1 ? 0 : ps - 1;
+              const int srcq_side = ps == P - 1 ? 0 : 1, srcq = ps == P - 1 ? ps : ps + 1;
+#pragma unroll
+              for (int m = 0; m < kH; ++m) {
+                if (ps != 0) xp[h * kH + m] = sm.xb[((srcp_side * kH + m) * W + srcp) * 8 + sub];
+                xq[h * kH + m] = sm.xb[((srcq_side * kH + m) * W + srcq) * 8 + sub];
+              }
+            }
+            __syncthreads();
+          }
+        }
+        if (!__syncthreads_or(rotated)) {
+          conv = true;
+          break;
+        }
+      }
+      if (!conv && tid == 0) atomicOr(status, QK_FLAG_NOCONV);
+      // singular values = column norms (columns are back in their slots)
+      double np = 0.0, nqq = 0.0;
+#pragma unroll
+      for (int m = 0; m < kR; ++m) {
+        np += xp[m].x * xp[m].x + xp[m].y * xp[m].y;
+        nqq += xq[m].x * xq[m].x + xq[m].y * xq[m].y;
+      }
+      np = group_sum(np, 3);
+      nqq = group_sum(nqq, 3);
+      if (live && sub == 0) {
+        sm.sv[colp] = sqrt(np);
+        sm.sv[colq] = sqrt(nqq);
+      }
+      __syncthreads();
+      for (int cc = tid; cc < C; cc += Sh::kThreads) {
+        const double mine = sm.sv[cc];
+        int rank = 0;
+        for (int j = 0; j < C; ++j) {
+          const double o = sm.sv[j];
+          rank += (o > mine) || (o == mine && j < cc);
+        }
+        sm.rnk[cc] = rank;
+        sm.perm[rank] = cc;
+      }
+      __syncthreads();
+      const double s0 = sm.sv[sm.perm[0]];
+      int keep = 0;
+      double norm2 = 0.0;
+      const int xc = R < C ? R : C;
+      const int kmax = xc < chi_max ? xc : chi_max;
+      for (int j = 0; j < kmax; ++j) {
+        const double sj = sm.sv[sm.perm[j]];
+        if (j == 0 || sj > cutoff * s0) {
+          ++keep;
+          norm2 += sj * sj;
+        } else {
+          break;
+        }
+      }
+      if (keep > W) {
+        if (tid == 0) atomicOr(status, QK_FLAG_CHI_OVER);
+        keep = W;
+        norm2 = 0.0;
+        for (int j = 0; j < keep; ++j) norm2 += sm.sv[sm.perm[j]] * sm.sv[sm.perm[j]];
+      }
+      const double inv_norm = norm2 > 0.0 ? 1.0 / sqrt(norm2) : 0.0;
+      if (keep > chi_seen) chi_seen = keep;
+      // kept left singular vectors U[:, j] = X[:, perm j] / S to LDS
+      if (live) {
+        const int jp = sm.rnk[colp], jq = sm.rnk[colq];
+        const double sp = sm.sv[colp], sq = sm.sv[colq];
+#pragma unroll
+        for (int m = 0; m < kR; ++m) {
+          const int row = sub + 8 * m;
+          if (row < R) {
+            if (jp < keep) sm.u[row * W + jp] = sp > 0.0 ? cscale(xp[m], 1.0 / sp) : make_double2(0, 0);
+            if (jq < keep) sm.u[row * W + jq] = sq > 0.0 ? cscale(xq[m], 1.0 / sq) : make_double2(0, 0);
+          }
+        }
+      }
+      __syncthreads();
+      // left site k: U (l2r) or U S / norm (r2l), zero outside the kept block
+      for (int e = tid; e < 2 * TT; e += Sh::kThreads) {
+        const int s = e / TT, r = e % TT, a = r / T, j = r % T;
+        double2 v = make_double2(0, 0);
+        if (a < cl && j < keep) {
+          v = sm.u[(s * cl + a) * W + j];
+          if (!l2r) v = cscale(v, sm.sv[sm.perm[j]] * inv_norm);
+        }
+        site(k)[e] = v;
+      }
+      // right site k+1: U^dagger Theta = S V^dagger, scaled by 1/norm (l2r)
+      // or 1/S (r2l); thread (t, c) = tid mod 2W, ranks j = tid / 2W + 4 n
+      {
+        constexpr int kJ = W / 4;  // ranks per thread
+        const int tc = tid % (2 * W), jg = tid / (2 * W);
+        const int t = tc / W, c = tc % W;
+        double2 acc[kJ];
+#pragma unroll
+        for (int n = 0; n < kJ; ++n) acc[n] = make_double2(0, 0);
+        if (c < cr) {
+          for (int row = 0; row < R; ++row) {
+            const double2 tv = th[row * D + t * cr + c];
+#pragma unroll
+            for (int n = 0; n < kJ; ++n) {
+              const int j = jg + 4 * n;
+              if (j < keep) acc[n] = cadd(acc[n], cmulc(sm.u[row * W + j], tv));
+            }
+          }
+        }
+#pragma unroll
+        for (int n = 0; n < kJ; ++n) {
+          const int j = jg + 4 * n;
+          double2 v = make_double2(0, 0);
+          if (j < keep && c < cr) {
+            const double sj = sm.sv[sm.perm[j]];
+            v = l2r ? cscale(acc[n], inv_norm) : (sj > 0.0 ? cscale(acc[n], 1.0 / sj) : make_double2(0, 0));
+          }
+          site(k + 1)[t * TT + j * T + c] = v;
+        }
+      }
+      if (tid == 0) chi[k + 1] = keep;
+      __syncthreads();
+    }
+  }
+  if (tid == 0) atomicMax(status + 1, chi_seen);
 }
 
 // ---------------------------------------------------------------------------
@@ -891,20 +1202,31 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
     const QkBuildPart part{x, ld_x, n, t64, chi, status};
     return qk_launch_build_many(&part, 1, nq, n_layers, chi_max, entangle, cutoff, chi_ws, T, s);
   }
-  // bond bounds of 32 and 64: X, V and the site copies of each sample in a
-  // stream-ordered global workspace for the duration of the build
-  double2* ws = nullptr;
-  if (T >= 32) {
-    const int64_t per = T == 32 ? kBuildWsPerSample<32> : kBuildWsPerSample<64>;
+  // bond bounds of 32 and 64: one workgroup per sample, Theta of each
+  // sample in a stream-ordered global workspace for the duration of the build
+  if (T == 32 || T == 64) {
+    const int64_t per = T == 32 ? kBuildWgWsPerSample<32> : kBuildWgWsPerSample<64>;
+    double2* ws = nullptr;
     const hipError_t ea = hipMallocAsync((void**)&ws, n * per * sizeof(double2), s);
     if (ea != hipSuccess) return ea;
+    if (T == 32)
+      hipLaunchKernelGGL(mps_build_wg_kernel<32>, dim3((unsigned)n),
+                         dim3(BuildWgShape<32>::kThreads), 0, s, x, ld_x, n, nq, n_layers,
+                         chi_max, entangle, cutoff, t64, chi, status, ws);
+    else
+      hipLaunchKernelGGL(mps_build_wg_kernel<64>, dim3((unsigned)n),
+                         dim3(BuildWgShape<64>::kThreads), 0, s, x, ld_x, n, nq, n_layers,
+                         chi_max, entangle, cutoff, t64, chi, status, ws);
+    const hipError_t e = hipGetLastError();
+    (void)hipFreeAsync(ws, s);  // stream-ordered: after the build
+    return e;
   }
   dim3 grid((unsigned)n), block(64);
 #define QK_BUILD_CASE(WV)                                                     \
   case WV:                                                                    \
     hipLaunchKernelGGL(mps_build_kernel<WV>, grid, block, 0, s, x, ld_x, n,   \
                        nq, n_layers, chi_max, entangle, cutoff, t64, chi,     \
-                       status, ws);                                           \
+                       status);                                               \
     break;
   switch (T) {
     QK_BUILD_CASE(1)
@@ -912,15 +1234,11 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
     QK_BUILD_CASE(4)
     QK_BUILD_CASE(8)
     QK_BUILD_CASE(16)
-    QK_BUILD_CASE(32)
-    QK_BUILD_CASE(64)
     default:
       return hipErrorInvalidValue;
   }
 #undef QK_BUILD_CASE
-  const hipError_t e = hipGetLastError();
-  if (ws) (void)hipFreeAsync(ws, s);  // stream-ordered: after the build
-  return e;
+  return hipGetLastError();
 }
 
 hipError_t qk_launch_build_many(const QkBuildPart* parts, int n_parts, int nq, int n_layers,
