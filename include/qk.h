@@ -92,7 +92,8 @@ typedef struct qk_mps_batch qk_mps_batch; /* opaque, device-resident, library-ow
 /*
  * qk_mps_build -- one MPS per sample (Eq. (6)).
  * Time-evolving block decimation in FP64 on the device (eight samples per
- * wavefront for chi_pad <= 4, one per wavefront above): per layer, the
+ * wavefront for chi_pad <= 4, one per wavefront at 8 and 16, one workgroup
+ * of 8 chi_pad threads per sample at 32 and 64): per layer, the
  * single-qubit gates, then the RZZ chain as two-site
  * steps (merge, phase, one-sided Jacobi SVD, truncate at s_j > cutoff*s_0 and
  * chi_max, renormalise), sweeping left to right on odd and right to left on
@@ -101,9 +102,9 @@ typedef struct qk_mps_batch qk_mps_batch; /* opaque, device-resident, library-ow
  *            min(chi_max, 2^min(n_layers, floor(n_qubits/2))) (1 when
  *            entangle = 0), the exact bond bound of this circuit family;
  *            tensors are padded to chi_pad = the power of two >= chi_ws;
- *            chi_ws <= 64 is supported (from 32 on, the build holds each
- *            sample's merged matrix in a temporary device workspace of
- *            about 0.8 MB per sample at 64).
+ *            chi_ws <= 64 is supported (from 32 on, the build keeps a copy
+ *            of each sample's merged matrix in a temporary device
+ *            workspace of (2 chi_pad)^2 complex: 256 KB per sample at 64).
  *   x_dev    n_samples x n_qubits FP64 features, row-major, leading dim ld_x.
  *            Must be finite (checked on the device, reported by qk_mps_info).
  *   store    QK_STORE_* mask of packed forms to keep.
