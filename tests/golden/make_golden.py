@@ -6,8 +6,12 @@
 * c3_pathsum_200.json: ln K_q by the exact path-sum chain for a seeded
   200-pair subset (20 diagonal, 120 train x train, 60 test x train) of the
   784-feature, 2-layer image workload, with K_c and the w = 0.5 mix.
+* s1_replay_3.json: the truncating regime at full size (784-feature images,
+  seed 6, 8 layers, chi_max 64, cutoff 1e-10): the oracle's step-by-step
+  TEBD replay of the first 3 training images (bond tables) and its FP64
+  overlaps (ln K_q for every pair, diagonal included).
 
-Run from the repository root: python tests/golden/make_golden.py
+Run from the repository root: python tests/golden/make_golden.py [s1]
 """
 import json
 import math
@@ -20,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
-from oracle import classical, pathsum  # noqa: E402
+from oracle import classical, mps, pathsum  # noqa: E402
 from oracle import statevector as sv  # noqa: E402
 from synthdata import config_inputs  # noqa: E402
 
@@ -68,5 +72,24 @@ def main():
         }, f)
 
 
+def s1_replay():
+    x, _, _ = config_inputs("S1", n_train=3, n_test=0)
+    built = [mps.build_mps(xi, 8, 64, 1e-10) for xi in x]
+    chi = [list(map(int, b[1])) for b in built]
+    P = mps.pad_batch([b[0] for b in built])
+    _, LN = mps.gram(P, P, symmetric=True)
+    with open(os.path.join(HERE, "s1_replay_3.json"), "w") as f:
+        json.dump({
+            "source": "oracle.mps.build_mps (TEBD replay), oracle.mps.gram (FP64 sweep)",
+            "workload": "images seed 6, first 3 training samples, d=784, L=8, chi_max=64, "
+                        "cutoff 1e-10",
+            "chi": chi, "lnkq": LN.tolist(),
+        }, f)
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "s1":
+        s1_replay()
+    else:
+        main()
+        s1_replay()

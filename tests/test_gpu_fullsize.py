@@ -113,3 +113,28 @@ def test_chi64_sweep_784_sites_sampled():
     assert checks.gate_b(got32, ref, tol=1e-3)[0]
     assert np.abs(got64 - ref).max() < 1e-8
     assert checks.gate_b(ln32, ln64, tol=1e-3)[0]
+
+
+def test_truncating_regime_784_qubits_vs_replay():
+    """The truncating regime at full size: 3 images of 784 features, 8 layers,
+    chi_max 64 (bonds would reach 2^8 without the cap). The device build's
+    bond tables equal the oracle's step-by-step replay, and its complex-FP64
+    overlaps meet the stated log gate against the replay's (fixture written
+    by tests/golden/make_golden.py, which calls only the oracle)."""
+    import paper_2602_01330_amd.qk as qk
+    fx = json.load(open(os.path.join(GOLDEN, "s1_replay_3.json")))
+    x, _, _ = config_inputs("S1", n_train=3, n_test=0)
+    print("[S1 full] 3 images, d=784, L=8, chi_max=64: building", flush=True)
+    xd = torch.as_tensor(x, device="cuda")
+    b = qk.qk_mps_build(xd, 8, 64, 1e-10)
+    info = qk.qk_mps_info(b)
+    assert info["chi_pad"] == 64 and info["chi_realized_max"] == 64
+    assert np.array_equal(qk.qk_mps_chi(b), np.array(fx["chi"], dtype=np.int32))
+    ln = torch.full((3, 3), float("nan"), dtype=torch.float64, device="cuda")
+    qk.qk_overlap_gram(b, b, True, "fp64", None, ln)
+    torch.cuda.synchronize()
+    ln = ln.cpu().numpy()
+    ok, lmax = checks.gate_b(ln, np.array(fx["lnkq"]))
+    print(f"[S1 full] max |d lnK| vs replay = {lmax:.3e}", flush=True)
+    assert ok, lmax
+    assert np.abs(np.diag(ln)).max() < 1e-8
