@@ -1,0 +1,45 @@
+"""The benchmark's algorithmic FLOP count (the numerator of its roofline
+fraction) against closed forms. Per pair, sum over sites k of
+16 (chi^A_k chi^B_k chi^B_{k+1} + chi^A_{k+1} chi^A_k chi^B_{k+1}) real FLOP
+on realized bonds (one complex MAC = 8 real FLOP; Eqs. (9), (10) as two
+matrix products per physical index). For the 2-layer circuit the bonds are
+1, 2, 4, ..., 4, 2, 1, which gives 2048 (d - 4) + 1728 per pair for d >= 4."""
+import numpy as np
+import pytest
+
+import bench
+
+
+def two_layer_bonds(d):
+    return np.array([min(2 ** k, 2 ** (d - k), 4) for k in range(d + 1)], dtype=np.int32)
+
+
+@pytest.mark.parametrize("d", [4, 5, 8, 64, 784])
+def test_two_layer_closed_form(d):
+    chi = two_layer_bonds(d)[None, :]
+    assert bench.algorithmic_flops(chi, chi, False) == 2048 * (d - 4) + 1728
+
+
+def test_brute_force_and_symmetric_count():
+    rng = np.random.default_rng(5)
+    d = 9
+    A = rng.integers(1, 5, size=(3, d + 1))
+    B = rng.integers(1, 5, size=(4, d + 1))
+    A[:, 0] = A[:, -1] = B[:, 0] = B[:, -1] = 1
+
+    def pair(a, b):
+        return sum(16 * (a[k] * b[k] * b[k + 1] + a[k + 1] * a[k] * b[k + 1]) for k in range(d))
+
+    full = sum(pair(a, b) for a in A for b in B)
+    assert bench.algorithmic_flops(A, B, False) == full
+    # symmetric: the upper triangle with its diagonal
+    tri = sum(pair(A[i], A[j]) for i in range(3) for j in range(i, 3))
+    assert bench.algorithmic_flops(A, A, True) == tri
+
+
+def test_bond_64_profile():
+    """784 sites with bonds min(2^k, 2^(784-k), 64): the per-pair figure the
+    bond-64 sweep leg divides by."""
+    d = 784
+    chi = np.array([min(2 ** min(k, 30), 2 ** min(d - k, 30), 64) for k in range(d + 1)])[None]
+    assert bench.algorithmic_flops(chi, chi, False) == 6483195584
