@@ -1,5 +1,9 @@
 // MPS build on the device: time-evolving block decimation of the encoding
-// circuit of Eq. (6), FP64, one 64-lane wavefront per sample.
+// circuit of Eq. (6), FP64. Three kernels by padded bond bound W: eight
+// samples per 64-lane wavefront for W <= 4 (mps_build8_kernel), one
+// wavefront per sample for W = 8, 16 and single qubits (mps_build_kernel),
+// one workgroup of 8 W threads per sample for W = 32, 64
+// (mps_build_wg_kernel).
 //
 // Per layer: the single-qubit gates G_k = RZ(2 x_k) H on every site, then the
 // RZZ(theta_k) chain as two-site steps, left to right on odd layers and right
@@ -166,65 +170,6 @@ __device__ bool jacobi_columns(double2* X, double2* V, int R, int C, double floo
   return false;
 }
 
-// The same one-sided Jacobi for the common full-bond case, an 8 x 8 X (chi
-// = 4 on both sides of the merged pair) in LDS with leading dimension 8:
-// lanes 0..31 rotate the columns of X and lanes 32..63 apply the same
-// rotation to V in the same instructions, 8 lanes (one per row) per pair of
-// the round-robin tournament. Both halves read the pair's X columns and
-// reduce them in the same order, so their rotation parameters are
-// bit-identical; rotation rule, tolerance and sweep limit are those of
-// jacobi_columns.
-__device__ bool jacobi_8x8(double2* X, double2* V, double floor2) {
-  constexpr int kC = 8, kPlayers = kC - 1;
-  const int lane = threadIdx.x;
-  const int half = lane >> 5, pair = (lane >> 3) & 3, row = lane & 7;
-  double2* Y = half ? V : X;  // the matrix this lane rotates
-  const double tol = 1e-14;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    int rotated = 0;
-    for (int r = 0; r < kPlayers; ++r) {
-      int p, q;
-      if (pair == 0) {
-        p = 0;
-        q = 1 + r;
-      } else {
-        int u = r + pair, v = r - pair + kPlayers;
-        if (u >= kPlayers) u -= kPlayers;
-        if (v >= kPlayers) v -= kPlayers;
-        p = 1 + u;
-        q = 1 + v;
-      }
-      const double2 xp = X[p * kC + row], xq = X[q * kC + row];
-      double al = xp.x * xp.x + xp.y * xp.y;
-      double be = xq.x * xq.x + xq.y * xq.y;
-      double gr = xp.x * xq.x + xp.y * xq.y;  // conj(xp) * xq
-      double gi = xp.x * xq.y - xp.y * xq.x;
-      al = group_sum(al, 3);
-      be = group_sum(be, 3);
-      gr = group_sum(gr, 3);
-      gi = group_sum(gi, 3);
-      const double gabs2 = gr * gr + gi * gi;
-      const bool do_rot = al > floor2 && be > floor2 && gabs2 > tol * tol * (al * be);
-      if (do_rot) {
-        const double inv_gabs = rsqrt(gabs2);
-        const double zeta = 0.5 * (be - al) * inv_gabs;
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = rsqrt(1.0 + t * t);
-        const double sn = c * t;
-        const double2 ph = make_double2(gr * inv_gabs, -gi * inv_gabs);
-        const double2 yp = Y[p * kC + row];
-        const double2 yq = cmul(ph, Y[q * kC + row]);
-        Y[p * kC + row] = make_double2(c * yp.x - sn * yq.x, c * yp.y - sn * yq.y);
-        Y[q * kC + row] = make_double2(sn * yp.x + c * yq.x, sn * yp.y + c * yq.y);
-      }
-      rotated |= do_rot ? 1 : 0;
-      __syncthreads();
-    }
-    if (!__any(rotated)) return true;
-  }
-  return false;
-}
-
 // LDS layout per workgroup, D = 2 * W (largest Theta dimension).
 template <int W>
 struct BuildSmem {
@@ -332,9 +277,7 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
       }
       __syncthreads();
       for (int off = 1; off < 64; off <<= 1) fro += __shfl_xor(fro, off, 64);
-      const bool conv = (D == 8 && XR == 8 && XCe == 8)
-                            ? jacobi_8x8(X, V, 1e-30 * fro)
-                            : jacobi_columns<D>(X, V, XR, XCe, 1e-30 * fro);
+      const bool conv = jacobi_columns<D>(X, V, XR, XCe, 1e-30 * fro);
       if (!conv && lane == 0) atomicOr(status, QK_FLAG_NOCONV);
       // singular values = column norms; rank them (descending, stable)
       for (int cc = lane; cc < XCe; cc += 64) {
@@ -1229,9 +1172,7 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
                        status);                                               \
     break;
   switch (T) {
-    QK_BUILD_CASE(1)
-    QK_BUILD_CASE(2)
-    QK_BUILD_CASE(4)
+    QK_BUILD_CASE(1)  // a single qubit (every multi-qubit bound <= 4 takes the 8-sample kernel)
     QK_BUILD_CASE(8)
     QK_BUILD_CASE(16)
     default:

@@ -350,13 +350,15 @@ def test_large_bond_mfma_sweep_on_oracle_mps(qk, d, L, chi_max, T):
     assert np.array_equal(ln_f.cpu().numpy()[up], ln_s.cpu().numpy()[up])
 
 
-@pytest.mark.parametrize("d,L,chi_max,tol", [(10, 5, 64, 1e-8), (16, 8, 64, None)])
+@pytest.mark.parametrize("d,L,chi_max,tol", [(8, 3, 64, 1e-8), (10, 4, 64, 1e-8),
+                                             (10, 5, 64, 1e-8), (16, 8, 64, None)])
 def test_large_bond_build(qk, d, L, chi_max, tol):
-    """Device build with bond bounds of 32 (exact regime) and 64 (truncating
-    at chi_max = 64: L = 8 allows 2^8): bond tables equal the oracle's, and
-    the FP64 overlaps match the oracle's MPS route (to rounding in the exact
-    regime; to the stated gates where truncation keeps 64 of up to 128
-    singular values)."""
+    """Device build with bond bounds of 8 and 16 (one wavefront per sample),
+    32 (exact regime) and 64 (truncating at chi_max = 64: L = 8 allows 2^8;
+    one workgroup per sample): bond tables equal the oracle's, and the FP64
+    overlaps match the oracle's MPS route (to rounding in the exact regime;
+    to the stated gates where truncation keeps 64 of up to 128 singular
+    values)."""
     X, _ = gen_clusters(9, d, 500 + d)
     print(f"[large bond build] d={d} L={L} chi_max={chi_max}", flush=True)
     g = gpu_gram(qk, X, L, chi_max, "fp64", True)
