@@ -272,6 +272,41 @@ def test_build_many_equals_separate_builds(qk):
         qk.qk_mps_build_many([xd] * 9, 2, 64)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "auto"])
+def test_mixed_bond_dimensions_in_one_call(qk, prec):
+    """One multi-task call holding a 2-layer task (bond 4, tile kernels) and
+    a 3-layer task (bond 8, one workgroup per pair), symmetric and
+    rectangular: every task's output is bitwise the one it gets alone."""
+    X4, _ = gen_clusters(21, 12, 61)
+    Y4, _ = gen_clusters(9, 12, 62)
+    X8, _ = gen_clusters(13, 10, 63)
+    b4, c4 = qk.qk_mps_build(dev(X4), 2, 64), qk.qk_mps_build(dev(Y4), 2, 64)
+    b8 = qk.qk_mps_build(dev(X8), 3, 64)
+    assert qk.qk_mps_info(b4)["chi_pad"] == 4 and qk.qk_mps_info(b8)["chi_pad"] == 8
+    print(f"[mixed bonds {prec}] tasks of bond 4 and 8 in one call", flush=True)
+
+    def outs():
+        return (torch.full((21, 21), float("nan"), dtype=torch.float64, device="cuda"),
+                torch.full((9, 21), float("nan"), dtype=torch.float64, device="cuda"),
+                torch.full((13, 13), float("nan"), dtype=torch.float64, device="cuda"))
+
+    mixed = outs()
+    qk.qk_overlap_gram_multi([
+        {"rows": b4, "cols": b4, "symmetric": True, "lnkq": mixed[0]},
+        {"rows": c4, "cols": b4, "symmetric": False, "lnkq": mixed[1]},
+        {"rows": b8, "cols": b8, "symmetric": True, "lnkq": mixed[2]}], prec)
+    alone = outs()
+    qk.qk_overlap_gram(b4, b4, True, prec, None, alone[0])
+    qk.qk_overlap_gram(c4, b4, False, prec, None, alone[1])
+    qk.qk_overlap_gram(b8, b8, True, prec, None, alone[2])
+    torch.cuda.synchronize()
+    for m, a in zip(mixed, alone):
+        m, a = m.cpu().numpy(), a.cpu().numpy()
+        assert np.all(np.isfinite(m)) and np.array_equal(m, a)
+    K, LN = oracle_gram(X8, 3, 64, symmetric=True)
+    assert checks.gate_b(mixed[2].cpu().numpy(), LN)[0]
+
+
 @pytest.mark.parametrize("d,L,chi_max,T", [(8, 3, 64, 8), (10, 4, 64, 16), (12, 5, 64, 32),
                                            (14, 8, 64, 64)])
 def test_large_bond_sweep_on_oracle_mps(qk, d, L, chi_max, T):
