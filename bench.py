@@ -521,17 +521,25 @@ def run(args):
         line["plain_fp64"] = {"value": pairs / (p["ms_per_step"] / 1e3),
                               "ms_per_step": p["ms_per_step"], "sweep_ms": p["sweep_ms"]}
         line["speedup_vs_plain_fp64"] = value / line["plain_fp64"]["value"]
+    def leg(key, fn):
+        # an optional leg that raises is recorded as such; the line still prints
+        try:
+            line[key] = fn(args)
+        except Exception as exc:  # noqa: BLE001
+            log(f"bench: {key} failed: {exc!r}")
+            line[key] = {"error": repr(exc)}
+
     if args.chi64:
-        line["chi64_sweep"] = chi64_sweep(args)
+        leg("chi64_sweep", chi64_sweep)
     if not args.no_ragged:
         log("bench: ragged multi-d run")
-        line["ragged"] = ragged(args)
+        leg("ragged", ragged)
     if not args.no_small:
         log("bench: smaller configurations")
-        line["small_configs"] = small_configs(args)
+        leg("small_configs", small_configs)
     if args.serve_seconds > 0:
         log("bench: serving run")
-        line["serving"] = serving(args)
+        leg("serving", serving)
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
