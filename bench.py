@@ -145,52 +145,54 @@ def serving(args):
     dev = torch.device("cuda:0")
     srv = qk.qk_server_create(budget_bytes=1 << 30, max_rows_per_iter=512, n_streams=2,
                               prec="auto")
-    pools = {}
-    for d in C5_DIMS:
-        sup, pool, _ = config_inputs("C5", d=d, n_train=5000, n_test=1024)
-        qk.qk_server_load_support(srv, torch.as_tensor(sup, device=dev), 2, 64)
-        pools[d] = pool
-    log("serve: supports loaded")
-    warm, dur = args.serve_warmup, args.serve_seconds
-    reqs = gen_requests(55, args.serve_rate, warm + dur, dims=C5_DIMS)
-    rng = np.random.default_rng(56)
-    submitted = queue.Queue()
-    t_start = time.perf_counter()
+    try:
+        pools = {}
+        for d in C5_DIMS:
+            sup, pool, _ = config_inputs("C5", d=d, n_train=5000, n_test=1024)
+            qk.qk_server_load_support(srv, torch.as_tensor(sup, device=dev), 2, 64)
+            pools[d] = pool
+        log("serve: supports loaded")
+        warm, dur = args.serve_warmup, args.serve_seconds
+        reqs = gen_requests(55, args.serve_rate, warm + dur, dims=C5_DIMS)
+        rng = np.random.default_rng(56)
+        submitted = queue.Queue()
+        t_start = time.perf_counter()
 
-    def submitter():
-        for r in reqs:
-            delay = t_start + r["t"] - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            d, n = r["d"], r["n_rows"]
-            off = int(rng.integers(0, pools[d].shape[0] - n))
-            rid = qk.qk_server_submit(srv, pools[d][off:off + n], r["w"])
-            submitted.put((rid, r))
-        submitted.put(None)
+        def submitter():
+            for r in reqs:
+                delay = t_start + r["t"] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                d, n = r["d"], r["n_rows"]
+                off = int(rng.integers(0, pools[d].shape[0] - n))
+                rid = qk.qk_server_submit(srv, pools[d][off:off + n], r["w"])
+                submitted.put((rid, r))
+            submitted.put(None)
 
-    th = threading.Thread(target=submitter)
-    th.start()
-    out = np.empty((64, 5000))
-    lat, measured_entries, t_first, t_last, sub = [], 0, None, 0.0, []
-    while True:
-        item = submitted.get()
-        if item is None:
-            break
-        rid, r = item
-        st = qk.qk_server_wait(srv, rid, -1)
-        ts, ta, td = qk.qk_server_request_times(srv, rid)
-        qk.qk_server_poll(srv, rid, out)
-        if st != qk.QK_REQ_DONE:
-            raise RuntimeError(f"request {rid} ended in state {st}: {qk.qk_last_error()}")
-        if r["t"] >= warm:
-            sub.append(ts)
-            lat.append(td - ts)
-            measured_entries += r["n_rows"] * 5000
-            t_first = ts if t_first is None else min(t_first, ts)
-            t_last = max(t_last, td)
-    th.join()
-    stats = qk.qk_server_stats(srv)
-    srv.close()
+        th = threading.Thread(target=submitter)
+        th.start()
+        out = np.empty((64, 5000))
+        lat, measured_entries, t_first, t_last, sub = [], 0, None, 0.0, []
+        while True:
+            item = submitted.get()
+            if item is None:
+                break
+            rid, r = item
+            st = qk.qk_server_wait(srv, rid, -1)
+            ts, ta, td = qk.qk_server_request_times(srv, rid)
+            qk.qk_server_poll(srv, rid, out)
+            if st != qk.QK_REQ_DONE:
+                raise RuntimeError(f"request {rid} ended in state {st}: {qk.qk_last_error()}")
+            if r["t"] >= warm:
+                sub.append(ts)
+                lat.append(td - ts)
+                measured_entries += r["n_rows"] * 5000
+                t_first = ts if t_first is None else min(t_first, ts)
+                t_last = max(t_last, td)
+        th.join()
+        stats = qk.qk_server_stats(srv)
+    finally:
+        srv.close()
     lat = np.array(lat) * 1e3
     meas = [r for r in reqs if r["t"] >= warm]
     offered = sum(r["n_rows"] for r in meas) * 5000 / dur
