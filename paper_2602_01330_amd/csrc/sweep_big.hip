@@ -8,12 +8,14 @@
 //
 // One 256-thread workgroup per pair (a flat list of the pairs of every
 // task; symmetric tasks list the upper triangle). E and the intermediate
-// G^s = E B^s sit in LDS (2 T^2 complex: 128 KB at T = 64). A thread owns
-// the entries (a, b') with b' = tid mod T and a = tid / T + (256 / T) m, so
-// that at T = 64 the lanes of a wavefront share a and read the B row they
-// need as one coalesced access, and in the left multiply share a' and read
-// A^s[a][a'] as one broadcast. Every entry follows the operation order of
-// the FP64 tile kernel (G over b ascending, E' over s then a ascending).
+// G^s = E B^s sit in LDS (2 T^2 complex, rows padded by one element: 130 KB
+// at T = 64). Each thread computes a K x K register tile of G^s and of E'
+// (K = 4 at T = 64, 2 at T = 32, 1 below), so that every operand it loads
+// (a row segment of B^s or A^s from memory, a column segment of E or G^s
+// from LDS) serves K products; the 16 tile columns of a wavefront read one
+// contiguous row of B^s or G^s, and its 4 tile rows share the E, A^s reads.
+// Every entry follows the operation order of the FP64 tile kernel (G over b
+// ascending, E' over s then a ascending).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,9 +29,16 @@ namespace {
 constexpr int kBigThreads = 256;
 
 template <int T>
+struct BigShape {
+  static constexpr int K = T == 64 ? 4 : (T == 32 ? 2 : 1);  // register tile
+  static constexpr int G = T / K;                           // tiles per dimension
+  static constexpr int P = T + 1;                           // LDS row pitch
+};
+
+template <int T>
 struct BigSmem {
-  double2 e[T * T];
-  double2 g[T * T];
+  double2 e[T * BigShape<T>::P];
+  double2 g[T * BigShape<T>::P];
   double red[kBigThreads / 64];
   int rede[kBigThreads / 64];
 };
@@ -45,48 +54,64 @@ __device__ inline double wave_sum(double v) {
 
 template <int T>
 __device__ void sweep_pair(const QkTask& t, int64_t i, int64_t j, BigSmem<T>& sm) {
-  constexpr int TT = T * T, kSlot = 2 * TT;
-  constexpr int kRows = kBigThreads / T > 0 ? kBigThreads / T : 1;  // rows per pass
-  constexpr int kPer = (TT + kBigThreads - 1) / kBigThreads;        // entries per thread
+  using S = BigShape<T>;
+  constexpr int TT = T * T, kSlot = 2 * TT, K = S::K, P = S::P;
   const int tid = threadIdx.x;
-  const int bp = tid % T, a0 = tid / T;
+  const bool act = tid < S::G * S::G;         // T = 8: 64 tiles of one entry
+  const int r0 = act ? (tid / S::G) * K : 0;  // tile rows a (or a')
+  const int c0 = act ? (tid % S::G) * K : 0;  // tile columns b'
   const double* ta = static_cast<const double*>(t.ta);
   const double* tb = static_cast<const double*>(t.tb);
   const int nq = t.nq;
-  for (int e = tid; e < TT; e += kBigThreads)
+  for (int e = tid; e < T * P; e += kBigThreads)
     sm.e[e] = make_double2(e == 0 ? 1.0 : 0.0, 0.0);
   int expo = 0;
   __syncthreads();
   for (int k = 0; k < nq; ++k) {
     const double2* A = reinterpret_cast<const double2*>(ta) + ((int64_t)k * t.na + i) * kSlot;
     const double2* B = reinterpret_cast<const double2*>(tb) + ((int64_t)k * t.nb + j) * kSlot;
-    double nr[kPer], ni[kPer];
+    double nr[K][K], ni[K][K];
 #pragma unroll
-    for (int m = 0; m < kPer; ++m) nr[m] = ni[m] = 0.0;
+    for (int x = 0; x < K; ++x)
+#pragma unroll
+      for (int y = 0; y < K; ++y) nr[x][y] = ni[x][y] = 0.0;
     for (int s = 0; s < 2; ++s) {
-      // G^s[a][b'] = sum_b E[a][b] B^s[b][b']
+      // G^s[a][b'] = sum_b E[a][b] B^s[b][b'], a in r0.., b' in c0..
+      if (act) {
+        double gr[K][K], gi[K][K];
 #pragma unroll
-      for (int m = 0; m < kPer; ++m) {
-        const int a = a0 + kRows * m;
-        if (a < T) {
-          double gr = 0.0, gi = 0.0;
-          for (int b = 0; b < T; ++b) {
-            const double2 ev = sm.e[a * T + b];
-            g_acc(gr, gi, ev.x, ev.y, B[s * TT + b * T + bp]);
-          }
-          sm.g[a * T + bp] = make_double2(gr, gi);
+        for (int x = 0; x < K; ++x)
+#pragma unroll
+          for (int y = 0; y < K; ++y) gr[x][y] = gi[x][y] = 0.0;
+        for (int b = 0; b < T; ++b) {
+          double2 ev[K], bv[K];
+#pragma unroll
+          for (int x = 0; x < K; ++x) ev[x] = sm.e[(r0 + x) * P + b];
+#pragma unroll
+          for (int y = 0; y < K; ++y) bv[y] = B[s * TT + b * T + c0 + y];
+#pragma unroll
+          for (int x = 0; x < K; ++x)
+#pragma unroll
+            for (int y = 0; y < K; ++y) g_acc(gr[x][y], gi[x][y], ev[x].x, ev[x].y, bv[y]);
         }
+#pragma unroll
+        for (int x = 0; x < K; ++x)
+#pragma unroll
+          for (int y = 0; y < K; ++y) sm.g[(r0 + x) * P + c0 + y] = make_double2(gr[x][y], gi[x][y]);
       }
       __syncthreads();
-      // E'[a'][b'] += sum_a conj(A^s[a][a']) G^s[a][b']
+      // E'[a'][b'] += sum_a conj(A^s[a][a']) G^s[a][b'], a' in r0.., b' in c0..
+      if (act) {
+        for (int a = 0; a < T; ++a) {
+          double2 av[K], gv[K];
 #pragma unroll
-      for (int m = 0; m < kPer; ++m) {
-        const int ap = a0 + kRows * m;
-        if (ap < T) {
-          for (int a = 0; a < T; ++a) {
-            const double2 gv = sm.g[a * T + bp];
-            e_acc(nr[m], ni[m], A[s * TT + a * T + ap], gv.x, gv.y);
-          }
+          for (int x = 0; x < K; ++x) av[x] = A[s * TT + a * T + r0 + x];
+#pragma unroll
+          for (int y = 0; y < K; ++y) gv[y] = sm.g[a * P + c0 + y];
+#pragma unroll
+          for (int x = 0; x < K; ++x)
+#pragma unroll
+            for (int y = 0; y < K; ++y) e_acc(nr[x][y], ni[x][y], av[x], gv[y].x, gv[y].y);
         }
       }
       __syncthreads();
@@ -94,7 +119,9 @@ __device__ void sweep_pair(const QkTask& t, int64_t i, int64_t j, BigSmem<T>& sm
     // exact power-of-two rescale: the exponent of the largest |entry|
     double mx = 0.0;
 #pragma unroll
-    for (int m = 0; m < kPer; ++m) mx = fmax(mx, fmax(fabs(nr[m]), fabs(ni[m])));
+    for (int x = 0; x < K; ++x)
+#pragma unroll
+      for (int y = 0; y < K; ++y) mx = fmax(mx, fmax(fabs(nr[x][y]), fabs(ni[x][y])));
     mx = wave_max(mx);
     if ((tid & 63) == 0) sm.red[tid >> 6] = mx;
     __syncthreads();
@@ -103,10 +130,12 @@ __device__ void sweep_pair(const QkTask& t, int64_t i, int64_t j, BigSmem<T>& sm
     const int ex = mx > 0.0 ? (int)((__double_as_longlong(mx) >> 52) & 0x7ff) - 1022 : 0;
     const double sc = __longlong_as_double((long long)(1023 - ex) << 52);
     expo += ex;
+    if (act) {
 #pragma unroll
-    for (int m = 0; m < kPer; ++m) {
-      const int ap = a0 + kRows * m;
-      if (ap < T) sm.e[ap * T + bp] = make_double2(nr[m] * sc, ni[m] * sc);
+      for (int x = 0; x < K; ++x)
+#pragma unroll
+        for (int y = 0; y < K; ++y)
+          sm.e[(r0 + x) * P + c0 + y] = make_double2(nr[x][y] * sc, ni[x][y] * sc);
     }
     __syncthreads();
   }
