@@ -559,8 +559,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-ragged", action="store_true", help="skip the ten-d ragged run")
     ap.add_argument("--chi64", action="store_true",
-                    help="add the 784-site bond-64 sweep leg (its matrix-core form is "
-                         "switched off in the library for now)")
+                    help="add the 784-site bond-64 sweep leg (its matrix-core form needs "
+                         "QK_ENABLE_WIDE_MFMA=1 in the environment)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the two smaller whole-job configurations")
     ap.add_argument("--serve-seconds", type=float, default=20.0,

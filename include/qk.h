@@ -198,8 +198,10 @@ typedef struct {
  *                triangles are written (train x train); 0: full rectangle.
  *   prec         QK_PREC_*; QK_PREC_FP64 needs QK_STORE_FP64 in both batches.
  *                chi_pad 1, 2, 4: every form (tile kernels); chi_pad 8..64:
- *                QK_PREC_FP64 only (one workgroup per pair) and AUTO
- *                resolves to it.
+ *                QK_PREC_FP64 (one workgroup per pair), and AUTO resolves to
+ *                it; QK_PREC_FP32_MFMA there only when the process sets the
+ *                environment variable QK_ENABLE_WIDE_MFMA=1 (off by
+ *                default: a GPU fault in a run that used it is unexplained).
  *   kq_dev       FP64 rows->n_samples x cols->n_samples output, ld_kq (may be
  *                NULL if lnkq_dev is given).
  *   lnkq_dev     FP64 ln K_q output, ld_ln (NULL to skip).

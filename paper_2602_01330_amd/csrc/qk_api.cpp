@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstdint>
 #include <cmath>
 #include <cstdio>
@@ -202,12 +203,20 @@ qk_status fill_task(QkTask& t, const qk_mps_batch* rows, const qk_mps_batch* col
   return QK_OK;
 }
 
-// The matrix-core sweep for padded bonds 8..64 (sweep_wide.hip) is switched
-// off: a GPU memory fault or hung queue ended a run of the whole GPU test
-// suite plus the benchmark in which it ran, and no cause has been shown
-// (each of its tests had passed when run on their own). Until one is, FP32
-// MFMA at bonds above 4 reports QK_ERR_UNSUPPORTED; complex FP64 serves them.
-constexpr bool kWideMfmaEnabled = false;
+// The matrix-core sweep for padded bonds 8..64 (sweep_wide.hip) is off by
+// default: a GPU memory fault or hung queue ended a run of the whole GPU
+// test suite plus the benchmark in which it ran, and no cause has been shown
+// (each of its tests had passed when run on their own, and a later fault
+// came without it). FP32 MFMA at bonds above 4 reports QK_ERR_UNSUPPORTED,
+// and complex FP64 serves those bonds, unless the process sets
+// QK_ENABLE_WIDE_MFMA=1 (read once).
+bool wide_mfma_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("QK_ENABLE_WIDE_MFMA");
+    return e && e[0] == '1' && e[1] == '\0';
+  }();
+  return on;
+}
 
 bool supported_T(qk_precision p, int T) {
   switch (p) {
@@ -216,7 +225,7 @@ bool supported_T(qk_precision p, int T) {
     case QK_PREC_FP32:
       return T == 1 || T == 2 || T == 4;
     case QK_PREC_FP32_MFMA:
-      return qk_mfma_supports(p, T) || (kWideMfmaEnabled && qk_sweep_wide_supports(T));
+      return qk_mfma_supports(p, T) || (wide_mfma_enabled() && qk_sweep_wide_supports(T));
     default:
       return qk_mfma_supports(p, T);
   }
