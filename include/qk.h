@@ -261,6 +261,22 @@ QK_API qk_status qk_dual_mix(const double* kq_dev, int64_t ld_kq, const double* 
                       double* k_dev, int64_t ld_k, void* hip_stream);
 
 /*
+ * qk_svm_decision -- decision values of an SVM on precomputed kernel rows
+ * (Eqs. (4), (5)): f[r] = sum_i coef[i] K[r][i] + intercept, with coef[i] =
+ * alpha_i y_i of the training samples (zero off the support vectors) and K
+ * rows against the training set (for example the rows a serving request
+ * returns). The predicted label of row r is sign(f[r]). FP64.
+ *   k_dev      m x n kernel rows, leading dimension ld_k >= n.
+ *   coef_dev   n coefficients (device).
+ *   f_dev      m outputs (device).
+ * Errors: INVALID_ARG (negative sizes, NULL pointers, ld_k < n, m >= 2^31,
+ *         non-finite intercept), HIP.
+ */
+QK_API qk_status qk_svm_decision(const double* k_dev, int64_t m, int64_t n, int64_t ld_k,
+                                 const double* coef_dev, double intercept, double* f_dev,
+                                 void* hip_stream);
+
+/*
  * Reduced-precision forms (QK_PREC_FP32, _FP32_MFMA, _BF16X2, _BF16X3) carry
  * a relative error of ~1e-5 (FP32-class) or ~2e-4 (BF16X2) in K_q after
  * hundreds of sites, which exceeds 1e-5 absolute only where K_q is large.

@@ -23,8 +23,8 @@ Quantum-Classical Dual Kernel"):
   alternating directions, SVD bond truncation at the orthogonality centre),
   and the pairwise transfer-matrix overlap sweep with power-of-two
   rescaling -- ``mps``;
-* the RBF kernel of Eq. (3) and the linear mix of Eq. (11) --
-  ``classical``;
+* the RBF kernel of Eq. (3), the linear mix of Eq. (11) and the SVM
+  decision values of Eqs. (4), (5) on kernel rows -- ``classical``;
 * kernel invariants and the tolerance gates used by the parity tests --
   ``checks``.
 

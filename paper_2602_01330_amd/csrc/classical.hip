@@ -1,5 +1,6 @@
-// Classical RBF Gram matrix (Eq. (3)) and the quantum-classical mix
-// (Eq. (11)) as standalone kernels; FP64 throughout.
+// Classical RBF Gram matrix (Eq. (3)), the quantum-classical mix (Eq. (11))
+// and the SVM decision values of kernel rows (Eqs. (4), (5)) as standalone
+// kernels; FP64 throughout.
 #include <hip/hip_runtime.h>
 
 #include "qk_internal.h"
@@ -54,7 +55,32 @@ __global__ void mix_kernel(const double* __restrict__ kq, int64_t ld_kq,
   }
 }
 
+// f[r] = sum_i coef[i] K[r][i] + b: one 256-thread workgroup per row, the
+// columns strided over the threads (coalesced), a fixed reduction order.
+__global__ __launch_bounds__(256) void svm_decision_kernel(const double* __restrict__ k,
+                                                           int64_t ld_k, int64_t n,
+                                                           const double* __restrict__ coef,
+                                                           double b, double* __restrict__ f) {
+  __shared__ double red[4];
+  const int64_t r = blockIdx.x;
+  const double* row = k + r * ld_k;
+  double acc = 0.0;
+  for (int64_t c = threadIdx.x; c < n; c += 256) acc = fma(coef[c], row[c], acc);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) f[r] = ((red[0] + red[1]) + (red[2] + red[3])) + b;
+}
+
 }  // namespace
+
+hipError_t qk_launch_svm_decision(const double* k, int64_t m, int64_t n, int64_t ld_k,
+                                  const double* coef, double b, double* f, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(svm_decision_kernel, dim3((unsigned)m), dim3(256), 0, s, k, ld_k, n, coef,
+                     b, f);
+  return hipGetLastError();
+}
 
 hipError_t qk_launch_rbf(const double* x, int64_t m, int64_t ld_x,
                          const double* y, int64_t n, int64_t ld_y, int d,

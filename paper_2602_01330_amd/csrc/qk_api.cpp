@@ -795,6 +795,21 @@ qk_status qk_dual_mix(const double* kq_dev, int64_t ld_kq, const double* kc_dev,
   return QK_OK;
 }
 
+qk_status qk_svm_decision(const double* k_dev, int64_t m, int64_t n, int64_t ld_k,
+                          const double* coef_dev, double intercept, double* f_dev,
+                          void* hip_stream) {
+  if (m < 0 || n < 0) return fail(QK_ERR_INVALID_ARG, "bad sizes");
+  if (m > INT32_MAX) return fail(QK_ERR_INVALID_ARG, "more than 2^31 - 1 rows");
+  if (m > 0 && (!f_dev || (n > 0 && (!k_dev || !coef_dev))))
+    return fail(QK_ERR_INVALID_ARG, "NULL pointer");
+  if (ld_k < n) return fail(QK_ERR_INVALID_ARG, "leading dimension too small");
+  if (!std::isfinite(intercept)) return fail(QK_ERR_INVALID_ARG, "intercept must be finite");
+  hipError_t e = qk_launch_svm_decision(k_dev, m, n, ld_k, coef_dev, intercept, f_dev,
+                                        (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "decision launch");
+  return QK_OK;
+}
+
 qk_status qk_resolve_precision(const qk_mps_batch* rows, const qk_mps_batch* cols,
                                qk_precision* out) {
   if (!rows || !cols || !out) return fail(QK_ERR_INVALID_ARG, "NULL argument");

@@ -197,3 +197,5 @@ hipError_t qk_launch_rbf(const double* x, int64_t m, int64_t ld_x,
 hipError_t qk_launch_mix(const double* kq, int64_t ld_kq, const double* kc,
                          int64_t ld_kc, int64_t m, int64_t n, double w,
                          double* k, int64_t ld_k, hipStream_t s);
+hipError_t qk_launch_svm_decision(const double* k, int64_t m, int64_t n, int64_t ld_k,
+                                  const double* coef, double b, double* f, hipStream_t s);

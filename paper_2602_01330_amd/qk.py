@@ -83,6 +83,8 @@ _lib.qk_rbf_gram.argtypes = [_P, C.c_int64, C.c_int64, _P, C.c_int64, C.c_int64,
                              C.c_double, _P, C.c_int64, _P]
 _lib.qk_dual_mix.argtypes = [_P, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int64, C.c_double,
                              _P, C.c_int64, _P]
+_lib.qk_svm_decision.argtypes = [_P, C.c_int64, C.c_int64, C.c_int64, _P, C.c_double, _P, _P]
+_lib.qk_svm_decision.restype = C.c_int
 _lib.qk_resolve_precision.argtypes = [_P, _P, C.POINTER(C.c_int)]
 _lib.qk_set_refine_threshold.argtypes = [C.c_int, C.c_double]
 _lib.qk_set_launch_timing.argtypes = [C.c_int32]
@@ -130,7 +132,7 @@ EXPORTED = ["qk_server_create", "qk_server_load_support", "qk_server_submit",
             "qk_server_stats", "qk_server_destroy",
             "qk_mps_build", "qk_mps_build_many", "qk_mps_import", "qk_mps_info", "qk_mps_chi",
             "qk_mps_release", "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
-            "qk_resolve_precision", "qk_set_refine_threshold", "qk_autotune",
+            "qk_svm_decision", "qk_resolve_precision", "qk_set_refine_threshold", "qk_autotune",
             "qk_tune_export", "qk_tune_import", "qk_status_string",
             "qk_last_error", "qk_set_launch_timing", "qk_last_launch_ms"]
 
@@ -322,6 +324,18 @@ def qk_dual_mix(kq, kc, w, k, stream=None):
     _check(_lib.qk_dual_mix(qp, ldq, cp, ldc, kq.shape[0], kq.shape[1], float(w), kp, ldk,
                             _stream(stream)))
     return k
+
+
+def qk_svm_decision(k, coef, intercept, f, stream=None):
+    """f[r] = sum_i coef[i] k[r, i] + intercept on the device (k: m x n FP64)."""
+    kp, ldk = _mat(k, "k")
+    cp, _ = _mat(coef.reshape(1, -1), "coef")
+    fp, _ = _mat(f.reshape(1, -1), "f")
+    if coef.numel() != k.shape[1] or f.numel() != k.shape[0]:
+        raise ValueError("coef must have k.shape[1] entries and f k.shape[0]")
+    _check(_lib.qk_svm_decision(kp, k.shape[0], k.shape[1], ldk, cp, float(intercept), fp,
+                                _stream(stream)))
+    return f
 
 
 def qk_resolve_precision(rows: MpsBatch, cols: MpsBatch) -> str:

@@ -406,3 +406,26 @@ def test_large_bond_build(qk, d, L, chi_max, tol):
         assert dmax < tol
     ok, info = gates("fp64", g["kq"], K, g["ln"], LN)
     assert ok, info
+
+
+def test_svm_decision_on_kernel_rows(qk):
+    """Eqs. (4), (5) on the device: f = K coef + b for 37 rows of 1000 kernel
+    values (leading dimension above the row length) against the oracle;
+    zero rows are accepted and a short leading dimension is rejected."""
+    rng = np.random.default_rng(77)
+    K = rng.uniform(0.0, 1.0, size=(37, 1003))
+    coef = rng.standard_normal(1000)
+    print("[svm decision] 37 x 1000", flush=True)
+    kd = dev(K)[:, :1000]
+    cd = dev(coef)
+    f = torch.full((37,), float("nan"), dtype=torch.float64, device="cuda")
+    qk.qk_svm_decision(kd, cd, -0.25, f)
+    torch.cuda.synchronize()
+    ref = classical.svm_decision(K[:, :1000], coef, -0.25)
+    assert np.allclose(f.cpu().numpy(), ref, rtol=1e-12, atol=1e-12)
+    empty = torch.empty((0,), dtype=torch.float64, device="cuda")
+    qk.qk_svm_decision(kd[:0], cd, 0.0, empty)
+    with pytest.raises(qk.QkError):
+        qk._check(qk._lib.qk_svm_decision(qk.C.c_void_p(kd.data_ptr()), 37, 1000, 999,
+                                          qk.C.c_void_p(cd.data_ptr()), 0.0,
+                                          qk.C.c_void_p(f.data_ptr()), None))

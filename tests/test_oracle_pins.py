@@ -241,3 +241,28 @@ def test_sweep_on_random_isometries_vs_statevector():
     ref = np.abs(V.conj() @ V.T) ** 2
     assert np.allclose(K, ref, rtol=1e-10, atol=1e-15)
     assert np.allclose(np.diag(K), 1.0, atol=1e-12)
+
+
+def test_svm_decision_vs_scikit_learn():
+    """Eqs. (4), (5) on precomputed kernel rows: the oracle's decision values
+    equal scikit-learn's SVC decision_function (a library routine) for a
+    binary problem on the dual kernel of two classes of the 8-feature
+    clusters, with coef_i = alpha_i y_i placed at the support vectors."""
+    from sklearn.svm import SVC
+    x, _, lab = config_inputs("C1")
+    pick = np.where((lab == 0) | (lab == 1))[0]
+    tr, te = pick[:30], pick[30:40]
+    P = mps.pad_batch(mps.build_batch(x[pick], 1, 16))
+    K, _ = mps.gram(P, P)
+    kc = classical.rbf_gram(x[pick], x[pick], 1.0 / 8)
+    Kmix = classical.mix(K, kc, 0.5)
+    ntr = len(tr)
+    y = np.where(lab[tr] == 1, 1, -1)
+    svc = SVC(kernel="precomputed", C=10.0).fit(Kmix[:ntr, :ntr], y)
+    coef = np.zeros(ntr)
+    coef[svc.support_] = svc.dual_coef_[0]
+    rows = Kmix[ntr:, :ntr]
+    f = classical.svm_decision(rows, coef, float(svc.intercept_[0]))
+    assert np.allclose(f, svc.decision_function(rows), rtol=1e-10, atol=1e-12)
+    # sign(f) is the predicted label: scikit-learn's classes_ are (-1, +1)
+    assert np.array_equal(np.where(f > 0, 1, -1), svc.predict(rows))
