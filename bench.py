@@ -335,57 +335,62 @@ def chi64_sweep(args):
     interior bond at 64 (bonds 1, 2, 4, ..., 64, ..., 4, 2, 1), on random
     left-canonical MPS (seeded; the device build of such deep circuits is not
     part of this leg), 32 row x 64 column samples = 2048 pairs, inputs
-    resident. The complex-FP32 matrix-core sweep over all pairs against the
-    complex-FP64 sweep over the first 8 rows (512 pairs)."""
+    resident. The complex-FP64 sweep over all pairs; with the matrix-core
+    form enabled (QK_ENABLE_WIDE_MFMA=1) also the complex-FP32 matrix-core
+    sweep over all pairs, with the FP64 one as its comparator."""
     import numpy as np
     import torch
 
     import paper_2602_01330_amd.qk as qk
     from synthdata import gen_isometry_mps
 
-    nq, T, nr, nc, nsub = 784, 64, 32, 64, 8
+    nq, T, nr, nc = 784, 64, 32, 64
     log("bench: chi64 leg: generating random left-canonical MPS")
     cr, tr = gen_isometry_mps(nr, nq, T, seed=71)
     cc, tc = gen_isometry_mps(nc, nq, T, seed=72)
-    br = qk.qk_mps_import(cr, tr, 8, T)
-    bs = qk.qk_mps_import(cr[:nsub], tr[:, :nsub], 8, T, store=qk.QK_STORE_FP64)
-    bc = qk.qk_mps_import(cc, tc, 8, T)
+    wide = os.environ.get("QK_ENABLE_WIDE_MFMA") == "1"
+    store = qk.QK_STORE_ALL if wide else qk.QK_STORE_FP64
+    br = qk.qk_mps_import(cr, tr, 8, T, store=store)
+    bc = qk.qk_mps_import(cc, tc, 8, T, store=store)
     del tr, tc
     flop_pair = algorithmic_flops(cr[:1], cc[:1], False)
+    pairs = nr * nc
     ln = torch.empty((nr, nc), dtype=torch.float64, device="cuda")
 
-    def timed(rows, form, reps):
+    def timed(form, reps):
         qk.qk_set_launch_timing(True)
         ms = []
         for _ in range(reps):
-            qk.qk_overlap_gram(rows, bc, False, form, None, ln[:qk.qk_mps_info(rows)["n_samples"]])
+            qk.qk_overlap_gram(br, bc, False, form, None, ln)
             ms.append(qk.qk_last_launch_ms()[0])
         qk.qk_set_launch_timing(False)
         return float(np.median(ms))
 
-    timed(br, "fp32_mfma", 1)  # warmup
-    ms32 = timed(br, "fp32_mfma", 3)
-    refined = int((ln >= math.log(1e-2)).sum().item())
-    ms64 = timed(bs, "fp64", 1)
-    pairs32, pairs64 = nr * nc, nsub * nc
-    tf32 = pairs32 * flop_pair / (ms32 / 1e3) / 1e12
-    res = {
-        "workload": f"{nq} sites, bonds up to {T} (chi_pad {T}), random left-canonical MPS, "
-                    f"{nr} x {nc} pairs",
-        "form": "fp32_mfma", "kernel": "sweep_wide_kernel<64> (+ FP64 list pass, "
-                                       f"{refined} pairs refined)",
-        "kernel_ms": ms32, "entries_per_s": pairs32 / (ms32 / 1e3),
-        "algorithmic_flop_per_pair": flop_pair,
-        "roofline": {"bound": "mfma", "achieved": tf32, "peak": 157.3, "unit": "TFLOP/s",
-                     "frac": tf32 / 157.3, "traffic": traffic_for("fp32_mfma_wide")},
-        "plain_fp64": {"pairs": pairs64, "kernel_ms": ms64,
-                       "entries_per_s": pairs64 / (ms64 / 1e3),
-                       "achieved_tflops": pairs64 * flop_pair / (ms64 / 1e3) / 1e12},
-    }
-    res["speedup_vs_plain_fp64"] = res["entries_per_s"] / res["plain_fp64"]["entries_per_s"]
-    log(f"bench: chi64 leg: fp32_mfma {ms32:.1f} ms for {pairs32} pairs ({tf32:.1f} TF/s), "
-        f"fp64 {ms64:.1f} ms for {pairs64} pairs")
-    for b in (br, bs, bc):
+    def entry(form, ms, peak, bound, kernel, traffic):
+        tf = pairs * flop_pair / (ms / 1e3) / 1e12
+        return {"form": form, "kernel": kernel, "kernel_ms": ms,
+                "entries_per_s": pairs / (ms / 1e3),
+                "roofline": {"bound": bound, "achieved": tf, "peak": peak, "unit": "TFLOP/s",
+                             "frac": tf / peak, "traffic": traffic}}
+
+    timed("fp64", 1)  # warmup
+    ms64 = timed("fp64", 3)
+    res = {"workload": f"{nq} sites, bonds up to {T} (chi_pad {T}), random left-canonical "
+                       f"MPS, {nr} x {nc} pairs",
+           "algorithmic_flop_per_pair": flop_pair,
+           "fp64": entry("fp64", ms64, 78.6, "alu", "sweep_big_kernel<64>", None)}
+    msg = f"fp64 {ms64:.1f} ms"
+    if wide:
+        timed("fp32_mfma", 1)
+        ms32 = timed("fp32_mfma", 3)
+        refined = int((ln >= math.log(1e-2)).sum().item())
+        res["fp32_mfma"] = entry("fp32_mfma", ms32, 157.3, "mfma",
+                                 f"sweep_wide_kernel<64> (+ FP64 list pass, {refined} refined)",
+                                 traffic_for("fp32_mfma_wide"))
+        res["speedup_vs_plain_fp64"] = ms64 / ms32
+        msg += f", fp32_mfma {ms32:.1f} ms"
+    log(f"bench: chi64 leg ({pairs} pairs): {msg}")
+    for b in (br, bc):
         b.close()
     return res
 
