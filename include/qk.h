@@ -374,6 +374,20 @@ QK_API qk_status qk_server_create(const qk_server_config* cfg, qk_server** out);
 QK_API qk_status qk_server_load_support(qk_server* s, const qk_circuit_desc* c,
                                         const double* x_dev, int64_t n, int64_t ld_x);
 
+/* Attaches a trained binary SVM (Eqs. (4), (5)) to the support set of
+ * dimension d: coef_host holds n = support-size FP64 coefficients
+ * alpha_i y_i (host, copied before the call returns; zero off the support
+ * vectors), intercept is b. Requests admitted after the call also get their
+ * decision values f[r] = sum_i coef[i] K[r][i] + b, computed on the device
+ * from the iteration's kernel rows in the same stream (qk_server_poll_decision
+ * returns them); requests already admitted keep the model they were admitted
+ * with. coef_host NULL removes the model. Replaced coefficient arrays stay on
+ * the device until qk_server_destroy. Errors: NOT_FOUND (no support set for
+ * d), INVALID_ARG (n differs from the support size, non-finite value),
+ * OUT_OF_MEMORY, HIP. */
+QK_API qk_status qk_server_set_model(qk_server* s, int32_t d, const double* coef_host,
+                                     int64_t n, double intercept);
+
 /* Queues a request: n_rows x d FP64 features on the host (copied before the
  * call returns), mixing weight w in [0, 1]. Never waits for the GPU. Writes
  * the request id. Errors: NOT_FOUND (no support set for d), INVALID_ARG
@@ -387,6 +401,14 @@ QK_API qk_status qk_server_submit(qk_server* s, const double* x_host, int64_t n_
  * carries the reason in qk_last_error(). */
 QK_API qk_status qk_server_poll(qk_server* s, int64_t id, double* rows_host,
                                 int64_t ld_rows, int32_t* state);
+
+/* As qk_server_poll, and when DONE also copies the request's n_rows FP64
+ * decision values to f_host if it is not NULL. Either output may be NULL; a
+ * non-NULL one releases the request. Errors: INVALID_ARG (f_host given for a
+ * request admitted while its support set had no model; nothing is released)
+ * and those of qk_server_poll. */
+QK_API qk_status qk_server_poll_decision(qk_server* s, int64_t id, double* rows_host,
+                                         int64_t ld_rows, double* f_host, int32_t* state);
 
 /* Blocks until the request leaves QUEUED/RUNNING or timeout_ms passes
  * (< 0: no limit); writes the state. */

@@ -9,7 +9,9 @@
 //   3. launch the admitted rows as one iteration on that slot's stream: per
 //      feature dimension d, stage the rows and weights, build their MPS, then
 //      ONE multi-task sweep launch (one task per d) with the fused RBF and
-//      per-row mix, and copy each request's rows to pinned host memory.
+//      per-row mix; where the support set carries a trained SVM, the decision
+//      values of the new rows follow on the same stream; copy each request's
+//      rows (and decision values) to pinned host memory.
 // Submissions only touch host memory and the queue, so they never wait for
 // the GPU.
 #include <hip/hip_runtime.h>
@@ -39,6 +41,8 @@ struct Support {
   qk_mps_batch* mps = nullptr;
   double* x = nullptr;  // n x d, library-owned copy of the features
   int64_t n = 0;
+  double* coef = nullptr;  // n SVM coefficients alpha_i y_i on the device, or NULL
+  double intercept = 0.0;
 };
 
 struct Request {
@@ -53,6 +57,7 @@ struct Request {
   int64_t n_support = 0;
   int64_t bytes = 0;           // budget reservation while admitted
   double* out_host = nullptr;  // pinned n_rows x n_support, filled by the D2H copy
+  double* f_host = nullptr;    // pinned n_rows decision values (admitted with a model)
 };
 
 struct Iteration {
@@ -78,6 +83,7 @@ struct qk_server {
   std::unordered_map<int64_t, Request*> reqs;
   std::unordered_map<int64_t, std::array<double, 3>> times;  // submit, admit, done
   std::map<int32_t, Support> supports;
+  std::vector<double*> old_coefs;  // replaced models, freed at destroy (iterations may hold them)
   std::vector<hipStream_t> streams;
   std::vector<bool> slot_busy;
   std::deque<Iteration*> inflight;
@@ -99,7 +105,15 @@ int64_t request_bytes(const Request& r, const Support& sup) {
          + rows * (d + 1) * 4                                                 // bond table
          + rows * d * 8 + rows * 8                                            // features, w
          + rows * ns * 8                                                      // K rows
-         + tiles * 32;                                                        // refinement masks
+         + tiles * 32                                                         // refinement masks
+         + (sup.coef ? rows * 8 : 0);                                         // decision values
+}
+
+void free_host(Request* r) {
+  if (r->out_host) (void)hipHostFree(r->out_host);
+  if (r->f_host) (void)hipHostFree(r->f_host);
+  r->out_host = nullptr;
+  r->f_host = nullptr;
 }
 
 void finish(qk_server* s, Request* r, int32_t state, const std::string& err = "") {
@@ -117,8 +131,7 @@ void retire(qk_server* s, Iteration* it) {
     s->budget_used -= r->bytes;
     r->bytes = 0;
     if (r->cancel) {
-      if (r->out_host) (void)hipHostFree(r->out_host);
-      r->out_host = nullptr;
+      free_host(r);
       finish(s, r, QK_REQ_CANCELLED);
     } else {
       finish(s, r, QK_REQ_DONE);
@@ -143,8 +156,17 @@ std::string launch(qk_server* s, Iteration* it) {
   struct Out {
     Request* r;
     double* k;
+    double* f;  // decision values of the d group, or NULL
     int64_t row0;
   };
+  struct Decision {
+    const double* k;
+    int64_t rows, n;
+    const double* coef;
+    double b;
+    double* f;
+  };
+  std::vector<Decision> decisions;
   std::vector<Out> outs;
   for (auto& kv : by_d) {
     const Support& sup = it->sups.at(kv.first);
@@ -193,17 +215,32 @@ std::string launch(qk_server* s, Iteration* it) {
     t.fuse.k_dev = dk;
     t.fuse.ld_k = sup.n;
     tasks.push_back(t);
+    double* df = nullptr;
+    if (sup.coef) {
+      if (hipMallocAsync((void**)&df, rows * sizeof(double), st) != hipSuccess)
+        return "device allocation for an iteration failed";
+      it->dev.push_back(df);
+      decisions.push_back({dk, rows, sup.n, sup.coef, sup.intercept, df});
+    }
     off = 0;
     for (Request* r : kv.second) {
-      outs.push_back({r, dk, off});
+      outs.push_back({r, dk, df, off});
       off += r->n_rows;
     }
   }
   qk_status gs = qk_overlap_gram_multi(tasks.data(), (int32_t)tasks.size(), s->cfg.prec, st);
   if (gs != QK_OK) return std::string("sweep launch failed: ") + qk_last_error();
+  for (const Decision& dc : decisions)
+    if (qk_launch_svm_decision(dc.k, dc.rows, dc.n, dc.n, dc.coef, dc.b, dc.f, st) != hipSuccess)
+      return "decision launch failed";
   for (const Out& o : outs) {
     const int64_t bytes = o.r->n_rows * o.r->n_support * (int64_t)sizeof(double);
     if (hipMemcpyAsync(o.r->out_host, o.k + o.row0 * o.r->n_support, bytes,
+                       hipMemcpyDeviceToHost, st) != hipSuccess)
+      return "result download failed";
+    // the request's pinned buffer exists iff its support set had a model at admission
+    if (o.f && o.r->f_host &&
+        hipMemcpyAsync(o.r->f_host, o.f + o.row0, o.r->n_rows * sizeof(double),
                        hipMemcpyDeviceToHost, st) != hipSuccess)
       return "result download failed";
   }
@@ -259,8 +296,11 @@ void worker_main(qk_server* s) {
         if (s->budget_used + need > budget || rows + r->n_rows > max_rows) break;
         // one sweep task per d: at most QK_MAX_TASKS distinct d per iteration
         if (it && !it->sups.count(r->d) && (int)it->sups.size() >= QK_MAX_TASKS) break;
-        if (!r->out_host &&
-            hipHostMalloc((void**)&r->out_host, r->n_rows * sup.n * sizeof(double), 0) != hipSuccess) {
+        if ((!r->out_host &&
+             hipHostMalloc((void**)&r->out_host, r->n_rows * sup.n * sizeof(double), 0) != hipSuccess) ||
+            (sup.coef && !r->f_host &&
+             hipHostMalloc((void**)&r->f_host, r->n_rows * sizeof(double), 0) != hipSuccess)) {
+          free_host(r);
           s->pending.pop_front();
           finish(s, r, QK_REQ_FAILED, "pinned result allocation failed");
           s->cv_done.notify_all();
@@ -389,6 +429,44 @@ qk_status qk_server_load_support(qk_server* s, const qk_circuit_desc* c, const d
   return QK_OK;
 }
 
+qk_status qk_server_set_model(qk_server* s, int32_t d, const double* coef_host, int64_t n,
+                              double intercept) {
+  if (!s) return qk_fail(QK_ERR_INVALID_ARG, "NULL server");
+  if (!std::isfinite(intercept)) return qk_fail(QK_ERR_INVALID_ARG, "intercept must be finite");
+  int64_t ns = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto f = s->supports.find(d);
+    if (f == s->supports.end()) return qk_fail(QK_ERR_NOT_FOUND, "no support set loaded for this d");
+    ns = f->second.n;
+  }
+  if (!coef_host) {
+    // removes the model: requests admitted from now on return kernel rows only
+    std::lock_guard<std::mutex> lk(s->mu);
+    Support& sup = s->supports.at(d);
+    if (sup.coef) s->old_coefs.push_back(sup.coef);
+    sup.coef = nullptr;
+    sup.intercept = 0.0;
+    return QK_OK;
+  }
+  if (n != ns) return qk_fail(QK_ERR_INVALID_ARG, "coefficient count differs from the support size");
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(coef_host[i])) return qk_fail(QK_ERR_INVALID_ARG, "non-finite coefficient");
+  double* dc = nullptr;
+  if (hipMalloc((void**)&dc, n * sizeof(double)) != hipSuccess)
+    return qk_fail(QK_ERR_OUT_OF_MEMORY, "model allocation failed");
+  if (hipMemcpy(dc, coef_host, n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(dc);
+    return qk_fail(QK_ERR_HIP, "model upload failed");
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  Support& sup = s->supports.at(d);
+  if (sup.coef) s->old_coefs.push_back(sup.coef);
+  sup.coef = dc;
+  sup.intercept = intercept;
+  return QK_OK;
+}
+
 qk_status qk_server_submit(qk_server* s, const double* x_host, int64_t n_rows, int32_t d,
                            double w, int64_t* id) {
   if (!s || !x_host || !id || n_rows < 1) return qk_fail(QK_ERR_INVALID_ARG, "bad request");
@@ -420,8 +498,8 @@ qk_status qk_server_submit(qk_server* s, const double* x_host, int64_t n_rows, i
   return QK_OK;
 }
 
-qk_status qk_server_poll(qk_server* s, int64_t id, double* rows_host, int64_t ld_rows,
-                         int32_t* state) {
+qk_status qk_server_poll_decision(qk_server* s, int64_t id, double* rows_host, int64_t ld_rows,
+                                  double* f_host, int32_t* state) {
   if (!s || !state) return qk_fail(QK_ERR_INVALID_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(s->mu);
   auto f = s->reqs.find(id);
@@ -429,19 +507,30 @@ qk_status qk_server_poll(qk_server* s, int64_t id, double* rows_host, int64_t ld
   Request* r = f->second;
   *state = r->state;
   if (r->state == QK_REQ_FAILED) return qk_fail(QK_OK, r->err);
-  if (r->state == QK_REQ_DONE && rows_host) {
-    if (ld_rows < r->n_support) return qk_fail(QK_ERR_INVALID_ARG, "ld_rows < support size");
-    for (int64_t q = 0; q < r->n_rows; ++q)
-      std::memcpy(rows_host + q * ld_rows, r->out_host + q * r->n_support,
-                  r->n_support * sizeof(double));
-    (void)hipHostFree(r->out_host);
+  const bool fetch = rows_host || f_host;
+  if (r->state == QK_REQ_DONE && fetch) {
+    if (rows_host && ld_rows < r->n_support)
+      return qk_fail(QK_ERR_INVALID_ARG, "ld_rows < support size");
+    if (f_host && !r->f_host)
+      return qk_fail(QK_ERR_INVALID_ARG, "the request was admitted without a model");
+    if (rows_host)
+      for (int64_t q = 0; q < r->n_rows; ++q)
+        std::memcpy(rows_host + q * ld_rows, r->out_host + q * r->n_support,
+                    r->n_support * sizeof(double));
+    if (f_host) std::memcpy(f_host, r->f_host, r->n_rows * sizeof(double));
+    free_host(r);
     s->reqs.erase(f);
     delete r;
-  } else if ((r->state == QK_REQ_CANCELLED) && rows_host) {
+  } else if (r->state == QK_REQ_CANCELLED && fetch) {
     s->reqs.erase(f);
     delete r;
   }
   return QK_OK;
+}
+
+qk_status qk_server_poll(qk_server* s, int64_t id, double* rows_host, int64_t ld_rows,
+                         int32_t* state) {
+  return qk_server_poll_decision(s, id, rows_host, ld_rows, nullptr, state);
 }
 
 qk_status qk_server_wait(qk_server* s, int64_t id, int32_t timeout_ms, int32_t* state) {
@@ -511,13 +600,15 @@ qk_status qk_server_destroy(qk_server* s) {
   if (s->worker.joinable()) s->worker.join();
   (void)hipDeviceSynchronize();
   for (auto& kv : s->reqs) {
-    if (kv.second->out_host) (void)hipHostFree(kv.second->out_host);
+    free_host(kv.second);
     delete kv.second;
   }
   for (auto& kv : s->supports) {
     qk_mps_release(kv.second.mps);
     (void)hipFree(kv.second.x);
+    if (kv.second.coef) (void)hipFree(kv.second.coef);
   }
+  for (double* c : s->old_coefs) (void)hipFree(c);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   delete s;
   return QK_OK;

@@ -114,6 +114,9 @@ _lib.qk_server_create.argtypes = [C.POINTER(qk_server_config), C.POINTER(_P)]
 _lib.qk_server_load_support.argtypes = [_P, C.POINTER(qk_circuit_desc), _P, C.c_int64, C.c_int64]
 _lib.qk_server_submit.argtypes = [_P, _P, C.c_int64, C.c_int32, C.c_double, _I64P]
 _lib.qk_server_poll.argtypes = [_P, C.c_int64, _P, C.c_int64, C.POINTER(C.c_int32)]
+_lib.qk_server_set_model.argtypes = [_P, C.c_int32, _P, C.c_int64, C.c_double]
+_lib.qk_server_poll_decision.argtypes = [_P, C.c_int64, _P, C.c_int64, _P,
+                                         C.POINTER(C.c_int32)]
 _lib.qk_server_wait.argtypes = [_P, C.c_int64, C.c_int32, C.POINTER(C.c_int32)]
 _lib.qk_server_cancel.argtypes = [_P, C.c_int64]
 _lib.qk_server_request_times.argtypes = [_P, C.c_int64, C.POINTER(C.c_double),
@@ -121,14 +124,14 @@ _lib.qk_server_request_times.argtypes = [_P, C.c_int64, C.POINTER(C.c_double),
 _lib.qk_server_stats.argtypes = [_P, _I64P, _I64P, _I64P, _I64P]
 _lib.qk_server_destroy.argtypes = [_P]
 for _f in ("qk_server_create", "qk_server_load_support", "qk_server_submit", "qk_server_poll",
-           "qk_server_wait", "qk_server_cancel", "qk_server_request_times", "qk_server_stats",
+           "qk_server_set_model", "qk_server_poll_decision", "qk_server_wait", "qk_server_cancel", "qk_server_request_times", "qk_server_stats",
            "qk_server_destroy"):
     getattr(_lib, _f).restype = C.c_int
 
 QK_REQ_QUEUED, QK_REQ_RUNNING, QK_REQ_DONE, QK_REQ_FAILED, QK_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 EXPORTED = ["qk_server_create", "qk_server_load_support", "qk_server_submit",
-            "qk_server_poll", "qk_server_wait", "qk_server_cancel", "qk_server_request_times",
+            "qk_server_poll", "qk_server_set_model", "qk_server_poll_decision", "qk_server_wait", "qk_server_cancel", "qk_server_request_times",
             "qk_server_stats", "qk_server_destroy",
             "qk_mps_build", "qk_mps_build_many", "qk_mps_import", "qk_mps_info", "qk_mps_chi",
             "qk_mps_release", "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
@@ -458,6 +461,36 @@ def qk_server_poll(server: Server, rid: int, out: np.ndarray | None = None):
         return st.value, (out if st.value == QK_REQ_DONE else None)
     _check(_lib.qk_server_poll(server.handle, rid, None, 0, C.byref(st)))
     return st.value, None
+
+
+def qk_server_set_model(server: Server, d: int, coef, intercept: float):
+    """Attaches SVM coefficients alpha_i y_i (one per support sample) and the
+    intercept b to the support set of dimension d; coef None removes it."""
+    if coef is None:
+        _check(_lib.qk_server_set_model(server.handle, int(d), None, 0, float(intercept)))
+        return
+    c = np.ascontiguousarray(coef, dtype=np.float64)
+    if c.ndim != 1:
+        raise ValueError("coef must be 1-D")
+    _check(_lib.qk_server_set_model(server.handle, int(d), c.ctypes.data_as(C.c_void_p),
+                                    c.shape[0], float(intercept)))
+
+
+def qk_server_poll_decision(server: Server, rid: int, n_rows: int, out: np.ndarray | None = None):
+    """Returns (state, rows or None, decision values or None); both are
+    fetched (and the request released) when DONE."""
+    st = C.c_int32()
+    f = np.empty(int(n_rows), dtype=np.float64)
+    rows_p, ld = None, 0
+    if out is not None:
+        if out.dtype != np.float64 or not out.flags.c_contiguous or out.shape[0] != n_rows:
+            raise TypeError("out must be a C-contiguous float64 array of n_rows rows")
+        rows_p, ld = out.ctypes.data_as(C.c_void_p), out.shape[1]
+    _check(_lib.qk_server_poll_decision(server.handle, rid, rows_p, ld,
+                                        f.ctypes.data_as(C.c_void_p), C.byref(st)))
+    if st.value != QK_REQ_DONE:
+        return st.value, None, None
+    return st.value, out, f
 
 
 def qk_server_wait(server: Server, rid: int, timeout_ms: int = -1) -> int:

@@ -149,3 +149,51 @@ def test_rejections_and_cancel(qk, data):
         assert qk.qk_server_stats(srv)["n_done"] >= 19
     finally:
         srv.close()
+
+
+def test_decision_values_with_model(qk, data):
+    """An SVM attached to the d=16 support set (Eqs. (4), (5)): each request
+    of that d also returns f = K_rows coef + b, equal to the oracle's decision
+    function on the returned rows, and within sum|coef| times the row
+    tolerance of the oracle's decision on the oracle's rows. A d=64 request
+    (no model) in the same iteration returns rows only; asking it for
+    decision values is rejected without releasing it. Removing the model
+    turns the values off for later requests."""
+    rng = np.random.default_rng(2016)
+    coef = rng.standard_normal(NSUP[16]) / NSUP[16]
+    coef[rng.random(NSUP[16]) < 0.4] = 0.0  # samples that are not support vectors
+    b = -0.125
+    srv = make_server(qk, data)
+    try:
+        with pytest.raises(qk.QkError):
+            qk.qk_server_set_model(srv, 16, coef[:-1], b)
+        with pytest.raises(qk.QkError):
+            qk.qk_server_set_model(srv, 32, coef, b)
+        qk.qk_server_set_model(srv, 16, coef, b)
+        x16, x64 = data[16][1][:9], data[64][1][:5]
+        r16 = qk.qk_server_submit(srv, x16, 0.7)
+        r64 = qk.qk_server_submit(srv, x64, 0.3)
+        print("[serve decision] d=16 rows=9 with model, d=64 rows=5 without", flush=True)
+        assert qk.qk_server_wait(srv, r16, 60000) == qk.QK_REQ_DONE
+        assert qk.qk_server_wait(srv, r64, 60000) == qk.QK_REQ_DONE
+        out = np.empty((9, NSUP[16]))
+        st, rows, f = qk.qk_server_poll_decision(srv, r16, 9, out)
+        assert st == qk.QK_REQ_DONE
+        assert np.allclose(f, classical.svm_decision(rows, coef, b), rtol=1e-12, atol=1e-12)
+        ref_rows = oracle_rows(x16, data[16][0], 0.7)
+        ok, dmax, rel = checks.gate_a(rows, ref_rows)
+        assert ok, (dmax, rel)
+        f_ref = classical.svm_decision(ref_rows, coef, b)
+        assert np.max(np.abs(f - f_ref)) <= 1e-5 * np.sum(np.abs(coef)) + 1e-12
+        with pytest.raises(qk.QkError):
+            qk.qk_server_poll_decision(srv, r64, 5, None)
+        assert fetch(qk, srv, r64, 5, NSUP[64]).shape == (5, NSUP[64])
+        qk.qk_server_set_model(srv, 16, None, 0.0)
+        r16b = qk.qk_server_submit(srv, x16[:2], 0.7)
+        assert qk.qk_server_wait(srv, r16b, 60000) == qk.QK_REQ_DONE
+        with pytest.raises(qk.QkError):
+            qk.qk_server_poll_decision(srv, r16b, 2, None)
+        got = fetch(qk, srv, r16b, 2, NSUP[16])
+        assert np.array_equal(got, rows[:2])
+    finally:
+        srv.close()
