@@ -25,6 +25,9 @@ Quantum-Classical Dual Kernel"):
   rescaling -- ``mps``;
 * the RBF kernel of Eq. (3), the linear mix of Eq. (11) and the SVM
   decision values of Eqs. (4), (5) on kernel rows -- ``classical``;
+* SVM training on a precomputed kernel: the dual of Eqs. (1)-(2) by
+  sequential minimal optimisation with second-order pair selection, the
+  bias of Eq. (5), and one-against-one voting -- ``svm``;
 * kernel invariants and the tolerance gates used by the parity tests --
   ``checks``.
 
@@ -34,4 +37,4 @@ the test-suite docstrings. ``mps.build_mps`` in the truncating regime
 through the discarded-weight bound; beyond that it is parity unpinned
 (its own step-by-step replay is the reference).
 """
-from . import circuit, statevector, closed_form, pathsum, mps, classical, checks  # noqa: F401
+from . import circuit, statevector, closed_form, pathsum, mps, classical, checks, svm  # noqa: F401

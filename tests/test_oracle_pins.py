@@ -266,3 +266,81 @@ def test_svm_decision_vs_scikit_learn():
     assert np.allclose(f, svc.decision_function(rows), rtol=1e-10, atol=1e-12)
     # sign(f) is the predicted label: scikit-learn's classes_ are (-1, +1)
     assert np.array_equal(np.where(f > 0, 1, -1), svc.predict(rows))
+
+
+def _c1_dual_kernel(n):
+    x, _, lab = config_inputs("C1")
+    P = mps.pad_batch(mps.build_batch(x[:n], 1, 16))
+    K, _ = mps.gram(P, P)
+    return classical.mix(K, classical.rbf_gram(x[:n], x[:n], 1.0 / 8), 0.5), lab[:n]
+
+
+def test_smo_closed_forms():
+    """Eqs. (1)-(2) by hand. Identity kernel, labels +1/-1: the equality
+    constraint gives a_1 = a_2 = a, the objective a^2 - 2a is least at a = 1
+    (b = 0), and C = 0.5 clips it to the bound (b = 0 by symmetry). Linear
+    kernel on x = (-2, -1, 1, 2): the hard-margin separator is f(x) = x, so
+    the support vectors are +-1 with a = 1/2 and b = 0."""
+    from oracle import svm
+    a, b, _ = svm.smo(np.eye(2), np.array([1.0, -1.0]), 10.0, 1e-12)
+    assert np.array_equal(a, [1.0, 1.0]) and b == 0.0
+    a, b, _ = svm.smo(np.eye(2), np.array([1.0, -1.0]), 0.5, 1e-12)
+    assert np.array_equal(a, [0.5, 0.5]) and b == 0.0
+    X = np.array([-2.0, -1.0, 1.0, 2.0])
+    y = np.array([-1.0, -1.0, 1.0, 1.0])
+    a, b, _ = svm.smo(np.outer(X, X), y, 100.0, 1e-12)
+    assert np.allclose(a, [0.0, 0.5, 0.5, 0.0], atol=1e-12) and abs(b) < 1e-12
+    xs = np.linspace(-3, 3, 7)
+    f = classical.svm_decision(np.outer(xs, X), a * y, b)
+    assert np.allclose(f, xs, atol=1e-12)
+
+
+def test_smo_kkt_and_scikit_learn_binary():
+    """The binary solver on the dual kernel of two classes of the 8-feature
+    clusters: feasibility (0 <= a <= C, sum a y = 0), the KKT violation of a
+    gradient recomputed from scratch below eps, and the multipliers, bias
+    and decision values of scikit-learn's SVC (LIBSVM) at a tight tolerance."""
+    from sklearn.svm import SVC
+
+    from oracle import svm
+    Km, lab = _c1_dual_kernel(80)
+    pick = np.where((lab == 0) | (lab == 1))[0]
+    tr, te = pick[:12], pick[12:]
+    y = np.where(lab[tr] == 1, 1.0, -1.0)
+    Kt = Km[np.ix_(tr, tr)]
+    for C in (10.0, 0.05):
+        a, b, it = svm.smo(Kt, y, C, 1e-10)
+        assert it > 0 and np.all(a >= 0) and np.all(a <= C)
+        assert abs(float(np.dot(a, y))) < 1e-12
+        G = (np.outer(y, y) * Kt) @ a - 1.0
+        v = -y * G
+        up = ((y > 0) & (a < C)) | ((y < 0) & (a > 0))
+        low = ((y > 0) & (a > 0)) | ((y < 0) & (a < C))
+        assert v[up].max() - v[low].min() < 1e-9
+        svc = SVC(kernel="precomputed", C=C, tol=1e-12, shrinking=False).fit(Kt, y)
+        coef = np.zeros(len(tr))
+        coef[svc.support_] = svc.dual_coef_[0]
+        assert np.allclose(a * y, coef, atol=1e-7)
+        assert abs(b - float(svc.intercept_[0])) < 1e-7
+        rows = Km[np.ix_(te, tr)]
+        assert np.allclose(classical.svm_decision(rows, a * y, b),
+                           svc.decision_function(rows), atol=1e-7)
+
+
+def test_ovo_voting_vs_scikit_learn():
+    """One-against-one over three classes (Section II-B): decision values
+    and voted labels equal scikit-learn's SVC with decision_function_shape
+    'ovo' (pair order (0,1), (0,2), (1,2); positive means the first class)."""
+    from sklearn.svm import SVC
+
+    from oracle import svm
+    Km, lab = _c1_dual_kernel(90)
+    labs = lab % 3
+    coef, b, iters = svm.fit_ovo(Km[:60, :60], labs[:60], 3, C=10.0, eps=1e-10)
+    assert np.all(iters > 0)
+    assert np.all(coef[0][labs[:60] == 2] == 0.0)  # pair (0, 1) uses no class-2 sample
+    svc = SVC(kernel="precomputed", C=10.0, tol=1e-12, shrinking=False,
+              decision_function_shape="ovo").fit(Km[:60, :60], labs[:60])
+    f, pred = svm.predict_ovo(Km[60:, :60], coef, b, 3)
+    assert np.allclose(f, svc.decision_function(Km[60:, :60]), atol=1e-6)
+    assert np.array_equal(pred, svc.predict(Km[60:, :60]))

@@ -83,3 +83,37 @@ def test_shifted_angle_index_is_caught(monkeypatch):
     u, v, w = x[0] - y[0], x[1] - y[1], 0.5 * (tx - ty)
     ref = abs(0.5 * (np.exp(1j * w) * math.cos(u + v) + np.exp(-1j * w) * math.cos(u - v))) ** 2
     assert sv.kernel_overlap(x, y, 1) != pytest.approx(ref, rel=1e-6)
+
+
+def _svm_vs_libsvm():
+    """True when the oracle's OvO decision values match scikit-learn's."""
+    from sklearn.svm import SVC
+
+    from oracle import classical, svm
+    from synthdata import config_inputs
+    x, _, lab = config_inputs("C1")
+    x, labs = x[:60], lab[:60] % 3
+    Km = classical.rbf_gram(x, x, 1.0 / 8)
+    coef, b, _ = svm.fit_ovo(Km[:45, :45], labs[:45], 3, C=10.0, eps=1e-10)
+    f, _ = svm.predict_ovo(Km[45:, :45], coef, b, 3)
+    svc = SVC(kernel="precomputed", C=10.0, tol=1e-12, shrinking=False,
+              decision_function_shape="ovo").fit(Km[:45, :45], labs[:45])
+    return bool(np.allclose(f, svc.decision_function(Km[45:, :45]), atol=1e-6))
+
+
+def test_unpatched_svm_oracle_agrees():
+    assert _svm_vs_libsvm()
+
+
+def test_flipped_svm_bias_sign_is_caught(monkeypatch):
+    from oracle import svm
+    orig = svm.intercept
+    monkeypatch.setattr(svm, "intercept", lambda *a: -orig(*a))
+    assert not _svm_vs_libsvm()
+
+
+def test_swapped_ovo_orientation_is_caught(monkeypatch):
+    from oracle import svm
+    orig = svm.ovo_pairs
+    monkeypatch.setattr(svm, "ovo_pairs", lambda n: [(b, a) for a, b in orig(n)])
+    assert not _svm_vs_libsvm()
