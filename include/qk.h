@@ -277,6 +277,59 @@ QK_API qk_status qk_svm_decision(const double* k_dev, int64_t m, int64_t n, int6
                                  void* hip_stream);
 
 /*
+ * qk_svm_fit_ovo -- trains the SVMs of Eqs. (1)-(2) on a precomputed kernel
+ * matrix, one binary problem per pair of classes (one-against-one, Section
+ * II-B), all problems in one launch (one workgroup each).
+ *   k_dev       n x n symmetric kernel matrix of the training samples
+ *               (device, leading dimension ld_k >= n), e.g. the dual kernel
+ *               from qk_overlap_gram in symmetric mode.
+ *   labels_host n class labels in [0, n_classes) (host, read before return).
+ *   n_classes   2..64; P = n_classes (n_classes - 1) / 2 problems, ordered
+ *               (0,1), (0,2), ..., (0,n_classes-1), (1,2), ...
+ *   C           the box bound of Eq. (2); eps the stopping tolerance on the
+ *               maximal KKT violation (LIBSVM's default is 1e-3); max_iter
+ *               caps the SMO steps per problem.
+ *   coef_dev    P x n output (device, leading dimension ld_coef >= n): row p
+ *               holds alpha_t y_t at the samples of problem p (y = +1 for
+ *               its first class) and 0 elsewhere, so qk_svm_decision with
+ *               row p gives f_p = K_row . coef_p + b_p.
+ *   intercept_dev  P biases b_p of Eq. (5) (device output).
+ *   n_iter_dev  P SMO step counts (device output, int64); a count equal to
+ *               max_iter means the problem stopped unconverged.
+ * Method: SMO with the second-order pair selection of Fan, Chen and Lin
+ * (2005), ties to the smallest sample index, each FP64 operation rounded
+ * separately; b from the KKT conditions (mean over the free multipliers,
+ * else the midpoint of the bounded interval). A problem's samples are those
+ * of its two classes in increasing order. Device scratch (about 36 bytes
+ * per sample per problem) comes from the stream-ordered pool. The call
+ * blocks until the stream has reached the upload of the problem tables (it
+ * waits for the work enqueued before it); training itself is asynchronous.
+ * The kernel matrix must be finite. Errors: INVALID_ARG (sizes, NULL
+ * pointers, labels out of range, C / eps not positive and finite,
+ * max_iter < 1), OUT_OF_MEMORY, HIP.
+ */
+#define QK_SVM_MAX_CLASSES 64
+QK_API qk_status qk_svm_fit_ovo(const double* k_dev, int64_t n, int64_t ld_k,
+                                const int32_t* labels_host, int32_t n_classes, double C,
+                                double eps, int64_t max_iter, double* coef_dev, int64_t ld_coef,
+                                double* intercept_dev, int64_t* n_iter_dev, void* hip_stream);
+
+/*
+ * qk_svm_predict_ovo -- one-against-one prediction from m kernel rows
+ * against the n training samples (k_dev m x n, leading dimension ld_k >= n),
+ * with the P coefficient rows and biases of qk_svm_fit_ovo. Writes the
+ * decision values f (m x P, leading dimension ld_f >= P; NULL to skip) and
+ * the voted labels (m int32; NULL to skip): problem (a, b) votes a when
+ * f > 0, else b; the label is the class with most votes, ties to the
+ * smaller class. One workgroup per row. FP64. Errors: INVALID_ARG (sizes,
+ * NULL pointers, both outputs NULL), HIP.
+ */
+QK_API qk_status qk_svm_predict_ovo(const double* k_dev, int64_t m, int64_t n, int64_t ld_k,
+                                    const double* coef_dev, int64_t ld_coef,
+                                    const double* intercept_dev, int32_t n_classes, double* f_dev,
+                                    int64_t ld_f, int32_t* labels_dev, void* hip_stream);
+
+/*
  * Reduced-precision forms (QK_PREC_FP32, _FP32_MFMA, _BF16X2, _BF16X3) carry
  * a relative error of ~1e-5 (FP32-class) or ~2e-4 (BF16X2) in K_q after
  * hundreds of sites, which exceeds 1e-5 absolute only where K_q is large.

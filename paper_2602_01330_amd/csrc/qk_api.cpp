@@ -810,6 +810,107 @@ qk_status qk_svm_decision(const double* k_dev, int64_t m, int64_t n, int64_t ld_
   return QK_OK;
 }
 
+qk_status qk_svm_fit_ovo(const double* k_dev, int64_t n, int64_t ld_k, const int32_t* labels_host,
+                         int32_t n_classes, double C, double eps, int64_t max_iter,
+                         double* coef_dev, int64_t ld_coef, double* intercept_dev,
+                         int64_t* n_iter_dev, void* hip_stream) {
+  if (n < 1 || n > INT32_MAX) return fail(QK_ERR_INVALID_ARG, "n must be in [1, 2^31 - 1]");
+  if (!k_dev || !labels_host || !coef_dev || !intercept_dev || !n_iter_dev)
+    return fail(QK_ERR_INVALID_ARG, "NULL pointer");
+  if (ld_k < n || ld_coef < n) return fail(QK_ERR_INVALID_ARG, "leading dimension too small");
+  if (n_classes < 2 || n_classes > QK_SVM_MAX_CLASSES)
+    return fail(QK_ERR_INVALID_ARG, "n_classes must be in [2, 64]");
+  if (!(C > 0.0) || !std::isfinite(C)) return fail(QK_ERR_INVALID_ARG, "C must be positive");
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(QK_ERR_INVALID_ARG, "eps must be positive");
+  if (max_iter < 1) return fail(QK_ERR_INVALID_ARG, "max_iter must be positive");
+  std::vector<std::vector<int32_t>> by_class(n_classes);
+  for (int64_t t = 0; t < n; ++t) {
+    const int32_t c = labels_host[t];
+    if (c < 0 || c >= n_classes) return fail(QK_ERR_INVALID_ARG, "label outside [0, n_classes)");
+    by_class[c].push_back((int32_t)t);
+  }
+  // problem (a, b), a < b, in lexicographic order: the samples of both
+  // classes in increasing order, y = +1 for class a
+  const int P = n_classes * (n_classes - 1) / 2;
+  std::vector<int64_t> off(P + 1, 0);
+  std::vector<int32_t> idx;
+  std::vector<double> yv;
+  idx.reserve((size_t)(n_classes - 1) * n);
+  yv.reserve((size_t)(n_classes - 1) * n);
+  int p = 0;
+  for (int a = 0; a < n_classes; ++a)
+    for (int b = a + 1; b < n_classes; ++b, ++p) {
+      const auto& A = by_class[a];
+      const auto& B = by_class[b];
+      size_t ia = 0, ib = 0;
+      while (ia < A.size() || ib < B.size()) {
+        if (ib == B.size() || (ia < A.size() && A[ia] < B[ib])) {
+          idx.push_back(A[ia++]);
+          yv.push_back(1.0);
+        } else {
+          idx.push_back(B[ib++]);
+          yv.push_back(-1.0);
+        }
+      }
+      off[p + 1] = (int64_t)idx.size();
+    }
+  const int64_t tot = (int64_t)idx.size();
+  hipStream_t s = (hipStream_t)hip_stream;
+  // one stream-ordered block: off | y | alpha | grad | diag | idx
+  const int64_t bytes = (int64_t)(P + 1) * 8 + tot * 8 * 4 + tot * 4 + 16;
+  char* dbuf = nullptr;
+  QK_HIP(hipMallocAsync((void**)&dbuf, bytes, s), "SVM scratch allocation");
+  int64_t* d_off = reinterpret_cast<int64_t*>(dbuf);
+  double* d_y = reinterpret_cast<double*>(dbuf + (int64_t)(P + 1) * 8);
+  double* d_alpha = d_y + tot;
+  double* d_grad = d_alpha + tot;
+  double* d_diag = d_grad + tot;
+  int32_t* d_idx = reinterpret_cast<int32_t*>(d_diag + tot);
+  // tables go up through pinned staging; the call waits for the upload so
+  // the staging can be freed before returning
+  const int64_t hbytes = (int64_t)(P + 1) * 8 + tot * 8 + tot * 4;
+  char* hbuf = nullptr;
+  if (hipHostMalloc((void**)&hbuf, hbytes, 0) != hipSuccess) {
+    (void)hipFreeAsync(dbuf, s);
+    return fail(QK_ERR_OUT_OF_MEMORY, "SVM staging allocation failed");
+  }
+  std::memcpy(hbuf, off.data(), (P + 1) * 8);
+  std::memcpy(hbuf + (P + 1) * 8, yv.data(), tot * 8);
+  std::memcpy(hbuf + (P + 1) * 8 + tot * 8, idx.data(), tot * 4);
+  hipError_t e = hipMemcpyAsync(d_off, hbuf, (P + 1) * 8 + tot * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_idx, hbuf + (P + 1) * 8 + tot * 8, tot * 4, hipMemcpyHostToDevice, s);
+  const hipError_t es = hipStreamSynchronize(s);
+  (void)hipHostFree(hbuf);
+  if (e == hipSuccess) e = es;
+  if (e == hipSuccess)
+    e = qk_launch_svm_smo(k_dev, ld_k, d_idx, d_y, d_off, P, C, eps, max_iter, d_alpha, d_grad,
+                          d_diag, coef_dev, ld_coef, n, intercept_dev, n_iter_dev, s);
+  (void)hipFreeAsync(dbuf, s);
+  if (e != hipSuccess) return hip_fail(e, "SVM training");
+  return QK_OK;
+}
+
+qk_status qk_svm_predict_ovo(const double* k_dev, int64_t m, int64_t n, int64_t ld_k,
+                             const double* coef_dev, int64_t ld_coef, const double* intercept_dev,
+                             int32_t n_classes, double* f_dev, int64_t ld_f, int32_t* labels_dev,
+                             void* hip_stream) {
+  if (m < 0 || m > INT32_MAX) return fail(QK_ERR_INVALID_ARG, "m must be in [0, 2^31 - 1]");
+  if (n < 1) return fail(QK_ERR_INVALID_ARG, "n < 1");
+  if (n_classes < 2 || n_classes > QK_SVM_MAX_CLASSES)
+    return fail(QK_ERR_INVALID_ARG, "n_classes must be in [2, 64]");
+  const int64_t P = (int64_t)n_classes * (n_classes - 1) / 2;
+  if (ld_k < n || ld_coef < n || (f_dev && ld_f < P))
+    return fail(QK_ERR_INVALID_ARG, "leading dimension too small");
+  if (!f_dev && !labels_dev) return fail(QK_ERR_INVALID_ARG, "no output requested");
+  if (m > 0 && (!k_dev || !coef_dev || !intercept_dev)) return fail(QK_ERR_INVALID_ARG, "NULL pointer");
+  hipError_t e = qk_launch_svm_predict(k_dev, m, n, ld_k, coef_dev, ld_coef, intercept_dev,
+                                       n_classes, f_dev, ld_f, labels_dev,
+                                       (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "SVM prediction launch");
+  return QK_OK;
+}
+
 qk_status qk_resolve_precision(const qk_mps_batch* rows, const qk_mps_batch* cols,
                                qk_precision* out) {
   if (!rows || !cols || !out) return fail(QK_ERR_INVALID_ARG, "NULL argument");

@@ -199,3 +199,19 @@ hipError_t qk_launch_mix(const double* kq, int64_t ld_kq, const double* kc,
                          double* k, int64_t ld_k, hipStream_t s);
 hipError_t qk_launch_svm_decision(const double* k, int64_t m, int64_t n, int64_t ld_k,
                                   const double* coef, double b, double* f, hipStream_t s);
+// SVM training by SMO, one workgroup per binary problem p: samples
+// idx[off[p] .. off[p+1]) (global rows of the symmetric kernel k), labels
+// y = +1/-1 alongside; alpha / grad / diag are scratch of the same length;
+// writes coef row p (n_all entries, a_t y_t at the problem's samples), b[p]
+// and the step count iters[p] (svm.hip).
+hipError_t qk_launch_svm_smo(const double* k, int64_t ld_k, const int32_t* idx, const double* y,
+                             const int64_t* off, int n_problems, double C, double eps,
+                             int64_t max_iter, double* alpha, double* grad, double* diag,
+                             double* coef, int64_t ld_coef, int64_t n_all, double* b,
+                             int64_t* iters, hipStream_t s);
+// One-against-one decision values (m x n_problems, optional) and voted
+// labels (optional) of m kernel rows (svm.hip).
+hipError_t qk_launch_svm_predict(const double* k, int64_t m, int64_t n, int64_t ld_k,
+                                 const double* coef, int64_t ld_coef, const double* b,
+                                 int n_classes, double* f, int64_t ld_f, int32_t* labels,
+                                 hipStream_t s);

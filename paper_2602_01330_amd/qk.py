@@ -85,6 +85,12 @@ _lib.qk_dual_mix.argtypes = [_P, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int64,
                              _P, C.c_int64, _P]
 _lib.qk_svm_decision.argtypes = [_P, C.c_int64, C.c_int64, C.c_int64, _P, C.c_double, _P, _P]
 _lib.qk_svm_decision.restype = C.c_int
+_lib.qk_svm_fit_ovo.argtypes = [_P, C.c_int64, C.c_int64, _P, C.c_int32, C.c_double, C.c_double,
+                                C.c_int64, _P, C.c_int64, _P, _P, _P]
+_lib.qk_svm_fit_ovo.restype = C.c_int
+_lib.qk_svm_predict_ovo.argtypes = [_P, C.c_int64, C.c_int64, C.c_int64, _P, C.c_int64, _P,
+                                    C.c_int32, _P, C.c_int64, _P, _P]
+_lib.qk_svm_predict_ovo.restype = C.c_int
 _lib.qk_resolve_precision.argtypes = [_P, _P, C.POINTER(C.c_int)]
 _lib.qk_set_refine_threshold.argtypes = [C.c_int, C.c_double]
 _lib.qk_set_launch_timing.argtypes = [C.c_int32]
@@ -135,7 +141,7 @@ EXPORTED = ["qk_server_create", "qk_server_load_support", "qk_server_submit",
             "qk_server_stats", "qk_server_destroy",
             "qk_mps_build", "qk_mps_build_many", "qk_mps_import", "qk_mps_info", "qk_mps_chi",
             "qk_mps_release", "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
-            "qk_svm_decision", "qk_resolve_precision", "qk_set_refine_threshold", "qk_autotune",
+            "qk_svm_decision", "qk_svm_fit_ovo", "qk_svm_predict_ovo", "qk_resolve_precision", "qk_set_refine_threshold", "qk_autotune",
             "qk_tune_export", "qk_tune_import", "qk_status_string",
             "qk_last_error", "qk_set_launch_timing", "qk_last_launch_ms"]
 
@@ -339,6 +345,48 @@ def qk_svm_decision(k, coef, intercept, f, stream=None):
     _check(_lib.qk_svm_decision(kp, k.shape[0], k.shape[1], ldk, cp, float(intercept), fp,
                                 _stream(stream)))
     return f
+
+
+def qk_svm_fit_ovo(k, labels, n_classes: int, C_box: float, eps: float = 1e-3,
+                   max_iter: int = 10_000_000, stream=None):
+    """Trains the one-against-one SVMs on the symmetric n x n kernel k
+    (device FP64). Returns device tensors (coef P x n, intercept P, n_iter P)."""
+    kp, ldk = _mat(k, "k")
+    n = k.shape[0]
+    if k.shape[1] != n:
+        raise ValueError("k must be square")
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    if lab.shape != (n,):
+        raise ValueError("labels must have one entry per row of k")
+    P = n_classes * (n_classes - 1) // 2
+    coef = torch.empty((max(P, 1), n), dtype=torch.float64, device=k.device)
+    b = torch.empty(max(P, 1), dtype=torch.float64, device=k.device)
+    it = torch.empty(max(P, 1), dtype=torch.int64, device=k.device)
+    _check(_lib.qk_svm_fit_ovo(kp, n, ldk, lab.ctypes.data_as(C.c_void_p), int(n_classes),
+                               float(C_box), float(eps), int(max_iter),
+                               C.c_void_p(coef.data_ptr()), n, C.c_void_p(b.data_ptr()),
+                               C.c_void_p(it.data_ptr()), _stream(stream)))
+    return coef, b, it
+
+
+def qk_svm_predict_ovo(k, coef, intercept, n_classes: int, stream=None):
+    """Decision values (m x P) and voted labels (m,) of kernel rows k (m x n)."""
+    kp, ldk = _mat(k, "k")
+    cp, ldc = _mat(coef, "coef")
+    if coef.shape[1] != k.shape[1]:
+        raise ValueError("coef and k must have the same number of columns")
+    P = n_classes * (n_classes - 1) // 2
+    if coef.shape[0] < P or intercept.numel() < P or intercept.dtype != torch.float64 \
+            or not intercept.is_contiguous():
+        raise ValueError("coef needs P rows and intercept P contiguous FP64 entries")
+    m = k.shape[0]
+    f = torch.empty((m, P), dtype=torch.float64, device=k.device)
+    lab = torch.empty(m, dtype=torch.int32, device=k.device)
+    _check(_lib.qk_svm_predict_ovo(kp, m, k.shape[1], ldk, cp, ldc,
+                                   C.c_void_p(intercept.data_ptr()), int(n_classes),
+                                   C.c_void_p(f.data_ptr()), P, C.c_void_p(lab.data_ptr()),
+                                   _stream(stream)))
+    return f, lab
 
 
 def qk_resolve_precision(rows: MpsBatch, cols: MpsBatch) -> str:

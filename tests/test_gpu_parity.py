@@ -429,3 +429,87 @@ def test_svm_decision_on_kernel_rows(qk):
         qk._check(qk._lib.qk_svm_decision(qk.C.c_void_p(kd.data_ptr()), 37, 1000, 999,
                                           qk.C.c_void_p(cd.data_ptr()), 0.0,
                                           qk.C.c_void_p(f.data_ptr()), None))
+
+
+def _svm_inputs(n_train, n_test):
+    """The dual kernel (Eq. (11), w = 0.5) of the 8-feature clusters,
+    computed by the oracle: train x train and test x train."""
+    x, _, lab = config_inputs("C1", n_train=n_train + n_test)
+    P = mps.pad_batch(mps.build_batch(x, 1, 16))
+    K, _ = mps.gram(P, P)
+    Km = classical.mix(K, classical.rbf_gram(x, x, 1.0 / 8), 0.5)
+    return Km[:n_train, :n_train].copy(), Km[n_train:, :n_train].copy(), lab[:n_train]
+
+
+@pytest.mark.parametrize("C_box,eps,max_iter", [(10.0, 1e-3, 100000), (0.05, 1e-6, 100000),
+                                                (10.0, 1e-6, 3)])
+def test_svm_fit_ovo_matches_oracle(qk, C_box, eps, max_iter):
+    """Eqs. (1)-(2) by SMO on the device, 45 one-against-one problems of 10
+    classes in one launch, on a kernel matrix both sides share: each pair
+    choice is an FP64 argmax / argmin that both sides evaluate with the same
+    roundings, so step counts, multipliers and biases are identical; the
+    decision values (Eq. (5)) agree to rounding and the votes are equal."""
+    from oracle import svm
+    Ktr, Kte, lab = _svm_inputs(160, 37)
+    print(f"[svm fit] n=160 classes=10 C={C_box} eps={eps} max_iter={max_iter}", flush=True)
+    coef, b, it = qk.qk_svm_fit_ovo(dev(Ktr), lab, 10, C_box, eps, max_iter)
+    torch.cuda.synchronize()
+    c_ref, b_ref, it_ref = svm.fit_ovo(Ktr, lab, 10, C_box, eps, max_iter)
+    assert np.array_equal(it.cpu().numpy(), it_ref)
+    assert np.array_equal(coef.cpu().numpy(), c_ref)
+    assert np.array_equal(b.cpu().numpy(), b_ref)
+    f, pred = qk.qk_svm_predict_ovo(dev(Kte), coef, b, 10)
+    torch.cuda.synchronize()
+    f_ref, pred_ref = svm.predict_ovo(Kte, c_ref, b_ref, 10)
+    f = f.cpu().numpy()
+    assert np.allclose(f, f_ref, rtol=1e-12, atol=1e-12)
+    clear = np.min(np.abs(f_ref), axis=1) > 1e-9
+    assert np.array_equal(pred.cpu().numpy()[clear], pred_ref[clear])
+
+
+def test_svm_binary_on_device_gram(qk):
+    """The pipeline end to end on the device: the fused symmetric Gram of
+    the encoded samples (Eqs. (7), (3), (11)), SMO training of the two
+    classes 0 / 1 on it, prediction on the test rows. The oracle solves the
+    same problem on the device's kernel matrix (copied to the host): the
+    same steps, multipliers and bias."""
+    from oracle import svm
+    x, _, lab = config_inputs("C1", n_train=120)
+    pick = np.where(lab < 2)[0]
+    xs = x[pick]
+    xd = dev(xs)
+    b = qk.qk_mps_build(xd, 1, 16)
+    n = xs.shape[0]
+    kq = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    ln = torch.empty_like(kq)
+    k = torch.empty_like(kq)
+    qk.qk_overlap_gram(b, b, True, "fp64", kq, ln,
+                       {"x_rows": xd, "x_cols": xd, "gamma": 1.0 / 8, "w": 0.5, "k": k})
+    ntr = 16
+    print(f"[svm binary] n={n} train={ntr}", flush=True)
+    ktr = k[:ntr, :ntr].contiguous()
+    coef, bias, it = qk.qk_svm_fit_ovo(ktr, lab[pick][:ntr], 2, 1.0, 1e-8)
+    f, pred = qk.qk_svm_predict_ovo(k[ntr:, :ntr].contiguous(), coef, bias, 2)
+    torch.cuda.synchronize()
+    K = k.cpu().numpy()
+    c_ref, b_ref, it_ref = svm.fit_ovo(K[:ntr, :ntr], lab[pick][:ntr], 2, 1.0, 1e-8)
+    assert it_ref[0] > 0 and np.array_equal(it.cpu().numpy(), it_ref)
+    assert np.array_equal(coef.cpu().numpy(), c_ref) and np.array_equal(bias.cpu().numpy(), b_ref)
+    f_ref, pred_ref = svm.predict_ovo(K[ntr:, :ntr], c_ref, b_ref, 2)
+    assert np.allclose(f.cpu().numpy(), f_ref, rtol=1e-12, atol=1e-12)
+    clear = np.abs(f_ref[:, 0]) > 1e-9
+    assert np.array_equal(pred.cpu().numpy()[clear], pred_ref[clear])
+    b.close()
+
+
+def test_svm_fit_rejections(qk):
+    Ktr, _, lab = _svm_inputs(20, 0)
+    kd = dev(Ktr)
+    bad = lab.copy()
+    bad[3] = 10
+    for args in [(kd, bad, 10, 1.0), (kd, lab, 1, 1.0), (kd, lab, 10, 0.0),
+                 (kd, lab, 10, float("inf"))]:
+        with pytest.raises(qk.QkError):
+            qk.qk_svm_fit_ovo(*args)
+    with pytest.raises(qk.QkError):
+        qk.qk_svm_fit_ovo(kd, lab, 10, 1.0, 1e-3, 0)
