@@ -395,6 +395,68 @@ def chi64_sweep(args):
     return res
 
 
+def svm_leg(args):
+    """SVM training and prediction (Eqs. (1)-(2), (4)-(5), one-against-one)
+    on the dual kernel of the 784-feature workload: 4000 train + 1000 test
+    images, 10 classes, L = 2, w = 0.5, gamma = 1/d. The Gram matrices come
+    from the library (untimed here); timed: the one-launch training of the 45
+    problems (C = 10, eps = 1e-3) and the prediction of the 1000 test rows.
+    The oracle solves the same 45 problems on the same kernel matrix (copied
+    to the host) for the step counts and the CPU time."""
+    import numpy as np
+    import torch
+
+    import paper_2602_01330_amd.qk as qk
+    from oracle import svm as osvm
+    from synthdata import config_inputs
+
+    x_tr, x_te, lab = config_inputs("C3")
+    ntr, nte, d = x_tr.shape[0], x_te.shape[0], x_tr.shape[1]
+    y_tr, y_te = lab[:ntr], lab[ntr:]
+    xtr = torch.as_tensor(x_tr, device="cuda")
+    xte = torch.as_tensor(x_te, device="cuda")
+    f64 = dict(dtype=torch.float64, device="cuda")
+    k_tr = torch.empty((ntr, ntr), **f64)
+    k_te = torch.empty((nte, ntr), **f64)
+    btr, bte = qk.qk_mps_build_many([xtr, xte], 2, 64, 1e-10)
+    tasks = [{"rows": btr, "cols": btr, "symmetric": True, "kq": None, "lnkq": None,
+              "fuse": {"x_rows": xtr, "x_cols": xtr, "gamma": 1.0 / d, "w": 0.5, "k": k_tr}},
+             {"rows": bte, "cols": btr, "symmetric": False, "kq": None, "lnkq": None,
+              "fuse": {"x_rows": xte, "x_cols": xtr, "gamma": 1.0 / d, "w": 0.5, "k": k_te}}]
+    qk.qk_overlap_gram_multi(tasks, "auto")
+    torch.cuda.synchronize()
+    C_box, eps = 10.0, 1e-3
+    qk.qk_svm_fit_ovo(k_tr, y_tr, 10, C_box, eps)  # warmup
+    torch.cuda.synchronize()
+    fit_ms, pred_ms = [], []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        coef, b, it = qk.qk_svm_fit_ovo(k_tr, y_tr, 10, C_box, eps)
+        torch.cuda.synchronize()
+        fit_ms.append((time.perf_counter() - t0) * 1e3)
+        t0 = time.perf_counter()
+        f, pred = qk.qk_svm_predict_ovo(k_te, coef, b, 10)
+        torch.cuda.synchronize()
+        pred_ms.append((time.perf_counter() - t0) * 1e3)
+    it = it.cpu().numpy()
+    acc = float((pred.cpu().numpy() == y_te).mean())
+    K = k_tr.cpu().numpy()
+    t0 = time.perf_counter()
+    _, _, it_ref = osvm.fit_ovo(K, y_tr, 10, C_box, eps)
+    cpu_s = time.perf_counter() - t0
+    log(f"bench: svm leg: fit {np.median(fit_ms):.1f} ms ({int(it.sum())} SMO steps), "
+        f"predict {np.median(pred_ms):.2f} ms, oracle fit {cpu_s:.1f} s")
+    for bb in (btr, bte):
+        bb.close()
+    return {"workload": "one-against-one SVMs (45 problems of 800 samples) on the dual kernel "
+                        "of 4000 train + 1000 test 784-feature images, C=10, eps=1e-3",
+            "fit_ms": float(np.median(fit_ms)), "predict_ms": float(np.median(pred_ms)),
+            "smo_steps_total": int(it.sum()), "smo_steps_max": int(it.max()),
+            "steps_equal_oracle": bool(np.array_equal(it, it_ref)),
+            "test_accuracy_synthetic_labels": acc,
+            "cpu_oracle_fit_s": cpu_s, "cpu_oracle_cores": 1}
+
+
 def run(args):
     import numpy as np
 
@@ -547,6 +609,8 @@ def run(args):
     if args.serve_seconds > 0:
         log("bench: serving run")
         leg("serving", serving)
+    if args.svm:
+        leg("svm", svm_leg)
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
@@ -572,11 +636,18 @@ def main():
                     help="measured seconds of the serving run (0 skips it)")
     ap.add_argument("--serve-warmup", type=float, default=3.0)
     ap.add_argument("--serve-rate", type=float, default=200.0, help="requests per second")
+    ap.add_argument("--svm", action="store_true",
+                    help="add the SVM training / prediction leg on the 784-feature Gram")
+    ap.add_argument("--svm-only", action="store_true",
+                    help="run only the SVM leg and print its JSON")
     ap.add_argument("--chi64-only", action="store_true",
                     help="run only the 784-site bond-64 sweep leg and print its JSON")
     args = ap.parse_args()
     if args.chi64_only:
         print(json.dumps(chi64_sweep(args)), flush=True)
+        return
+    if args.svm_only:
+        print(json.dumps(svm_leg(args)), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the Gram tiles shard across GPUs without "
