@@ -283,7 +283,10 @@ QK_API qk_status qk_svm_decision(const double* k_dev, int64_t m, int64_t n, int6
  *   k_dev       n x n symmetric kernel matrix of the training samples
  *               (device, leading dimension ld_k >= n), e.g. the dual kernel
  *               from qk_overlap_gram in symmetric mode.
- *   labels_host n class labels in [0, n_classes) (host, read before return).
+ *   labels_host n class labels in [0, n_classes) (host, read before return);
+ *               -1 leaves a sample out of training (its coefficients are 0),
+ *               so the folds of a cross-validation train on one resident
+ *               kernel matrix without copying submatrices.
  *   n_classes   2..64; P = n_classes (n_classes - 1) / 2 problems, ordered
  *               (0,1), (0,2), ..., (0,n_classes-1), (1,2), ...
  *   C           the box bound of Eq. (2); eps the stopping tolerance on the
@@ -305,7 +308,7 @@ QK_API qk_status qk_svm_decision(const double* k_dev, int64_t m, int64_t n, int6
  * blocks until the stream has reached the upload of the problem tables (it
  * waits for the work enqueued before it); training itself is asynchronous.
  * The kernel matrix must be finite. Errors: INVALID_ARG (sizes, NULL
- * pointers, labels out of range, C / eps not positive and finite,
+ * pointers, labels outside [-1, n_classes), C / eps not positive and finite,
  * max_iter < 1), OUT_OF_MEMORY, HIP.
  */
 #define QK_SVM_MAX_CLASSES 64

@@ -114,7 +114,9 @@ def fit_ovo(K, labels, n_classes: int, C: float, eps: float = 1e-3,
             max_iter: int = 10_000_000):
     """One binary problem per class pair. Returns (coef, b, n_iter): coef is
     (P, n) with coef[p][t] = alpha_t y_t on the samples of problem p and 0
-    elsewhere, so f_p(row) = row . coef[p] + b[p]."""
+    elsewhere, so f_p(row) = row . coef[p] + b[p]. A sample whose label is
+    outside [0, n_classes) (e.g. -1) belongs to no problem: it is left out
+    of training, as the held-out fold of a cross-validation is."""
     K = np.asarray(K, dtype=np.float64)
     labels = np.asarray(labels)
     n = K.shape[0]

@@ -826,8 +826,8 @@ qk_status qk_svm_fit_ovo(const double* k_dev, int64_t n, int64_t ld_k, const int
   std::vector<std::vector<int32_t>> by_class(n_classes);
   for (int64_t t = 0; t < n; ++t) {
     const int32_t c = labels_host[t];
-    if (c < 0 || c >= n_classes) return fail(QK_ERR_INVALID_ARG, "label outside [0, n_classes)");
-    by_class[c].push_back((int32_t)t);
+    if (c < -1 || c >= n_classes) return fail(QK_ERR_INVALID_ARG, "label outside [-1, n_classes)");
+    if (c >= 0) by_class[c].push_back((int32_t)t);  // -1: left out of training
   }
   // problem (a, b), a < b, in lexicographic order: the samples of both
   // classes in increasing order, y = +1 for class a

@@ -513,3 +513,41 @@ def test_svm_fit_rejections(qk):
             qk.qk_svm_fit_ovo(*args)
     with pytest.raises(qk.QkError):
         qk.qk_svm_fit_ovo(kd, lab, 10, 1.0, 1e-3, 0)
+
+
+def test_svm_cross_validation_on_resident_kernels(qk):
+    """Cross-validation over the mixing weight w (Eq. (11)) and C on one
+    resident K_q / K_c pair: the device re-mixes K for each w, trains each
+    of 3 folds with the held-out samples labelled -1 and predicts the fold's
+    rows. The oracle trains and predicts on the device's mixed matrix: fits
+    identical, fold accuracies equal."""
+    from oracle import svm
+    x, _, lab = config_inputs("C1", n_train=150)
+    labs = lab[:150] % 5
+    P = mps.pad_batch(mps.build_batch(x, 1, 16))
+    Kq, _ = mps.gram(P, P)
+    Kc = classical.rbf_gram(x, x, 1.0 / 8)
+    kq, kc = dev(Kq), dev(Kc)
+    k = torch.empty_like(kq)
+    folds = [(0, 50), (50, 100), (100, 150)]
+    for w in (0.25, 0.75):
+        qk.qk_dual_mix(kq, kc, w, k)
+        torch.cuda.synchronize()
+        K = k.cpu().numpy()
+        assert np.allclose(K, classical.mix(Kq, Kc, w), rtol=1e-15, atol=1e-15)
+        for C_box in (1.0, 10.0):
+            for lo, hi in folds:
+                print(f"[svm cv] w={w} C={C_box} fold={lo}:{hi}", flush=True)
+                masked = labs.copy()
+                masked[lo:hi] = -1
+                coef, b, it = qk.qk_svm_fit_ovo(k, masked, 5, C_box, 1e-4)
+                _, pred = qk.qk_svm_predict_ovo(k[lo:hi].contiguous(), coef, b, 5)
+                torch.cuda.synchronize()
+                c_ref, b_ref, it_ref = svm.fit_ovo(K, masked, 5, C_box, 1e-4)
+                assert np.array_equal(it.cpu().numpy(), it_ref)
+                assert np.array_equal(coef.cpu().numpy(), c_ref)
+                assert np.array_equal(b.cpu().numpy(), b_ref)
+                assert np.all(c_ref[:, lo:hi] == 0.0)
+                f_ref, pred_ref = svm.predict_ovo(K[lo:hi], c_ref, b_ref, 5)
+                clear = np.min(np.abs(f_ref), axis=1) > 1e-9
+                assert np.array_equal(pred.cpu().numpy()[clear], pred_ref[clear])

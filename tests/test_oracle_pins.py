@@ -344,3 +344,19 @@ def test_ovo_voting_vs_scikit_learn():
     f, pred = svm.predict_ovo(Km[60:, :60], coef, b, 3)
     assert np.allclose(f, svc.decision_function(Km[60:, :60]), atol=1e-6)
     assert np.array_equal(pred, svc.predict(Km[60:, :60]))
+
+
+def test_left_out_samples_equal_submatrix_training():
+    """A label of -1 leaves a sample out: training on the full matrix with
+    the held-out fold masked gives exactly the coefficients, biases and step
+    counts of training on the submatrix of the kept samples."""
+    from oracle import svm
+    Km, lab = _c1_dual_kernel(60)
+    labs = lab % 4
+    masked = labs.copy()
+    masked[20:40] = -1
+    keep = np.r_[0:20, 40:60]
+    c_full, b_full, it_full = svm.fit_ovo(Km, masked, 4, 10.0, 1e-6)
+    c_sub, b_sub, it_sub = svm.fit_ovo(Km[np.ix_(keep, keep)], labs[keep], 4, 10.0, 1e-6)
+    assert np.array_equal(c_full[:, keep], c_sub) and np.all(c_full[:, 20:40] == 0.0)
+    assert np.array_equal(b_full, b_sub) and np.array_equal(it_full, it_sub)
