@@ -155,18 +155,15 @@ __device__ void sweep_pair(const QkTask& t, int64_t i, int64_t j, BigSmem<T>& sm
     for (int w = 0; w < kThreads / 64; ++w) d2 += sm.red[w];
   }
   if (tid == 0) {
-    const double re = sm.e[0].x, im = sm.e[0].y;
-    const double mag2 = re * re + im * im;
-    const double lnk = mag2 > 0.0 ? log(mag2) + 2.0 * (double)expo * 0.69314718055994530942
-                                  : -INFINITY;
-    const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
+    const double lnk = qk_ln_kq(sm.e[0].x, sm.e[0].y, expo);
+    const double kq = exp(lnk);  // 0 for an amplitude of 0
     qk_pair_put(t, t.kq, t.ld_kq, i, j, kq);
     qk_pair_put(t, t.lnkq, t.ld_ln, i, j, lnk);
     if (t.fuse) {
       const double kc = exp(-t.gamma * d2);
       const double w = t.w_rows ? t.w_rows[i] : t.w;
       qk_pair_put(t, t.kc, t.ld_kc, i, j, kc);
-      qk_pair_put(t, t.k, t.ld_k, i, j, w * kq + (1.0 - w) * kc);
+      qk_pair_put(t, t.k, t.ld_k, i, j, qk_mix(w, kq, kc));
     }
   }
   __syncthreads();  // E and the reduction slots are reused by the next pair

@@ -199,12 +199,9 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, SweepSmem<R, T>& sm,
   const int bit = r * kTile + c;
   // refinement pass: write only the pairs the reduced pass marked
   if (mask_in && !((mask_in[bit >> 5] >> (bit & 31)) & 1u)) return;
-  const double re = (double)er[0][0], im = (double)ei[0][0];
-  const double mag2 = re * re + im * im;
-  const double lnk = mag2 > 0.0 ? log(mag2) + 2.0 * (double)expo * 0.69314718055994530942
-                                : -INFINITY;
+  const double lnk = qk_ln_kq((double)er[0][0], (double)ei[0][0], expo);
   if (mask_out && lnk > ln_tau) atomicOr(&mask_out[bit >> 5], 1u << (bit & 31));
-  const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
+  const double kq = exp(lnk);  // 0 for an amplitude of 0
   auto put = [&](double* p, int64_t ld, double v) {
     if (!p) return;
     p[i * ld + j] = v;
@@ -213,17 +210,10 @@ __device__ void run_tile(const QkTask& t, int ti, int tj, SweepSmem<R, T>& sm,
   put(t.kq, t.ld_kq, kq);
   put(t.lnkq, t.ld_ln, lnk);
   if (t.fuse) {
-    const double* xr = t.xr + i * t.ld_xr;
-    const double* xc = t.xc + j * t.ld_xc;
-    double d2 = 0.0;
-    for (int f = 0; f < nq; ++f) {
-      double df = xr[f] - xc[f];
-      d2 += df * df;
-    }
-    const double kc = exp(-t.gamma * d2);
+    const double kc = exp(-t.gamma * qk_sq_dist(t.xr + i * t.ld_xr, t.xc + j * t.ld_xc, nq));
     const double w = t.w_rows ? t.w_rows[i] : t.w;
     put(t.kc, t.ld_kc, kc);
-    put(t.k, t.ld_k, w * kq + (1.0 - w) * kc);
+    put(t.k, t.ld_k, qk_mix(w, kq, kc));
   }
 }
 
@@ -436,10 +426,8 @@ __device__ void refine_tile_pairs(const QkTask& t, int ti, int tj, const uint32_
     }
     // epilogue on lane (0, 0) of the pair, as in the tile kernel
     if (have && l == 0) {
-      const double mag2 = er * er + ei * ei;
-      const double lnk = mag2 > 0.0 ? log(mag2) + 2.0 * (double)expo * 0.69314718055994530942
-                                    : -INFINITY;
-      const double kq = mag2 > 0.0 ? exp(lnk) : 0.0;
+      const double lnk = qk_ln_kq(er, ei, expo);
+      const double kq = exp(lnk);  // 0 for an amplitude of 0
       auto put = [&](double* ptr, int64_t ld, double v) {
         if (!ptr) return;
         ptr[i * ld + j] = v;
@@ -448,17 +436,10 @@ __device__ void refine_tile_pairs(const QkTask& t, int ti, int tj, const uint32_
       put(t.kq, t.ld_kq, kq);
       put(t.lnkq, t.ld_ln, lnk);
       if (t.fuse) {
-        const double* xr = t.xr + i * t.ld_xr;
-        const double* xc = t.xc + j * t.ld_xc;
-        double d2 = 0.0;
-        for (int f = 0; f < nq; ++f) {
-          double df = xr[f] - xc[f];
-          d2 += df * df;
-        }
-        const double kc = exp(-t.gamma * d2);
+        const double kc = exp(-t.gamma * qk_sq_dist(t.xr + i * t.ld_xr, t.xc + j * t.ld_xc, nq));
         const double w = t.w_rows ? t.w_rows[i] : t.w;
         put(t.kc, t.ld_kc, kc);
-        put(t.k, t.ld_k, w * kq + (1.0 - w) * kc);
+        put(t.k, t.ld_k, qk_mix(w, kq, kc));
       }
     }
     wave_lds_sync();
