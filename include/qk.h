@@ -160,6 +160,16 @@ QK_API qk_status qk_mps_info(const qk_mps_batch* b, int64_t* n_samples,
 /* Copies the realized bond table (n_samples x (n_qubits+1) int32) to host. */
 QK_API qk_status qk_mps_chi(const qk_mps_batch* b, int32_t* chi_host);
 
+/* Copies the per-sample discarded weight (n_samples FP64, host) of the
+ * build: the sum over the sample's truncations of sum_{j >= keep} s_j^2 /
+ * sum_j s_j^2, the singular values s of each merged two-site matrix in
+ * descending order (Section III's bond truncation; cutoff and chi_max decide
+ * keep). The state's squared error against the untruncated circuit state is
+ * bounded by about twice this sum, so it says how far a truncating build is
+ * from the exact kernel. 0 for batches from qk_mps_import and for samples no
+ * truncation touched beyond rounding noise. Synchronises the build stream. */
+QK_API qk_status qk_mps_discarded(const qk_mps_batch* b, double* disc_host);
+
 /* Frees the batch after waiting for all work on the device (sweeps on any
  * stream may read it). NULL is accepted. */
 QK_API qk_status qk_mps_release(qk_mps_batch* b);

@@ -185,7 +185,7 @@ template <int W>
 __global__ __launch_bounds__(64) void mps_build_kernel(
     const double* __restrict__ x, int64_t ld_x, int64_t N, int nq, int n_layers,
     int chi_max, int entangle, double cutoff, double2* __restrict__ t64,
-    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status) {
+    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status, double* __restrict__ disc_out) {
   constexpr int D = 2 * W;
   __shared__ BuildSmem<W> sm;
   const int64_t i = blockIdx.x;
@@ -214,6 +214,7 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
 
   const double inv_sqrt2 = 0.70710678118654752440;
   int chi_seen = 1;
+  double disc = 0.0;  // discarded weight, summed over the truncations (lane 0)
   for (int layer = 0; layer < n_layers; ++layer) {
     // 1. single-qubit layer: A'[0] = e^{-ix}(A0 + A1)/sqrt2, A'[1] = e^{ix}(A0 - A1)/sqrt2
     for (int64_t e = lane; e < (int64_t)nq * TT; e += 64) {
@@ -318,6 +319,15 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
         norm2 = 0.0;
         for (int j = 0; j < keep; ++j) norm2 += sm.S[sm.perm[j]] * sm.S[sm.perm[j]];
       }
+      if (lane == 0) {  // weight of the dropped singular values, in rank order
+        double tot = 0.0, tail = 0.0;
+        for (int j = 0; j < XCe; ++j) {
+          const double s2 = sm.S[sm.perm[j]] * sm.S[sm.perm[j]];
+          tot += s2;
+          if (j >= keep) tail += s2;
+        }
+        if (tot > 0.0) disc += tail / tot;
+      }
       const double inv_norm = norm2 > 0.0 ? 1.0 / sqrt(norm2) : 0.0;
       if (keep > chi_seen) chi_seen = keep;
       // Left factor Lf (R x keep) and right factor Rf (keep x C) of Theta:
@@ -359,7 +369,10 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
       __syncthreads();
     }
   }
-  if (lane == 0) atomicMax(status + 1, chi_seen);
+  if (lane == 0) {
+    atomicMax(status + 1, chi_seen);
+    if (disc_out) disc_out[i] = disc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -408,7 +421,8 @@ template <int W>
 __global__ __launch_bounds__(BuildWgShape<W>::kThreads) void mps_build_wg_kernel(
     const double* __restrict__ x, int64_t ld_x, int64_t N, int nq, int n_layers,
     int chi_max, int entangle, double cutoff, double2* __restrict__ t64,
-    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status, double2* __restrict__ ws) {
+    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status, double2* __restrict__ ws,
+    double* __restrict__ disc_out) {
   using Sh = BuildWgShape<W>;
   constexpr int D = Sh::D, kR = Sh::kRows, kH = Sh::kHalf, kP = Sh::kPitch;
   constexpr int T = W, TT = W * W, slot = 2 * TT;
@@ -434,6 +448,7 @@ __global__ __launch_bounds__(BuildWgShape<W>::kThreads) void mps_build_wg_kernel
 
   const double inv_sqrt2 = 0.70710678118654752440;
   int chi_seen = 1;
+  double disc = 0.0;  // discarded weight, summed over the truncations (thread 0)
   for (int layer = 0; layer < n_layers; ++layer) {
     // 1. single-qubit layer on the realized blocks:
     //    A'[0] = e^{-ix}(A0 + A1)/sqrt2, A'[1] = e^{ix}(A0 - A1)/sqrt2
@@ -633,6 +648,15 @@ __global__ __launch_bounds__(BuildWgShape<W>::kThreads) void mps_build_wg_kernel
         norm2 = 0.0;
         for (int j = 0; j < keep; ++j) norm2 += sm.sv[sm.perm[j]] * sm.sv[sm.perm[j]];
       }
+      if (tid == 0) {  // weight of the dropped singular values, in rank order
+        double tot = 0.0, tail = 0.0;
+        for (int j = 0; j < C; ++j) {
+          const double s2 = sm.sv[sm.perm[j]] * sm.sv[sm.perm[j]];
+          tot += s2;
+          if (j >= keep) tail += s2;
+        }
+        if (tot > 0.0) disc += tail / tot;
+      }
       const double inv_norm = norm2 > 0.0 ? 1.0 / sqrt(norm2) : 0.0;
       if (keep > chi_seen) chi_seen = keep;
       // kept left singular vectors U[:, j] = X[:, perm j] / S to LDS
@@ -693,7 +717,10 @@ __global__ __launch_bounds__(BuildWgShape<W>::kThreads) void mps_build_wg_kernel
       __syncthreads();
     }
   }
-  if (tid == 0) atomicMax(status + 1, chi_seen);
+  if (tid == 0) {
+    atomicMax(status + 1, chi_seen);
+    if (disc_out) disc_out[i] = disc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -801,7 +828,7 @@ __device__ bool jacobi_rows(double2 (&xr)[D], double2 (&vr)[D], double floor2) {
 template <int W, int NC>
 __device__ int b8_factor(double2 (&xr)[2 * W], double2 (&vr)[2 * W], double floor2, int r,
                          int XC, int cl, int cr, bool tr, bool l2r, int chi_max, double cutoff,
-                         double2* Lo, double2* Ro, int& noconv, int& over) {
+                         double2* Lo, double2* Ro, int& noconv, int& over, double& dw) {
   constexpr int D = 2 * W, TT = W * W;
   const bool conv = jacobi_rows<D, NC>(xr, vr, floor2);
   noconv |= conv ? 0 : 1;
@@ -847,6 +874,16 @@ __device__ int b8_factor(double2 (&xr)[2 * W], double2 (&vr)[2 * W], double floo
     norm2 = 0.0;
 #pragma unroll
     for (int q = 0; q < (NC < W ? NC : W); ++q) norm2 += s_at[q] * s_at[q];
+  }
+  {  // weight of the dropped singular values (same value in every lane)
+    double tot = 0.0, tail = 0.0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const double s2 = s_at[q] * s_at[q];
+      tot += s2;
+      if (q >= keep) tail += s2;
+    }
+    if (tot > 0.0) dw += tail / tot;
   }
   const double inv_norm = norm2 > 0.0 ? 1.0 / sqrt(norm2) : 0.0;
   const int R = 2 * cl, C = 2 * cr;
@@ -964,6 +1001,7 @@ __global__ __launch_bounds__(64) void mps_build8_kernel(B8Table tab, int nq, int
   };
 
   int chi_seen = 1, noconv = 0, over = 0;
+  double disc = 0.0;  // discarded weight, summed over the truncations
   for (int layer = 0; layer < n_layers; ++layer) {
     const bool l2r = (layer % 2) == 0;
     // bond dimension before this layer's step rewrote it (all 1 before the
@@ -1051,13 +1089,13 @@ __global__ __launch_bounds__(64) void mps_build8_kernel(B8Table tab, int nq, int
       const double floor2 = 1e-30 * fro;
       int keep;
       if (nc <= 2)
-        keep = b8_factor<W, 2>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over);
+        keep = b8_factor<W, 2>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over, disc);
       else if (nc <= 4 || D <= 4)
-        keep = b8_factor<W, (D < 4 ? D : 4)>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over);
+        keep = b8_factor<W, (D < 4 ? D : 4)>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over, disc);
       else if (nc <= 6 || D <= 6)
-        keep = b8_factor<W, (D < 6 ? D : 6)>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over);
+        keep = b8_factor<W, (D < 6 ? D : 6)>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over, disc);
       else
-        keep = b8_factor<W, D>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over);
+        keep = b8_factor<W, D>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over, disc);
       if (keep > chi_seen) chi_seen = keep;
       wave_lds_sync();
       // The finished site goes to memory (the carried one too on the layer's
@@ -1116,6 +1154,7 @@ __global__ __launch_bounds__(64) void mps_build8_kernel(B8Table tab, int nq, int
     if (noconv) atomicOr(status, QK_FLAG_NOCONV);
     if (over) atomicOr(status, QK_FLAG_CHI_OVER);
     atomicMax(status + 1, chi_seen);
+    if (P.disc) P.disc[i] = disc;
   }
 }
 
@@ -1139,10 +1178,10 @@ __global__ void pack32_kernel(const double2* __restrict__ a, float* __restrict__
 hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
                            int n_layers, int chi_max, int entangle,
                            double cutoff, int chi_ws, int T, double2* t64,
-                           int32_t* chi, int32_t* status, hipStream_t s) {
+                           int32_t* chi, int32_t* status, double* disc, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (nq >= 2 && (T == 1 || T == 2 || T == 4)) {
-    const QkBuildPart part{x, ld_x, n, t64, chi, status};
+    const QkBuildPart part{x, ld_x, n, t64, chi, status, disc};
     return qk_launch_build_many(&part, 1, nq, n_layers, chi_max, entangle, cutoff, chi_ws, T, s);
   }
   // bond bounds of 32 and 64: one workgroup per sample, Theta of each
@@ -1155,11 +1194,11 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
     if (T == 32)
       hipLaunchKernelGGL(mps_build_wg_kernel<32>, dim3((unsigned)n),
                          dim3(BuildWgShape<32>::kThreads), 0, s, x, ld_x, n, nq, n_layers,
-                         chi_max, entangle, cutoff, t64, chi, status, ws);
+                         chi_max, entangle, cutoff, t64, chi, status, ws, disc);
     else
       hipLaunchKernelGGL(mps_build_wg_kernel<64>, dim3((unsigned)n),
                          dim3(BuildWgShape<64>::kThreads), 0, s, x, ld_x, n, nq, n_layers,
-                         chi_max, entangle, cutoff, t64, chi, status, ws);
+                         chi_max, entangle, cutoff, t64, chi, status, ws, disc);
     const hipError_t e = hipGetLastError();
     (void)hipFreeAsync(ws, s);  // stream-ordered: after the build
     return e;
@@ -1169,7 +1208,7 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
   case WV:                                                                    \
     hipLaunchKernelGGL(mps_build_kernel<WV>, grid, block, 0, s, x, ld_x, n,   \
                        nq, n_layers, chi_max, entangle, cutoff, t64, chi,     \
-                       status);                                               \
+                       status, disc);                                         \
     break;
   switch (T) {
     QK_BUILD_CASE(1)  // a single qubit (every multi-qubit bound <= 4 takes the 8-sample kernel)
@@ -1191,7 +1230,7 @@ hipError_t qk_launch_build_many(const QkBuildPart* parts, int n_parts, int nq, i
     for (int k = 0; k < n_parts; ++k) {
       const QkBuildPart& p = parts[k];
       const hipError_t e = qk_launch_build(p.x, p.ld_x, p.n, nq, n_layers, chi_max, entangle,
-                                           cutoff, chi_ws, T, p.t64, p.chi, p.status, s);
+                                           cutoff, chi_ws, T, p.t64, p.chi, p.status, p.disc, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -30,6 +30,8 @@ void free_batch_memory(qk_mps_batch* b, hipStream_t s) {
   if (b->t32) (void)hipFreeAsync(b->t32, s);
   if (b->chi) (void)hipFreeAsync(b->chi, s);
   if (b->status) (void)hipFreeAsync(b->status, s);
+  if (b->disc) (void)hipFreeAsync(b->disc, s);
+  b->disc = nullptr;
   b->t64 = nullptr;
   b->t32 = nullptr;
   b->chi = nullptr;
@@ -116,6 +118,11 @@ qk_status alloc_batch(const qk_circuit_desc* c, int64_t n, int T, uint32_t store
     return cleanup(QK_ERR_OUT_OF_MEMORY, "device allocation of the status word failed");
   if (hipMemsetAsync(b->status, 0, 2 * sizeof(int32_t), s) != hipSuccess)
     return cleanup(QK_ERR_HIP, "status reset failed");
+  // discarded weight per sample: written by the build, zero for imports
+  if (hipMallocAsync((void**)&b->disc, std::max<int64_t>(n, 1) * sizeof(double), s) != hipSuccess)
+    return cleanup(QK_ERR_OUT_OF_MEMORY, "device allocation of the discarded weights failed");
+  if (hipMemsetAsync(b->disc, 0, std::max<int64_t>(n, 1) * sizeof(double), s) != hipSuccess)
+    return cleanup(QK_ERR_HIP, "discarded-weight reset failed");
   if (hipEventCreateWithFlags(&b->ready, hipEventDisableTiming) != hipSuccess)
     return cleanup(QK_ERR_HIP, "event creation failed");
   b->bytes = elems * (int64_t)sizeof(double2) +
@@ -434,7 +441,7 @@ qk_status qk_mps_build(const qk_circuit_desc* c, const double* x_dev,
   b->chi_ws = ws;
   hipError_t e = qk_launch_build(x_dev, ld_x, n_samples, c->n_qubits, c->n_layers,
                                  c->chi_max, c->entangle, c->cutoff_rel, ws, T,
-                                 b->t64, b->chi, b->status, s);
+                                 b->t64, b->chi, b->status, b->disc, s);
   if (e != hipSuccess) {
     qk_mps_release(b);
     return hip_fail(e, "build launch");
@@ -482,7 +489,8 @@ qk_status qk_mps_build_many(const qk_circuit_desc* c, int32_t n_inputs,
       return st;
     }
     b[k]->chi_ws = ws;
-    parts[k] = QkBuildPart{x_devs[k], ld_x[k], n_samples[k], b[k]->t64, b[k]->chi, b[k]->status};
+    parts[k] = QkBuildPart{x_devs[k], ld_x[k], n_samples[k], b[k]->t64, b[k]->chi, b[k]->status,
+                           b[k]->disc};
   }
   hipError_t e = qk_launch_build_many(parts, n_inputs, c->n_qubits, c->n_layers, c->chi_max,
                                       c->entangle, c->cutoff_rel, ws, T, s);
@@ -576,6 +584,14 @@ qk_status qk_mps_chi(const qk_mps_batch* b, int32_t* chi_host) {
   QK_HIP(hipMemcpy(chi_host, b->chi, b->n * (b->nq + 1) * sizeof(int32_t),
                    hipMemcpyDeviceToHost),
          "bond table read");
+  return QK_OK;
+}
+
+qk_status qk_mps_discarded(const qk_mps_batch* b, double* disc_host) {
+  if (!b || !disc_host) return fail(QK_ERR_INVALID_ARG, "NULL argument");
+  QK_HIP(hipEventSynchronize(b->ready), "batch synchronisation");
+  QK_HIP(hipMemcpy(disc_host, b->disc, b->n * sizeof(double), hipMemcpyDeviceToHost),
+         "discarded-weight read");
   return QK_OK;
 }
 

@@ -30,6 +30,7 @@ struct qk_mps_batch {
   float* t32 = nullptr;   // [nq][n][2][T][T] complex FP32, kQkPackFloats floats each
   int32_t* chi = nullptr; // [n][nq+1] realized bond dimensions
   int32_t* status = nullptr;  // [0] flag bits, [1] max realized chi
+  double* disc = nullptr;     // [n] discarded weight per sample (0 when nothing is cut)
   hipStream_t stream = nullptr;
   hipEvent_t ready = nullptr;
   int64_t bytes = 0;
@@ -46,7 +47,7 @@ void qk_mps_release_nosync(qk_mps_batch* b, hipStream_t s);
 hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
                            int n_layers, int chi_max, int entangle,
                            double cutoff, int chi_ws, int T, double2* t64,
-                           int32_t* chi, int32_t* status, hipStream_t s);
+                           int32_t* chi, int32_t* status, double* disc, hipStream_t s);
 // Several feature matrices of one circuit built in one launch (bond bound
 // up to 4): one part per batch.
 struct QkBuildPart {
@@ -56,6 +57,7 @@ struct QkBuildPart {
   double2* t64;
   int32_t* chi;
   int32_t* status;
+  double* disc;  // per-sample discarded weight (may be NULL)
 };
 constexpr int QK_MAX_BUILD_PARTS = 8;
 hipError_t qk_launch_build_many(const QkBuildPart* parts, int n_parts, int nq, int n_layers,

@@ -75,6 +75,8 @@ _lib.qk_mps_info.argtypes = [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                              C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                              C.POINTER(C.c_int64)]
 _lib.qk_mps_chi.argtypes = [_P, _P]
+_lib.qk_mps_discarded.argtypes = [_P, _P]
+_lib.qk_mps_discarded.restype = C.c_int
 _lib.qk_mps_release.argtypes = [_P]
 _lib.qk_overlap_gram.argtypes = [_P, _P, C.c_int32, C.c_int, _P, C.c_int64, _P, C.c_int64,
                                  C.POINTER(qk_fuse_desc), _P]
@@ -140,7 +142,7 @@ EXPORTED = ["qk_server_create", "qk_server_load_support", "qk_server_submit",
             "qk_server_poll", "qk_server_set_model", "qk_server_poll_decision", "qk_server_wait", "qk_server_cancel", "qk_server_request_times",
             "qk_server_stats", "qk_server_destroy",
             "qk_mps_build", "qk_mps_build_many", "qk_mps_import", "qk_mps_info", "qk_mps_chi",
-            "qk_mps_release", "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
+            "qk_mps_discarded", "qk_mps_release", "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
             "qk_svm_decision", "qk_svm_fit_ovo", "qk_svm_predict_ovo", "qk_resolve_precision", "qk_set_refine_threshold", "qk_autotune",
             "qk_tune_export", "qk_tune_import", "qk_status_string",
             "qk_last_error", "qk_set_launch_timing", "qk_last_launch_ms"]
@@ -262,6 +264,14 @@ def qk_mps_chi(batch: MpsBatch) -> np.ndarray:
     info = qk_mps_info(batch)
     out = np.empty((info["n_samples"], info["n_qubits"] + 1), dtype=np.int32)
     _check(_lib.qk_mps_chi(batch.handle, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def qk_mps_discarded(batch: MpsBatch) -> np.ndarray:
+    """Per-sample discarded weight of the build (zeros for imported batches)."""
+    info = qk_mps_info(batch)
+    out = np.empty(info["n_samples"], dtype=np.float64)
+    _check(_lib.qk_mps_discarded(batch.handle, out.ctypes.data_as(C.c_void_p)))
     return out
 
 

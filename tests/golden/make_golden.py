@@ -74,8 +74,9 @@ def main():
 
 def s1_replay():
     x, _, _ = config_inputs("S1", n_train=3, n_test=0)
-    built = [mps.build_mps(xi, 8, 64, 1e-10) for xi in x]
+    built = [mps.build_mps(xi, 8, 64, 1e-10, return_discarded=True) for xi in x]
     chi = [list(map(int, b[1])) for b in built]
+    discarded = [float(b[2]) for b in built]
     P = mps.pad_batch([b[0] for b in built])
     _, LN = mps.gram(P, P, symmetric=True)
     with open(os.path.join(HERE, "s1_replay_3.json"), "w") as f:
@@ -84,6 +85,7 @@ def s1_replay():
             "workload": "images seed 6, first 3 training samples, d=784, L=8, chi_max=64, "
                         "cutoff 1e-10",
             "chi": chi, "lnkq": LN.tolist(),
+            "discarded": discarded,
         }, f)
 
 

@@ -120,9 +120,10 @@ def test_chi64_sweep_784_sites_sampled():
 def test_truncating_regime_784_qubits_vs_replay():
     """The truncating regime at full size: 3 images of 784 features, 8 layers,
     chi_max 64 (bonds would reach 2^8 without the cap). The device build's
-    bond tables equal the oracle's step-by-step replay, and its complex-FP64
-    overlaps meet the stated log gate against the replay's (fixture written
-    by tests/golden/make_golden.py, which calls only the oracle)."""
+    bond tables equal the oracle's step-by-step replay, its complex-FP64
+    overlaps meet the stated log gate against the replay's, and its
+    per-sample discarded weights equal the replay's (fixture written by
+    tests/golden/make_golden.py, which calls only the oracle)."""
     import paper_2602_01330_amd.qk as qk
     fx = json.load(open(os.path.join(GOLDEN, "s1_replay_3.json")))
     x, _, _ = config_inputs("S1", n_train=3, n_test=0)
@@ -140,3 +141,6 @@ def test_truncating_regime_784_qubits_vs_replay():
     print(f"[S1 full] max |d lnK| vs replay = {lmax:.3e}", flush=True)
     assert ok, lmax
     assert np.abs(np.diag(ln)).max() < 1e-8
+    disc = qk.qk_mps_discarded(b)
+    print(f"[S1 full] discarded weight {disc} (replay {fx['discarded']})", flush=True)
+    assert np.allclose(disc, fx["discarded"], rtol=1e-6, atol=1e-15)

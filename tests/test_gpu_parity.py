@@ -551,3 +551,36 @@ def test_svm_cross_validation_on_resident_kernels(qk):
                 f_ref, pred_ref = svm.predict_ovo(K[lo:hi], c_ref, b_ref, 5)
                 clear = np.min(np.abs(f_ref), axis=1) > 1e-9
                 assert np.array_equal(pred.cpu().numpy()[clear], pred_ref[clear])
+
+
+@pytest.mark.parametrize("d,L,chi_max", [(10, 3, 4), (10, 4, 8), (12, 5, 16), (12, 6, 32),
+                                         (14, 8, 64), (16, 2, 64)])
+def test_discarded_weight_per_build_kernel(qk, d, L, chi_max):
+    """The device build's per-sample discarded weight (each build kernel:
+    eight samples per wave at bond bound 4, one wave per sample at 8 and 16,
+    one workgroup per sample at 32 and 64) equals the oracle's TEBD replay;
+    a circuit that needs no truncation (L = 2, bonds <= 4) discards nothing
+    beyond rounding. Where truncation happens, the device overlaps stay
+    within the discarded-weight bound of the exact (statevector) kernel:
+    |K' - K| <= 2 (sqrt(2 w_i) + sqrt(2 w_j))."""
+    from oracle import statevector as sv
+    X, _ = gen_clusters(6, d, 900 + d + L)
+    print(f"[discarded] d={d} L={L} chi_max={chi_max}", flush=True)
+    xd = dev(X)
+    b = qk.qk_mps_build(xd, L, chi_max, 1e-10)
+    kq = torch.full((6, 6), float("nan"), dtype=torch.float64, device="cuda")
+    qk.qk_overlap_gram(b, b, True, "fp64", kq, None)
+    torch.cuda.synchronize()
+    disc = qk.qk_mps_discarded(b)
+    ref = np.array([mps.build_mps(x, L, chi_max, 1e-10, return_discarded=True)[2] for x in X])
+    print(f"[discarded] device {disc} oracle {ref}", flush=True)
+    assert np.allclose(disc, ref, rtol=1e-6, atol=1e-15)
+    if L == 2:
+        assert disc.max() < 1e-20
+        return
+    assert disc.max() > 1e-9  # truncation really happened
+    exact = sv.gram(X, X, L)
+    eps = np.sqrt(2 * disc)
+    bound = 2 * (eps[:, None] + eps[None, :]) + 1e-12
+    assert np.all(np.abs(kq.cpu().numpy() - exact) <= bound)
+    b.close()
