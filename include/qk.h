@@ -287,6 +287,36 @@ QK_API qk_status qk_svm_decision(const double* k_dev, int64_t m, int64_t n, int6
                                  void* hip_stream);
 
 /*
+ * qk_pathsum_gram -- the quantum kernel (Eqs. (7), (10)) of one- and
+ * two-layer encoding circuits (Eq. (6)) by exact path-sum evaluation, with
+ * no MPS build and no truncation: every gate but H is diagonal, so the
+ * overlap is a sum over computational-basis histories, evaluated as a chain
+ * over the qubits of 2^(2L-1) states (2 at L = 1, 8 at L = 2) whose bond
+ * factor splits into one 2 x 2 factor per history line. Complex FP64, one
+ * pair per lane; exact power-of-two rescaling, so ln K_q is exact in range.
+ * Equal, to rounding, to the MPS route wherever that route does not
+ * truncate (chi_max >= 2^L); it costs about 150 FP64 operations per pair and
+ * qubit at L = 2 against 2048 for the bond-4 sweep.
+ *   x_rows_dev  m x d features (leading dimension ld_xr >= d); x_cols_dev
+ *               n x d. symmetric = 1 needs the same pointer, m = n and
+ *               ld_xr = ld_xc, contracts the upper triangle and mirrors it.
+ *   n_layers    1 or 2 (QK_ERR_UNSUPPORTED otherwise); entangle 0 drops the
+ *               RZZ chain.
+ *   kq_dev, lnkq_dev  optional m x n outputs (leading dimensions >= n).
+ *   fuse        optional RBF (Eq. (3)) and mix (Eq. (11)) outputs as in
+ *               qk_overlap_gram; its x fields are ignored (the RBF uses
+ *               x_rows_dev / x_cols_dev).
+ * Device scratch: (m + n) d 32 bytes of tables (m d when symmetric) from the
+ * stream-ordered pool. Features must be finite. Errors: INVALID_ARG,
+ * UNSUPPORTED, OUT_OF_MEMORY, HIP.
+ */
+QK_API qk_status qk_pathsum_gram(const double* x_rows_dev, int64_t m, int64_t ld_xr,
+                                 const double* x_cols_dev, int64_t n, int64_t ld_xc, int32_t d,
+                                 int32_t n_layers, int32_t entangle, int32_t symmetric,
+                                 double* kq_dev, int64_t ld_kq, double* lnkq_dev, int64_t ld_ln,
+                                 const qk_fuse_desc* fuse, void* hip_stream);
+
+/*
  * qk_svm_fit_ovo -- trains the SVMs of Eqs. (1)-(2) on a precomputed kernel
  * matrix, one binary problem per pair of classes (one-against-one, Section
  * II-B), all problems in one launch (one workgroup each).

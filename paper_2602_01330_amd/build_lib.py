@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libqk.so")
 
 SOURCES = ["qk_api.cpp", "tune.cpp", "server.cpp", "build.hip", "sweep_valu.hip",
            "sweep_mfma.hip", "sweep_big.hip", "sweep_wide.hip", "classical.hip",
-           "svm.hip"]
+           "svm.hip", "pathsum.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -826,6 +826,56 @@ qk_status qk_svm_decision(const double* k_dev, int64_t m, int64_t n, int64_t ld_
   return QK_OK;
 }
 
+qk_status qk_pathsum_gram(const double* x_rows_dev, int64_t m, int64_t ld_xr,
+                          const double* x_cols_dev, int64_t n, int64_t ld_xc, int32_t d,
+                          int32_t n_layers, int32_t entangle, int32_t symmetric, double* kq_dev,
+                          int64_t ld_kq, double* lnkq_dev, int64_t ld_ln,
+                          const qk_fuse_desc* fuse, void* hip_stream) {
+  if (m < 0 || n < 0 || m > INT32_MAX || n > INT32_MAX)
+    return fail(QK_ERR_INVALID_ARG, "sample counts must be in [0, 2^31 - 1]");
+  if (d < 1) return fail(QK_ERR_INVALID_ARG, "d < 1");
+  if (n_layers != 1 && n_layers != 2)
+    return fail(QK_ERR_UNSUPPORTED, "the path-sum evaluator covers one and two layers");
+  if (symmetric && (m != n || x_rows_dev != x_cols_dev || ld_xr != ld_xc))
+    return fail(QK_ERR_INVALID_ARG, "symmetric mode needs the same rows and columns");
+  if ((m > 0 && !x_rows_dev) || (n > 0 && !x_cols_dev))
+    return fail(QK_ERR_INVALID_ARG, "features are NULL");
+  if (ld_xr < d || ld_xc < d) return fail(QK_ERR_INVALID_ARG, "feature leading dimension < d");
+  if ((kq_dev && ld_kq < n) || (lnkq_dev && ld_ln < n))
+    return fail(QK_ERR_INVALID_ARG, "output leading dimension < n");
+  qk_fuse_desc f{};
+  if (fuse) {
+    f = *fuse;
+    f.x_rows_dev = x_rows_dev;  // the RBF uses the same features
+    f.ld_xr = ld_xr;
+    f.x_cols_dev = x_cols_dev;
+    f.ld_xc = ld_xc;
+    if (!std::isfinite(f.gamma)) return fail(QK_ERR_INVALID_ARG, "gamma must be finite");
+    if (!f.w_rows_dev && !(f.w >= 0.0 && f.w <= 1.0))
+      return fail(QK_ERR_INVALID_ARG, "w must be in [0, 1]");
+    if ((f.kc_dev && f.ld_kc < n) || (f.k_dev && f.ld_k < n))
+      return fail(QK_ERR_INVALID_ARG, "fused output leading dimension < n");
+  }
+  if (!kq_dev && !lnkq_dev && !(fuse && (f.kc_dev || f.k_dev)))
+    return fail(QK_ERR_INVALID_ARG, "no output requested");
+  if (m == 0 || n == 0) return QK_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int64_t rows_tab = m * (int64_t)d, cols_tab = symmetric ? 0 : n * (int64_t)d;
+  double4* tab = nullptr;
+  QK_HIP(hipMallocAsync((void**)&tab, (rows_tab + cols_tab) * sizeof(double4), s),
+         "path-sum table allocation");
+  double4* tc = symmetric ? tab : tab + rows_tab;
+  hipError_t e = qk_launch_pathsum_table(x_rows_dev, m, ld_xr, d, n_layers, entangle, tab, s);
+  if (e == hipSuccess && !symmetric)
+    e = qk_launch_pathsum_table(x_cols_dev, n, ld_xc, d, n_layers, entangle, tc, s);
+  if (e == hipSuccess)
+    e = qk_launch_pathsum(tab, m, tc, n, d, n_layers, symmetric, kq_dev, ld_kq, lnkq_dev, ld_ln,
+                          fuse ? &f : nullptr, s);
+  (void)hipFreeAsync(tab, s);
+  if (e != hipSuccess) return hip_fail(e, "path-sum launch");
+  return QK_OK;
+}
+
 qk_status qk_svm_fit_ovo(const double* k_dev, int64_t n, int64_t ld_k, const int32_t* labels_host,
                          int32_t n_classes, double C, double eps, int64_t max_iter,
                          double* coef_dev, int64_t ld_coef, double* intercept_dev,

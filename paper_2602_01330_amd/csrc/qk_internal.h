@@ -201,6 +201,15 @@ hipError_t qk_launch_mix(const double* kq, int64_t ld_kq, const double* kc,
                          double* k, int64_t ld_k, hipStream_t s);
 hipError_t qk_launch_svm_decision(const double* k, int64_t m, int64_t n, int64_t ld_k,
                                   const double* coef, double b, double* f, hipStream_t s);
+// Path-sum evaluation for one- and two-layer circuits (pathsum.hip): the
+// per-sample tables (site-major, n x d entries of (q, p)), then one pair per
+// lane over 16 x 16 tiles, the upper triangle only when symmetric.
+hipError_t qk_launch_pathsum_table(const double* x, int64_t n, int64_t ld_x, int d, int n_layers,
+                                   int entangle, double4* tab, hipStream_t s);
+hipError_t qk_launch_pathsum(const double4* tr, int64_t m, const double4* tc, int64_t n, int d,
+                             int n_layers, int symmetric, double* kq, int64_t ld_kq,
+                             double* lnkq, int64_t ld_ln, const qk_fuse_desc* fuse,
+                             hipStream_t s);
 // SVM training by SMO, one workgroup per binary problem p: samples
 // idx[off[p] .. off[p+1]) (global rows of the symmetric kernel k), labels
 // y = +1/-1 alongside; alpha / grad / diag are scratch of the same length;

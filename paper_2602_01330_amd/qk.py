@@ -87,6 +87,10 @@ _lib.qk_dual_mix.argtypes = [_P, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int64,
                              _P, C.c_int64, _P]
 _lib.qk_svm_decision.argtypes = [_P, C.c_int64, C.c_int64, C.c_int64, _P, C.c_double, _P, _P]
 _lib.qk_svm_decision.restype = C.c_int
+_lib.qk_pathsum_gram.argtypes = [_P, C.c_int64, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int32,
+                                 C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64,
+                                 _P, _P]
+_lib.qk_pathsum_gram.restype = C.c_int
 _lib.qk_svm_fit_ovo.argtypes = [_P, C.c_int64, C.c_int64, _P, C.c_int32, C.c_double, C.c_double,
                                 C.c_int64, _P, C.c_int64, _P, _P, _P]
 _lib.qk_svm_fit_ovo.restype = C.c_int
@@ -143,7 +147,7 @@ EXPORTED = ["qk_server_create", "qk_server_load_support", "qk_server_submit",
             "qk_server_stats", "qk_server_destroy",
             "qk_mps_build", "qk_mps_build_many", "qk_mps_import", "qk_mps_info", "qk_mps_chi",
             "qk_mps_discarded", "qk_mps_release", "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
-            "qk_svm_decision", "qk_svm_fit_ovo", "qk_svm_predict_ovo", "qk_resolve_precision", "qk_set_refine_threshold", "qk_autotune",
+            "qk_svm_decision", "qk_pathsum_gram", "qk_svm_fit_ovo", "qk_svm_predict_ovo", "qk_resolve_precision", "qk_set_refine_threshold", "qk_autotune",
             "qk_tune_export", "qk_tune_import", "qk_status_string",
             "qk_last_error", "qk_set_launch_timing", "qk_last_launch_ms"]
 
@@ -305,6 +309,26 @@ def qk_overlap_gram(rows: MpsBatch, cols: MpsBatch, symmetric=False, prec="auto"
     lp, ldl = _opt(lnkq, "lnkq")
     f = _fuse(fuse)
     _check(_lib.qk_overlap_gram(rows.handle, cols.handle, 1 if symmetric else 0, p, kp, ldk,
+                                lp, ldl, C.byref(f) if f is not None else None,
+                                _stream(stream)))
+    return kq, lnkq
+
+
+def qk_pathsum_gram(x_rows, x_cols=None, n_layers=2, entangle=True, kq=None, lnkq=None,
+                    fuse=None, stream=None):
+    """Exact path-sum K_q of x_rows x x_cols (symmetric when x_cols is None);
+    fills kq / lnkq (and fused kc / k) in place; returns (kq, lnkq)."""
+    sym = x_cols is None
+    xc = x_rows if sym else x_cols
+    rp, ldr = _mat(x_rows, "x_rows")
+    cp, ldc = _mat(xc, "x_cols")
+    if xc.shape[1] != x_rows.shape[1]:
+        raise ValueError("x_rows and x_cols need the same feature count")
+    kp, ldk = _opt(kq, "kq")
+    lp, ldl = _opt(lnkq, "lnkq")
+    f = _fuse(dict(fuse, x_rows=x_rows, x_cols=xc)) if fuse is not None else None
+    _check(_lib.qk_pathsum_gram(rp, x_rows.shape[0], ldr, cp, xc.shape[0], ldc, x_rows.shape[1],
+                                int(n_layers), 1 if entangle else 0, 1 if sym else 0, kp, ldk,
                                 lp, ldl, C.byref(f) if f is not None else None,
                                 _stream(stream)))
     return kq, lnkq
