@@ -395,6 +395,69 @@ def chi64_sweep(args):
     return res
 
 
+PATHSUM_FLOP_SITE = {1: 14 + 6 + 3 * 6, 2: 12 * 14 + 6 + 7 * 6}
+
+
+def pathsum_flops(d, n_layers, pairs):
+    """Algorithmic FLOP of the path-sum chain as written (an FMA counts 2):
+    per bond, one butterfly per line and state pair (14 FLOP) and the shared
+    line's phase (6); per site the weight's complex products (6 each; the
+    first site's only)."""
+    per_site = PATHSUM_FLOP_SITE[n_layers]
+    first = 18 if n_layers == 1 else 42
+    return float(pairs) * (per_site * (d - 1) + first)
+
+
+def pathsum_leg(args):
+    """The exact path-sum evaluator on the 784-qubit job (4000 train + 1000
+    test images, L = 2, the same outputs as the MPS step: K_q, ln K_q, K_c,
+    K with w = 0.5, gamma = 1/d), inputs resident; no build."""
+    import numpy as np
+    import torch
+
+    import paper_2602_01330_amd.qk as qk
+    from synthdata import config_inputs
+
+    x_tr, x_te, _ = config_inputs("C3")
+    ntr, nte, d = x_tr.shape[0], x_te.shape[0], x_tr.shape[1]
+    xtr = torch.as_tensor(x_tr, device="cuda")
+    xte = torch.as_tensor(x_te, device="cuda")
+    f64 = dict(dtype=torch.float64, device="cuda")
+    o_tr = {k: torch.empty((ntr, ntr), **f64) for k in ("kq", "ln", "kc", "k")}
+    o_te = {k: torch.empty((nte, ntr), **f64) for k in ("kq", "ln", "kc", "k")}
+    pairs = ntr * (ntr + 1) // 2 + nte * ntr
+
+    def step():
+        qk.qk_pathsum_gram(xtr, None, 2, True, o_tr["kq"], o_tr["ln"],
+                           {"gamma": 1.0 / d, "w": 0.5, "kc": o_tr["kc"], "k": o_tr["k"]})
+        qk.qk_pathsum_gram(xte, xtr, 2, True, o_te["kq"], o_te["ln"],
+                           {"gamma": 1.0 / d, "w": 0.5, "kc": o_te["kc"], "k": o_te["k"]})
+
+    step()
+    torch.cuda.synchronize()
+    steps = max(1, args.steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    ms = e0.elapsed_time(e1) / steps
+    flops = pathsum_flops(d, 2, pairs)
+    tf = flops / (ms / 1e3) / 1e12
+    log(f"bench: pathsum leg: {ms:.1f} ms/step ({pairs / (ms / 1e3):.3g} pairs/s, "
+        f"{tf:.1f} TFLOP/s)")
+    return {"workload": "784-qubit images, 4000 train + 1000 test, L=2, exact path-sum "
+                        "(no MPS build), fused RBF (gamma=1/d) + mix w=0.5",
+            "ms_per_step": ms, "wall_ms_per_step": wall, "steps": steps,
+            "pairs_per_s": pairs / (ms / 1e3), "algorithmic_flop": flops,
+            "roofline": {"bound": "alu", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s",
+                         "frac": tf / 78.6, "traffic": None,
+                         "note": "step time includes the two table kernels and the epilogue"}}
+
+
 def svm_leg(args):
     """SVM training and prediction (Eqs. (1)-(2), (4)-(5), one-against-one)
     on the dual kernel of the 784-feature workload: 4000 train + 1000 test
@@ -611,6 +674,8 @@ def run(args):
         leg("serving", serving)
     if args.svm:
         leg("svm", svm_leg)
+    if args.pathsum:
+        leg("pathsum", pathsum_leg)
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
@@ -636,6 +701,10 @@ def main():
                     help="measured seconds of the serving run (0 skips it)")
     ap.add_argument("--serve-warmup", type=float, default=3.0)
     ap.add_argument("--serve-rate", type=float, default=200.0, help="requests per second")
+    ap.add_argument("--pathsum", action="store_true",
+                    help="add the exact path-sum leg on the 784-qubit job")
+    ap.add_argument("--pathsum-only", action="store_true",
+                    help="run only the path-sum leg and print its JSON")
     ap.add_argument("--svm", action="store_true",
                     help="add the SVM training / prediction leg on the 784-feature Gram")
     ap.add_argument("--svm-only", action="store_true",
@@ -645,6 +714,9 @@ def main():
     args = ap.parse_args()
     if args.chi64_only:
         print(json.dumps(chi64_sweep(args)), flush=True)
+        return
+    if args.pathsum_only:
+        print(json.dumps(pathsum_leg(args)), flush=True)
         return
     if args.svm_only:
         print(json.dumps(svm_leg(args)), flush=True)

@@ -43,3 +43,15 @@ def test_bond_64_profile():
     d = 784
     chi = np.array([min(2 ** min(k, 30), 2 ** min(d - k, 30), 64) for k in range(d + 1)])[None]
     assert bench.algorithmic_flops(chi, chi, False) == 6483195584
+
+
+def test_pathsum_flop_count():
+    """The path-sum's FLOP per pair, counted from its operations: at L = 2
+    each bond applies 12 butterflies (3 lines x 4 state pairs; 4 sums, 2
+    products, 4 FMAs = 14 FLOP) and one shared-line phase (a complex product,
+    6), each site 7 complex products of the weight (6 each; the first site
+    skips the bond); at L = 1, 1 butterfly, the phase and 3 weight products."""
+    from bench import pathsum_flops
+    assert pathsum_flops(784, 2, 1) == 783 * (12 * 14 + 6 + 7 * 6) + 42
+    assert pathsum_flops(784, 1, 1) == 783 * (14 + 6 + 3 * 6) + 18
+    assert pathsum_flops(1, 2, 10) == 420.0
