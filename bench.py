@@ -418,8 +418,16 @@ def pathsum_leg(args):
     import paper_2602_01330_amd.qk as qk
     from synthdata import config_inputs
 
+    from oracle import pathsum as opathsum
+
     x_tr, x_te, _ = config_inputs("C3")
     ntr, nte, d = x_tr.shape[0], x_te.shape[0], x_tr.shape[1]
+    # the oracle's path-sum on a bounded sample (one process, one core)
+    rng = np.random.default_rng(11)
+    sample = np.stack([rng.integers(0, ntr, 1024), rng.integers(0, ntr, 1024)], axis=1)
+    t0 = time.perf_counter()
+    opathsum.ln_kernel_pairs(x_tr, x_tr, 2, sample)
+    cpu_rate = len(sample) / (time.perf_counter() - t0)
     xtr = torch.as_tensor(x_tr, device="cuda")
     xte = torch.as_tensor(x_te, device="cuda")
     f64 = dict(dtype=torch.float64, device="cuda")
@@ -455,7 +463,9 @@ def pathsum_leg(args):
             "pairs_per_s": pairs / (ms / 1e3), "algorithmic_flop": flops,
             "roofline": {"bound": "alu", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s",
                          "frac": tf / 78.6, "traffic": None,
-                         "note": "step time includes the two table kernels and the epilogue"}}
+                         "note": "step time includes the two table kernels and the epilogue"},
+            "cpu_oracle": {"pairs_per_s": cpu_rate, "cores": 1, "kind": "oracle",
+                           "sample": "1024 random train pairs at d=784, L=2 (oracle.pathsum)"}}
 
 
 def svm_leg(args):
