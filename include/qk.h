@@ -287,11 +287,11 @@ QK_API qk_status qk_svm_decision(const double* k_dev, int64_t m, int64_t n, int6
                                  void* hip_stream);
 
 /*
- * qk_pathsum_gram -- the quantum kernel (Eqs. (7), (10)) of one- and
- * two-layer encoding circuits (Eq. (6)) by exact path-sum evaluation, with
+ * qk_pathsum_gram -- the quantum kernel (Eqs. (7), (10)) of encoding
+ * circuits (Eq. (6)) of one to three layers by exact path-sum evaluation, with
  * no MPS build and no truncation: every gate but H is diagonal, so the
  * overlap is a sum over computational-basis histories, evaluated as a chain
- * over the qubits of 2^(2L-1) states (2 at L = 1, 8 at L = 2) whose bond
+ * over the qubits of 2^(2L-1) states (2, 8 or 32) whose bond
  * factor splits into one 2 x 2 factor per history line. Complex FP64, one
  * pair per lane; exact power-of-two rescaling, so ln K_q is exact in range.
  * Equal, to rounding, to the MPS route wherever that route does not
@@ -300,7 +300,7 @@ QK_API qk_status qk_svm_decision(const double* k_dev, int64_t m, int64_t n, int6
  *   x_rows_dev  m x d features (leading dimension ld_xr >= d); x_cols_dev
  *               n x d. symmetric = 1 needs the same pointer, m = n and
  *               ld_xr = ld_xc, contracts the upper triangle and mirrors it.
- *   n_layers    1 or 2 (QK_ERR_UNSUPPORTED otherwise); entangle 0 drops the
+ *   n_layers    1, 2 or 3 (QK_ERR_UNSUPPORTED otherwise); entangle 0 drops the
  *               RZZ chain.
  *   kq_dev, lnkq_dev  optional m x n outputs (leading dimensions >= n).
  *   fuse        optional RBF (Eq. (3)) and mix (Eq. (11)) outputs as in

@@ -1,5 +1,5 @@
-// Exact path-sum evaluation of the quantum kernel for one- and two-layer
-// circuits, an alternative to building MPS and sweeping them.
+// Exact path-sum evaluation of the quantum kernel for circuits of one to
+// three layers, an alternative to building MPS and sweeping them.
 //
 // Every gate of the encoding circuit except H is diagonal in the
 // computational basis (Eq. (6)). Expanding each Hadamard layer over basis
@@ -19,6 +19,10 @@
 //   w_k = 1/4 (q conj r, 1, q, -r, conj r, -conj q, 1, conj q r).
 // L = 1: c = z and, with q = e^{i x_k}, r = e^{i y_k},
 //   w_k = 1/2 (q conj r, conj q r).
+// L = 3: c = 16 u1 + 8 u2 + 4 v1 + 2 v2 + z (32 states, 5 lines), with
+//   q = e^{i x_k}, r = e^{i y_k}: w_k(c) = 1/8 (-1)^(u1 u2 + u2 z + v1 v2 + v2 z)
+//   q^{su} conj(r)^{sv}, su = s(u1) + s(u2) + s(z), sv likewise; the 16
+//   products q^a conj(r)^b (a, b in {3, 1, -1, -3}) are formed once per site.
 // The 2^-L factors go into the base-2 exponent, and the chain vector is
 // rescaled by an exact power of two every 8 sites, so ln K_q is exact in
 // range. One pair per lane, a 16 x 16 pair tile per 256-thread workgroup;
@@ -49,7 +53,7 @@ __global__ void pathsum_table_kernel(const double* __restrict__ x, int64_t n, in
   const double* xs = x + s * ld_x;
   const double xk = xs[k];
   double qs, qc, ps = 0.0, pc = 1.0;
-  sincos(n_layers == 1 ? xk : 2.0 * xk, &qs, &qc);
+  sincos(n_layers == 2 ? 2.0 * xk : xk, &qs, &qc);
   if (entangle && k + 1 < d) {
     const double th = 2.0 * (M_PI - xk) * (M_PI - xs[k + 1]);
     sincos(0.5 * th, &ps, &pc);
@@ -77,7 +81,7 @@ __device__ inline void butterfly(Cd& t, Cd& o, Cd p) {
 
 template <int L>
 struct PsState {
-  static constexpr int S = L == 1 ? 2 : 8;
+  static constexpr int S = 1 << (2 * L - 1);
   Cd v[S];
 };
 
@@ -88,7 +92,7 @@ __device__ inline void apply_weight(PsState<L>& st, Cd q, Cd r) {
     const Cd g = cmulc(q, r);  // q conj r
     st.v[0] = cmul(st.v[0], g);
     st.v[1] = cmulc(st.v[1], g);
-  } else {
+  } else if constexpr (L == 2) {
     const Cd t = cmulc(q, r);  // q conj r
     st.v[0] = cmul(st.v[0], t);
     st.v[2] = cmul(st.v[2], q);
@@ -98,6 +102,25 @@ __device__ inline void apply_weight(PsState<L>& st, Cd q, Cd r) {
     const Cd v5 = cmulc(st.v[5], q);
     st.v[5] = {-v5.re, -v5.im};
     st.v[7] = cmulc(st.v[7], t);
+  } else {
+    // powers q^a, a = 3, 1, -1, -3 (index (3 - a) / 2), and conj(r)^b
+    const Cd q3 = cmul(cmul(q, q), q), r3 = cmul(cmul(r, r), r);
+    const Cd qa[4] = {q3, q, {q.re, -q.im}, {q3.re, -q3.im}};  // q^a
+    const Cd rb[4] = {{r3.re, -r3.im}, {r.re, -r.im}, r, r3};    // conj(r)^b
+    Cd w[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) w[a][b] = cmul(qa[a], rb[b]);
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+      const int u1 = (c >> 4) & 1, u2 = (c >> 3) & 1, v1 = (c >> 2) & 1, v2 = (c >> 1) & 1,
+                z = c & 1;
+      const int su = 3 - 2 * (u1 + u2 + z), sv = 3 - 2 * (v1 + v2 + z);
+      const bool neg = ((u1 & u2) ^ (u2 & z) ^ (v1 & v2) ^ (v2 & z)) != 0;
+      const Cd p = cmul(st.v[c], w[(3 - su) / 2][(3 - sv) / 2]);
+      st.v[c] = neg ? Cd{-p.re, -p.im} : p;
+    }
   }
 }
 
@@ -107,6 +130,16 @@ __device__ inline void apply_bond(PsState<L>& st, Cd px, Cd py) {
   const Cd pz = cmulc(px, py);  // shared line: e^{i (theta_x - theta_y) / 2}
   if constexpr (L == 1) {
     butterfly(st.v[0], st.v[1], pz);
+  } else if constexpr (L == 3) {
+    const Cd pyc = {py.re, -py.im};
+    // lines u1, u2 (bits 4, 3) take px; v1, v2 (bits 2, 1) conj(py); z pz
+#pragma unroll
+    for (int bit = 4; bit >= 0; --bit) {
+      const Cd p = bit >= 3 ? px : (bit >= 1 ? pyc : pz);
+#pragma unroll
+      for (int c = 0; c < 32; ++c)
+        if (!((c >> bit) & 1)) butterfly(st.v[c], st.v[c | (1 << bit)], p);
+    }
   } else {
     const Cd pyc = {py.re, -py.im};
 #pragma unroll
@@ -218,6 +251,9 @@ hipError_t qk_launch_pathsum(const double4* tr, int64_t m, const double4* tc, in
   const int use_fuse = fuse ? 1 : 0;
   if (n_layers == 1)
     hipLaunchKernelGGL(pathsum_kernel<1>, dim3((unsigned)tiles), dim3(kPsThreads), 0, s, tr, m, tc,
+                       n, d, symmetric, ntc, kq, ld_kq, lnkq, ld_ln, f, use_fuse);
+  else if (n_layers == 3)
+    hipLaunchKernelGGL(pathsum_kernel<3>, dim3((unsigned)tiles), dim3(kPsThreads), 0, s, tr, m, tc,
                        n, d, symmetric, ntc, kq, ld_kq, lnkq, ld_ln, f, use_fuse);
   else
     hipLaunchKernelGGL(pathsum_kernel<2>, dim3((unsigned)tiles), dim3(kPsThreads), 0, s, tr, m, tc,

@@ -834,8 +834,8 @@ qk_status qk_pathsum_gram(const double* x_rows_dev, int64_t m, int64_t ld_xr,
   if (m < 0 || n < 0 || m > INT32_MAX || n > INT32_MAX)
     return fail(QK_ERR_INVALID_ARG, "sample counts must be in [0, 2^31 - 1]");
   if (d < 1) return fail(QK_ERR_INVALID_ARG, "d < 1");
-  if (n_layers != 1 && n_layers != 2)
-    return fail(QK_ERR_UNSUPPORTED, "the path-sum evaluator covers one and two layers");
+  if (n_layers < 1 || n_layers > 3)
+    return fail(QK_ERR_UNSUPPORTED, "the path-sum evaluator covers one to three layers");
   if (symmetric && (m != n || x_rows_dev != x_cols_dev || ld_xr != ld_xc))
     return fail(QK_ERR_INVALID_ARG, "symmetric mode needs the same rows and columns");
   if ((m > 0 && !x_rows_dev) || (n > 0 && !x_cols_dev))

@@ -1,4 +1,4 @@
-"""The exact path-sum evaluator on the device (one- and two-layer circuits).
+"""The exact path-sum evaluator on the device (circuits of one to three layers).
 
 Checked against the oracle's path-sum (itself pinned to the statevector on
 up to 12 qubits and to the MPS oracle at 784 qubits), the entangler-free
@@ -32,7 +32,7 @@ def all_pairs(m, n):
     return np.array([(i, j) for i in range(m) for j in range(n)])
 
 
-@pytest.mark.parametrize("L", [1, 2])
+@pytest.mark.parametrize("L", [1, 2, 3])
 @pytest.mark.parametrize("m,n", [(37, 37), (17, 33), (1, 1)])
 def test_pathsum_vs_oracle(qk, L, m, n):
     """Symmetric (37 samples: three tiles, a ragged edge) and rectangular
@@ -56,7 +56,7 @@ def test_pathsum_vs_oracle(qk, L, m, n):
         assert np.max(np.abs(np.diag(got))) < 1e-12
 
 
-@pytest.mark.parametrize("L", [1, 2])
+@pytest.mark.parametrize("L", [1, 2, 3])
 def test_pathsum_without_entanglers_is_the_product_form(qk, L):
     """entangle = 0: the kernel is the product of per-qubit overlaps (closed
     form, no chain)."""
@@ -112,9 +112,27 @@ def test_pathsum_rejections(qk):
     X, _ = gen_clusters(4, 6, 1)
     ln = torch.empty((4, 4), dtype=torch.float64, device="cuda")
     with pytest.raises(qk.QkError):
-        qk.qk_pathsum_gram(dev(X), None, 3, True, None, ln)  # three layers
+        qk.qk_pathsum_gram(dev(X), None, 4, True, None, ln)  # four layers
     with pytest.raises(qk.QkError):
         qk.qk_pathsum_gram(dev(X), None, 2, True, None, None)  # no output
     with pytest.raises(ValueError):
         qk.qk_pathsum_gram(dev(X), dev(X[:, :5]), 2, True, None, ln)
     assert math.isfinite(float(qk.qk_pathsum_gram(dev(X), None, 2, True, None, ln)[1][0, 0]))
+
+
+def test_pathsum_three_layers_equals_bond8_mps_route(qk):
+    """L = 3 at 64 features: bonds reach 8, so the MPS route runs the
+    one-workgroup-per-pair complex-FP64 sweep; the path-sum (32 states) gives
+    the same ln K_q."""
+    X, _ = gen_clusters(24, 64, 364)
+    xd = dev(X)
+    print("[pathsum L=3] 24 samples, d=64", flush=True)
+    ln_ps = torch.empty((24, 24), dtype=torch.float64, device="cuda")
+    qk.qk_pathsum_gram(xd, None, 3, True, None, ln_ps)
+    b = qk.qk_mps_build(xd, 3, 64, 1e-10, store=qk.QK_STORE_FP64)
+    assert qk.qk_mps_info(b)["chi_pad"] == 8
+    ln_m = torch.empty((24, 24), dtype=torch.float64, device="cuda")
+    qk.qk_overlap_gram(b, b, True, "fp64", None, ln_m)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(ln_ps.cpu().numpy() - ln_m.cpu().numpy())) < 1e-8
+    b.close()
