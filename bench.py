@@ -395,23 +395,27 @@ def chi64_sweep(args):
     return res
 
 
-PATHSUM_FLOP_SITE = {1: 14 + 6 + 3 * 6, 2: 12 * 14 + 6 + 7 * 6}
+PATHSUM_FLOP_SITE = {1: 14 + 6 + 3 * 6, 2: 12 * 14 + 6 + 7 * 6,
+                     3: 80 * 14 + 6 + (4 + 16 + 32) * 6}
 
 
 def pathsum_flops(d, n_layers, pairs):
     """Algorithmic FLOP of the path-sum chain as written (an FMA counts 2):
     per bond, one butterfly per line and state pair (14 FLOP) and the shared
     line's phase (6); per site the weight's complex products (6 each; the
-    first site's only)."""
+    first site's only). At L = 3: 80 butterflies, and the weight's q^3, r^3
+    (4 products), the 16 products q^a conj(r)^b and one per state (32)."""
     per_site = PATHSUM_FLOP_SITE[n_layers]
-    first = 18 if n_layers == 1 else 42
+    first = {1: 18, 2: 42, 3: (4 + 16 + 32) * 6}[n_layers]
     return float(pairs) * (per_site * (d - 1) + first)
 
 
 def pathsum_leg(args):
     """The exact path-sum evaluator on the 784-qubit job (4000 train + 1000
     test images, L = 2, the same outputs as the MPS step: K_q, ln K_q, K_c,
-    K with w = 0.5, gamma = 1/d), inputs resident; no build."""
+    K with w = 0.5, gamma = 1/d), inputs resident; no build. With
+    --pathsum-layers 3 the same job at three layers, timed beside the MPS
+    route (device build, bonds 8, complex-FP64 sweep) on the same outputs."""
     import numpy as np
     import torch
 
@@ -424,9 +428,11 @@ def pathsum_leg(args):
     ntr, nte, d = x_tr.shape[0], x_te.shape[0], x_tr.shape[1]
     # the oracle's path-sum on a bounded sample (one process, one core)
     rng = np.random.default_rng(11)
-    sample = np.stack([rng.integers(0, ntr, 1024), rng.integers(0, ntr, 1024)], axis=1)
+    L = args.pathsum_layers
+    ns = 1024 if L < 3 else 128  # about 5 s of oracle time either way
+    sample = np.stack([rng.integers(0, ntr, ns), rng.integers(0, ntr, ns)], axis=1)
     t0 = time.perf_counter()
-    opathsum.ln_kernel_pairs(x_tr, x_tr, 2, sample)
+    opathsum.ln_kernel_pairs(x_tr, x_tr, L, sample)
     cpu_rate = len(sample) / (time.perf_counter() - t0)
     xtr = torch.as_tensor(x_tr, device="cuda")
     xte = torch.as_tensor(x_te, device="cuda")
@@ -436,9 +442,9 @@ def pathsum_leg(args):
     pairs = ntr * (ntr + 1) // 2 + nte * ntr
 
     def step():
-        qk.qk_pathsum_gram(xtr, None, 2, True, o_tr["kq"], o_tr["ln"],
+        qk.qk_pathsum_gram(xtr, None, L, True, o_tr["kq"], o_tr["ln"],
                            {"gamma": 1.0 / d, "w": 0.5, "kc": o_tr["kc"], "k": o_tr["k"]})
-        qk.qk_pathsum_gram(xte, xtr, 2, True, o_te["kq"], o_te["ln"],
+        qk.qk_pathsum_gram(xte, xtr, L, True, o_te["kq"], o_te["ln"],
                            {"gamma": 1.0 / d, "w": 0.5, "kc": o_te["kc"], "k": o_te["k"]})
 
     step()
@@ -453,19 +459,42 @@ def pathsum_leg(args):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
     ms = e0.elapsed_time(e1) / steps
-    flops = pathsum_flops(d, 2, pairs)
+    flops = pathsum_flops(d, L, pairs)
     tf = flops / (ms / 1e3) / 1e12
     log(f"bench: pathsum leg: {ms:.1f} ms/step ({pairs / (ms / 1e3):.3g} pairs/s, "
         f"{tf:.1f} TFLOP/s)")
-    return {"workload": "784-qubit images, 4000 train + 1000 test, L=2, exact path-sum "
+    mps = None
+    if L == 3:
+        ln_ps = o_tr["ln"].clone()
+        e0.record()
+        btr, bte = qk.qk_mps_build_many([xtr, xte], 3, 64, 1e-10, store=qk.QK_STORE_FP64)
+        tasks = [{"rows": btr, "cols": btr, "symmetric": True, "kq": o_tr["kq"],
+                  "lnkq": o_tr["ln"], "fuse": {"x_rows": xtr, "x_cols": xtr, "gamma": 1.0 / d,
+                                               "w": 0.5, "kc": o_tr["kc"], "k": o_tr["k"]}},
+                 {"rows": bte, "cols": btr, "symmetric": False, "kq": o_te["kq"],
+                  "lnkq": o_te["ln"], "fuse": {"x_rows": xte, "x_cols": xtr, "gamma": 1.0 / d,
+                                               "w": 0.5, "kc": o_te["kc"], "k": o_te["k"]}}]
+        qk.qk_overlap_gram_multi(tasks, "fp64")
+        e1.record()
+        torch.cuda.synchronize()
+        mps_ms = e0.elapsed_time(e1)
+        dln = float((o_tr["ln"] - ln_ps).abs().max())
+        mps = {"ms_per_step": mps_ms, "pairs_per_s": pairs / (mps_ms / 1e3),
+               "chi_pad": qk.qk_mps_info(btr)["chi_pad"], "max_abs_dlnk_vs_pathsum": dln,
+               "pathsum_speedup": mps_ms / ms}
+        log(f"bench: MPS route at L=3 (FP64, bonds 8): {mps_ms:.1f} ms, |d lnK| {dln:.1e}")
+        btr.close()
+        bte.close()
+    return {"workload": f"784-qubit images, 4000 train + 1000 test, L={L}, exact path-sum "
                         "(no MPS build), fused RBF (gamma=1/d) + mix w=0.5",
+            "mps_route_fp64": mps,
             "ms_per_step": ms, "wall_ms_per_step": wall, "steps": steps,
             "pairs_per_s": pairs / (ms / 1e3), "algorithmic_flop": flops,
             "roofline": {"bound": "alu", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s",
                          "frac": tf / 78.6, "traffic": None,
                          "note": "step time includes the two table kernels and the epilogue"},
             "cpu_oracle": {"pairs_per_s": cpu_rate, "cores": 1, "kind": "oracle",
-                           "sample": "1024 random train pairs at d=784, L=2 (oracle.pathsum)"}}
+                           "sample": f"{ns} random train pairs at d=784, L={L} (oracle.pathsum)"}}
 
 
 def svm_leg(args):
@@ -713,6 +742,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="requests per second")
     ap.add_argument("--pathsum", action="store_true",
                     help="add the exact path-sum leg on the 784-qubit job")
+    ap.add_argument("--pathsum-layers", type=int, default=2, choices=[1, 2, 3],
+                    help="circuit layers of the path-sum leg (3 also times the MPS route)")
     ap.add_argument("--pathsum-only", action="store_true",
                     help="run only the path-sum leg and print its JSON")
     ap.add_argument("--svm", action="store_true",

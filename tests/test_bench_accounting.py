@@ -55,3 +55,5 @@ def test_pathsum_flop_count():
     assert pathsum_flops(784, 2, 1) == 783 * (12 * 14 + 6 + 7 * 6) + 42
     assert pathsum_flops(784, 1, 1) == 783 * (14 + 6 + 3 * 6) + 18
     assert pathsum_flops(1, 2, 10) == 420.0
+    # L = 3: 80 butterflies, the phase, q^3 / r^3, 16 cross products, 32 states
+    assert pathsum_flops(3, 3, 1) == 2 * (80 * 14 + 6 + 52 * 6) + 52 * 6
