@@ -8,8 +8,8 @@
 // classes); all problems of a class set run in one launch. Thread k owns the
 // problem's samples t = k, k + 256, ...: their multiplier a_t, gradient G_t
 // and diagonal K_tt live in a global scratch slice that only that thread
-// writes, so one step needs only three barriers (the two block reductions
-// and the broadcast of the step).
+// writes, so one step needs four barriers: one per block reduction (i, the
+// stopping gap, j) and one for the broadcast of the step.
 //
 // Per step, in the problem's sample order, with v_t = -y_t G_t:
 //   i = argmax v over I_up, m = v_i; M = min v over I_low; stop if m - M < eps;
