@@ -38,7 +38,11 @@ TRAFFIC = {"fp32_mfma": {"source": "paper_2602_01330_amd/csrc/sweep_mfma.hip",
                          "bytes": 296.2e9 + 0.809e9},
            "fp32_mfma_wide": {"source": "paper_2602_01330_amd/csrc/sweep_wide.hip",
                               "sha256_prefix": "d9cf1b83de8347d1",
-                              "bytes": 143.1e9 + 0.0027e9}}
+                              "bytes": 143.1e9 + 0.0027e9},
+           # per step of the path-sum leg (both launches)
+           "pathsum_l2_step": {"source": "paper_2602_01330_amd/csrc/pathsum.hip",
+                               "sha256_prefix": "5a94561d7e8a54e6",
+                               "bytes": 24.584e9 + 0.640e9}}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp32_mfma": "f32", "bf16x2": "bf16", "bf16x3": "bf16"}
 
 
@@ -491,7 +495,8 @@ def pathsum_leg(args):
             "ms_per_step": ms, "wall_ms_per_step": wall, "steps": steps,
             "pairs_per_s": pairs / (ms / 1e3), "algorithmic_flop": flops,
             "roofline": {"bound": "alu", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s",
-                         "frac": tf / 78.6, "traffic": None,
+                         "frac": tf / 78.6,
+                         "traffic": traffic_for("pathsum_l2_step") if L == 2 else None,
                          "note": "step time includes the two table kernels and the epilogue"},
             "cpu_oracle": {"pairs_per_s": cpu_rate, "cores": 1, "kind": "oracle",
                            "sample": f"{ns} random train pairs at d=784, L={L} (oracle.pathsum)"}}
