@@ -52,3 +52,44 @@ def test_tuning_table_round_trip_without_gpu():
         qk.qk_tune_import("4 10 99 1 1.0\n")  # unknown form
     with pytest.raises(qk.QkError):
         qk.qk_tune_import("garbage")
+
+
+def test_argument_checks_of_the_svm_and_path_sum_entry_points_without_gpu():
+    """Host-side validation returns before any device call: bad labels,
+    class counts, box bound and step cap of qk_svm_fit_ovo; sizes and
+    outputs of qk_svm_predict_ovo; layer count and outputs of
+    qk_pathsum_gram. The pointers are never dereferenced."""
+    lib = ctypes.CDLL(LIB)
+    P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.qk_svm_fit_ovo.argtypes = [P, I64, I64, P, I32, D, D, I64, P, I64, P, P, P]
+    lib.qk_svm_predict_ovo.argtypes = [P, I64, I64, I64, P, I64, P, I32, P, I64, P, P]
+    lib.qk_pathsum_gram.argtypes = [P, I64, I64, P, I64, I64, I32, I32, I32, I32, P, I64, P,
+                                    I64, P, P]
+    INVALID, UNSUPPORTED = -1, -4
+    fake = P(0x1000)
+    labels = (ctypes.c_int32 * 4)(0, 1, 2, 1)
+
+    def fit(lab, n_classes=3, C=1.0, eps=1e-3, max_iter=10):
+        return lib.qk_svm_fit_ovo(fake, 4, 4, ctypes.cast(lab, P), n_classes, C, eps, max_iter,
+                                  fake, 4, fake, fake, None)
+
+    assert fit((ctypes.c_int32 * 4)(0, 1, 3, 1)) == INVALID   # label >= n_classes
+    assert fit((ctypes.c_int32 * 4)(0, -2, 2, 1)) == INVALID  # label below -1
+    assert fit(labels, n_classes=1) == INVALID
+    assert fit(labels, n_classes=65) == INVALID
+    assert fit(labels, C=0.0) == INVALID
+    assert fit(labels, C=float("inf")) == INVALID
+    assert fit(labels, eps=0.0) == INVALID
+    assert fit(labels, max_iter=0) == INVALID
+    assert lib.qk_svm_predict_ovo(fake, 3, 4, 4, fake, 4, fake, 3, None, 3, None, None) == INVALID
+    assert lib.qk_svm_predict_ovo(fake, 3, 4, 4, fake, 4, fake, 3, fake, 2, None, None) == INVALID
+    assert lib.qk_svm_predict_ovo(fake, 3, 4, 3, fake, 4, fake, 3, fake, 3, None, None) == INVALID
+    ln = fake
+    assert lib.qk_pathsum_gram(fake, 4, 8, fake, 4, 8, 8, 4, 1, 1, None, 0, ln, 4, None,
+                               None) == UNSUPPORTED
+    assert lib.qk_pathsum_gram(fake, 4, 8, fake, 4, 8, 8, 2, 1, 1, None, 0, None, 0, None,
+                               None) == INVALID  # no output
+    assert lib.qk_pathsum_gram(fake, 4, 8, P(0x2000), 4, 8, 8, 2, 1, 1, None, 0, ln, 4, None,
+                               None) == INVALID  # symmetric with different features
+    assert lib.qk_pathsum_gram(fake, 4, 7, fake, 4, 7, 8, 2, 1, 0, None, 0, ln, 4, None,
+                               None) == INVALID  # leading dimension below d
