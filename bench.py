@@ -77,10 +77,73 @@ def traffic_for(form):
     return t["bytes"] if h.startswith(t["sha256_prefix"]) else None
 
 
+def gpu_state_held():
+    """Reasons this process holds GPU state (empty if none): an open /dev/kfd
+    (the HSA runtime has started), torch's CUDA/HIP state initialised, or
+    libqk.so mapped. A process in any of these states must not fork: the
+    children would share the runtime's queues, signals and device mappings
+    copy-on-write with the parent."""
+    reasons = []
+    try:
+        for fd in os.listdir("/proc/self/fd"):
+            try:
+                if os.readlink(os.path.join("/proc/self/fd", fd)) == "/dev/kfd":
+                    reasons.append("/dev/kfd is open")
+                    break
+            except OSError:
+                pass
+    except OSError:
+        pass
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_initialized():
+        reasons.append("torch's GPU state is initialised")
+    try:
+        with open("/proc/self/maps") as f:
+            if "libqk.so" in f.read():
+                reasons.append("libqk.so is loaded")
+    except OSError:
+        pass
+    return reasons
+
+
+def cpu_model():
+    """Host CPU description from /proc/cpuinfo and the sysfs topology."""
+    info = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if ":" not in line:
+                    continue
+                k, v = (t.strip() for t in line.split(":", 1))
+                if k in ("model name", "vendor_id", "cpu family", "model", "stepping",
+                          "cpu MHz", "cache size") and k not in info:
+                    info[k] = v
+    except OSError:
+        pass
+    try:
+        info["online"] = open("/sys/devices/system/cpu/online").read().strip()
+    except OSError:
+        pass
+    info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    return info
+
+
+# The worker pool is sized to the host threads this process may use, at most
+# 16: the CPU share of one GPU on the machines this runs on.
+CPU_WORKERS_MAX = 16
+
+
 def cpu_baseline(x_tr, seconds_target=15.0):
-    """Time the FP64 oracle on a bounded sample with a process pool."""
+    """Time the FP64 oracle on a bounded sample with a process pool forked
+    from this process, which must hold no GPU state (checked: it raises
+    otherwise, whatever order the caller runs its legs in)."""
     import multiprocessing as mp
-    cores = min(len(os.sched_getaffinity(0)), 16)
+    held = gpu_state_held()
+    if held:
+        raise RuntimeError("cpu_baseline forks worker processes and must run before anything "
+                           "touches the GPU: " + "; ".join(held))
+    avail = len(os.sched_getaffinity(0))
+    cores = min(avail, CPU_WORKERS_MAX)
     n_build, n_pairs = 8, 24576
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
@@ -94,18 +157,12 @@ def cpu_baseline(x_tr, seconds_target=15.0):
     sweep_rate = cores * n_pairs / sweep_s        # pairs / s
     pairs = 4000 * 4001 // 2 + 1000 * 4000
     job_s = 5000 / build_rate + pairs / sweep_rate
-    model = "unknown"
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
+    cpu = cpu_model()
     return {"value": pairs / job_s, "unit": "entries/s", "cores": cores, "kind": "oracle",
-            "cpu_model": model,
-            "sample": (f"{cores} processes x ({n_build} TEBD builds + {n_pairs} FP64 pair "
+            "cpu_model": cpu.get("model name", "unknown"), "cpu": cpu,
+            "cpus_available": avail,
+            "sample": (f"{cores} processes (one per host thread available, at most "
+                       f"{CPU_WORKERS_MAX}) x ({n_build} TEBD builds + {n_pairs} FP64 pair "
                        f"sweeps) at d=784, L=2; wall {wall:.1f}s; whole-job rate "
                        f"extrapolated to 5000 builds + {pairs} pairs")}
 
@@ -339,9 +396,9 @@ def chi64_sweep(args):
     interior bond at 64 (bonds 1, 2, 4, ..., 64, ..., 4, 2, 1), on random
     left-canonical MPS (seeded; the device build of such deep circuits is not
     part of this leg), 32 row x 64 column samples = 2048 pairs, inputs
-    resident. The complex-FP64 sweep over all pairs; with the matrix-core
-    form enabled (QK_ENABLE_WIDE_MFMA=1) also the complex-FP32 matrix-core
-    sweep over all pairs, with the FP64 one as its comparator."""
+    resident. The complex-FP32 matrix-core sweep over all pairs (with its
+    FP64 refinement of pairs above the threshold) and the complex-FP64 sweep
+    over all pairs as its comparator."""
     import numpy as np
     import torch
 
@@ -352,10 +409,8 @@ def chi64_sweep(args):
     log("bench: chi64 leg: generating random left-canonical MPS")
     cr, tr = gen_isometry_mps(nr, nq, T, seed=71)
     cc, tc = gen_isometry_mps(nc, nq, T, seed=72)
-    wide = os.environ.get("QK_ENABLE_WIDE_MFMA") == "1"
-    store = qk.QK_STORE_ALL if wide else qk.QK_STORE_FP64
-    br = qk.qk_mps_import(cr, tr, 8, T, store=store)
-    bc = qk.qk_mps_import(cc, tc, 8, T, store=store)
+    br = qk.qk_mps_import(cr, tr, 8, T, store=qk.QK_STORE_ALL)
+    bc = qk.qk_mps_import(cc, tc, 8, T, store=qk.QK_STORE_ALL)
     del tr, tc
     flop_pair = algorithmic_flops(cr[:1], cc[:1], False)
     pairs = nr * nc
@@ -383,16 +438,14 @@ def chi64_sweep(args):
                        f"MPS, {nr} x {nc} pairs",
            "algorithmic_flop_per_pair": flop_pair,
            "fp64": entry("fp64", ms64, 78.6, "alu", "sweep_big_kernel<64>", None)}
-    msg = f"fp64 {ms64:.1f} ms"
-    if wide:
-        timed("fp32_mfma", 1)
-        ms32 = timed("fp32_mfma", 3)
-        refined = int((ln >= math.log(1e-2)).sum().item())
-        res["fp32_mfma"] = entry("fp32_mfma", ms32, 157.3, "mfma",
-                                 f"sweep_wide_kernel<64> (+ FP64 list pass, {refined} refined)",
-                                 traffic_for("fp32_mfma_wide"))
-        res["speedup_vs_plain_fp64"] = ms64 / ms32
-        msg += f", fp32_mfma {ms32:.1f} ms"
+    timed("fp32_mfma", 1)
+    ms32 = timed("fp32_mfma", 3)
+    refined = int((ln >= math.log(1e-2)).sum().item())
+    res["fp32_mfma"] = entry("fp32_mfma", ms32, 157.3, "mfma",
+                             f"sweep_wide_kernel<64> (+ FP64 list pass, {refined} refined)",
+                             traffic_for("fp32_mfma_wide"))
+    res["speedup_vs_plain_fp64"] = ms64 / ms32
+    msg = f"fp64 {ms64:.1f} ms, fp32_mfma {ms32:.1f} ms"
     log(f"bench: chi64 leg ({pairs} pairs): {msg}")
     for b in (br, bc):
         b.close()
@@ -798,6 +851,20 @@ def run(args):
     print(json.dumps(line), flush=True)
 
 
+def hbm_copy():
+    """A plain device-to-device copy of exactly 1 GiB, twice: the known byte
+    count that scales the FETCH_SIZE / WRITE_SIZE counters of a profiled run
+    to HBM bytes."""
+    import torch
+    n_bytes = 1 << 30
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+        torch.cuda.synchronize()
+    print(json.dumps({"hbm_copy_bytes": n_bytes, "copies": 2}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -810,8 +877,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-ragged", action="store_true", help="skip the ten-d ragged run")
     ap.add_argument("--chi64", action="store_true",
-                    help="add the 784-site bond-64 sweep leg (its matrix-core form needs "
-                         "QK_ENABLE_WIDE_MFMA=1 in the environment)")
+                    help="add the 784-site bond-64 sweep leg (FP32 matrix-core form and "
+                         "the FP64 comparator)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the two smaller whole-job configurations")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -830,9 +897,15 @@ def main():
                     help="add the SVM training / prediction leg on the 784-feature Gram")
     ap.add_argument("--svm-only", action="store_true",
                     help="run only the SVM leg and print its JSON")
+    ap.add_argument("--hbm-copy", action="store_true",
+                    help="only copy 1 GiB device to device twice (calibrates the HBM byte "
+                         "counters FETCH_SIZE / WRITE_SIZE under rocprofv3)")
     ap.add_argument("--chi64-only", action="store_true",
                     help="run only the 784-site bond-64 sweep leg and print its JSON")
     args = ap.parse_args()
+    if args.hbm_copy:
+        hbm_copy()
+        return
     if args.chi64_only:
         print(json.dumps(chi64_sweep(args)), flush=True)
         return

@@ -150,7 +150,8 @@ QK_API qk_status qk_mps_import(const qk_circuit_desc* c, int64_t n_samples,
  * qk_mps_info -- synchronises the batch's build stream, then reports the
  * sample count, qubit count, padded and largest realized bond dimension and
  * the device bytes held. Returns QK_ERR_DEVICE if the build latched an error
- * (non-finite input or a bond above chi_ws); qk_last_error() says which.
+ * (non-finite input, a bond above chi_ws, or a two-site SVD that reached the
+ * Jacobi sweep limit); qk_last_error() says which.
  * Any output pointer may be NULL.
  */
 QK_API qk_status qk_mps_info(const qk_mps_batch* b, int64_t* n_samples,
@@ -163,8 +164,11 @@ QK_API qk_status qk_mps_chi(const qk_mps_batch* b, int32_t* chi_host);
 /* Copies the per-sample discarded weight (n_samples FP64, host) of the
  * build: the sum over the sample's truncations of sum_{j >= keep} s_j^2 /
  * sum_j s_j^2, the singular values s of each merged two-site matrix in
- * descending order (Section III's bond truncation; cutoff and chi_max decide
- * keep). The state's squared error against the untruncated circuit state is
+ * descending order (cutoff and chi_max decide keep). The paper contracts the
+ * overlap network exactly (Section II-C, Eqs. (8)-(10)); truncating the bonds
+ * is this library's choice for circuits whose exact bonds exceed chi_max,
+ * and this weight measures it. The state's squared error against the
+ * untruncated circuit state is
  * bounded by about twice this sum, so it says how far a truncating build is
  * from the exact kernel. 0 for batches from qk_mps_import and for samples no
  * truncation touched beyond rounding noise. Synchronises the build stream. */
@@ -208,10 +212,9 @@ typedef struct {
  *                triangles are written (train x train); 0: full rectangle.
  *   prec         QK_PREC_*; QK_PREC_FP64 needs QK_STORE_FP64 in both batches.
  *                chi_pad 1, 2, 4: every form (tile kernels); chi_pad 8..64:
- *                QK_PREC_FP64 (one workgroup per pair), and AUTO resolves to
- *                it; QK_PREC_FP32_MFMA there only when the process sets the
- *                environment variable QK_ENABLE_WIDE_MFMA=1 (off by
- *                default: a GPU fault in a run that used it is unexplained).
+ *                QK_PREC_FP64 and QK_PREC_FP32_MFMA (one workgroup per
+ *                pair; the FP32 form recomputes pairs with K_q above its
+ *                refinement threshold in FP64).
  *   kq_dev       FP64 rows->n_samples x cols->n_samples output, ld_kq (may be
  *                NULL if lnkq_dev is given).
  *   lnkq_dev     FP64 ln K_q output, ld_ln (NULL to skip).
@@ -386,6 +389,18 @@ QK_API qk_status qk_svm_predict_ovo(const double* k_dev, int64_t m, int64_t n, i
 QK_API qk_status qk_set_refine_threshold(qk_precision prec, double tau);
 
 /*
+ * Jacobi sweep limit of the build's two-site SVDs (one-sided Jacobi: the
+ * factorisation behind the bond truncation of each two-qubit gate step). A
+ * build whose SVD has not converged after `sweeps` sweeps latches the
+ * non-convergence flag, which qk_mps_info reports and the server turns into
+ * a failed request. Default 60 (converged builds take 2 to 4 sweeps per SVD);
+ * accepted range [0, 1000]; 0 makes every SVD report non-convergence.
+ * Process-wide; applies to builds launched after the call.
+ * Errors: INVALID_ARG.
+ */
+QK_API qk_status qk_set_svd_sweep_limit(int32_t sweeps);
+
+/*
  * qk_autotune -- times the sweep forms that meet the stated tolerance
  * (complex FP64, complex FP32 on VALU with 2..4 persistent workgroups per CU,
  * complex FP32 on MFMA, split BF16x3 on MFMA) on the first max_tiles 16 x 16
@@ -491,6 +506,19 @@ QK_API qk_status qk_server_set_model(qk_server* s, int32_t d, const double* coef
 QK_API qk_status qk_server_submit(qk_server* s, const double* x_host, int64_t n_rows,
                                   int32_t d, double w, int64_t* id);
 
+/* Output flags of qk_server_submit_ex. QK_OUT_LNKQ: the request also returns
+ * its rows of ln K_q (FP64, -inf where the overlap amplitude is 0), the
+ * faithful form of K_q for many qubits, where K_q itself falls below the
+ * FP64 range (Eq. (7) at d = 784 reaches 1e-300 and less on these inputs). */
+enum { QK_OUT_LNKQ = 1 };
+
+/* As qk_server_submit, with extra outputs requested by `outputs` (QK_OUT_*
+ * bits). The ln K_q rows count against the budget like the K rows and are
+ * fetched with qk_server_poll_ex. Errors: those of qk_server_submit, and
+ * INVALID_ARG for an unknown flag. */
+QK_API qk_status qk_server_submit_ex(qk_server* s, const double* x_host, int64_t n_rows,
+                                     int32_t d, double w, uint32_t outputs, int64_t* id);
+
 /* Writes the request state (QK_REQ_*). When DONE and rows_host is not NULL,
  * copies its n_rows x n_support FP64 rows (leading dim ld_rows >= n_support)
  * and releases them; a later poll of that id returns NOT_FOUND. FAILED
@@ -505,6 +533,15 @@ QK_API qk_status qk_server_poll(qk_server* s, int64_t id, double* rows_host,
  * and those of qk_server_poll. */
 QK_API qk_status qk_server_poll_decision(qk_server* s, int64_t id, double* rows_host,
                                          int64_t ld_rows, double* f_host, int32_t* state);
+
+/* As qk_server_poll_decision, and when DONE also copies the request's
+ * n_rows x n_support ln K_q rows (leading dim ld_ln >= n_support) to ln_host
+ * if it is not NULL. Any non-NULL output releases the request. Errors:
+ * INVALID_ARG (ln_host given for a request submitted without QK_OUT_LNKQ, or
+ * ld_ln too small; nothing is released) and those of qk_server_poll_decision. */
+QK_API qk_status qk_server_poll_ex(qk_server* s, int64_t id, double* rows_host,
+                                   int64_t ld_rows, double* f_host, double* ln_host,
+                                   int64_t ld_ln, int32_t* state);
 
 /* Blocks until the request leaves QUEUED/RUNNING or timeout_ms passes
  * (< 0: no limit); writes the state. */

@@ -86,7 +86,8 @@ __device__ inline void wave_lds_sync() {
 // noise of a rank-deficient X and are left alone. Returns false if the sweep
 // limit was reached.
 template <int LD>
-__device__ bool jacobi_columns(double2* X, double2* V, int R, int C, double floor2) {
+__device__ bool jacobi_columns(double2* X, double2* V, int R, int C, double floor2,
+                               int max_sweeps) {
   const int lane = threadIdx.x;
   const int npairs = C >> 1;
   // lanes per pair: the smallest power of two covering the rows (so the
@@ -105,7 +106,7 @@ __device__ bool jacobi_columns(double2* X, double2* V, int R, int C, double floo
   const int players = C - 1;
   const double tol = 1e-14;
 
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     int rotated = 0;
     for (int r = 0; r < players; ++r) {
       int p = 0, q = 0;
@@ -185,7 +186,8 @@ template <int W>
 __global__ __launch_bounds__(64) void mps_build_kernel(
     const double* __restrict__ x, int64_t ld_x, int64_t N, int nq, int n_layers,
     int chi_max, int entangle, double cutoff, double2* __restrict__ t64,
-    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status, double* __restrict__ disc_out) {
+    int32_t* __restrict__ chi_tab, int32_t* __restrict__ status, double* __restrict__ disc_out,
+    int max_sweeps) {
   constexpr int D = 2 * W;
   __shared__ BuildSmem<W> sm;
   const int64_t i = blockIdx.x;
@@ -278,7 +280,7 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
       }
       __syncthreads();
       for (int off = 1; off < 64; off <<= 1) fro += __shfl_xor(fro, off, 64);
-      const bool conv = jacobi_columns<D>(X, V, XR, XCe, 1e-30 * fro);
+      const bool conv = jacobi_columns<D>(X, V, XR, XCe, 1e-30 * fro, max_sweeps);
       if (!conv && lane == 0) atomicOr(status, QK_FLAG_NOCONV);
       // singular values = column norms; rank them (descending, stable)
       for (int cc = lane; cc < XCe; cc += 64) {
@@ -422,7 +424,7 @@ __global__ __launch_bounds__(BuildWgShape<W>::kThreads) void mps_build_wg_kernel
     const double* __restrict__ x, int64_t ld_x, int64_t N, int nq, int n_layers,
     int chi_max, int entangle, double cutoff, double2* __restrict__ t64,
     int32_t* __restrict__ chi_tab, int32_t* __restrict__ status, double2* __restrict__ ws,
-    double* __restrict__ disc_out) {
+    double* __restrict__ disc_out, int max_sweeps) {
   using Sh = BuildWgShape<W>;
   constexpr int D = Sh::D, kR = Sh::kRows, kH = Sh::kHalf, kP = Sh::kPitch;
   constexpr int T = W, TT = W * W, slot = 2 * TT;
@@ -537,7 +539,7 @@ __global__ __launch_bounds__(BuildWgShape<W>::kThreads) void mps_build_wg_kernel
       // one-sided Jacobi over the C columns
       const double tol = 1e-14;
       bool conv = false;
-      for (int sweep = 0; sweep < 60; ++sweep) {
+      for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         int rotated = 0;
         for (int rnd = 0; rnd < C - 1; ++rnd) {
           double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
@@ -764,10 +766,10 @@ __device__ constexpr int rr_q(int r, int k, int players) {
 // each sample (lane holds xr[col]); V rows likewise (vr[col]). Returns
 // whether the sweeps converged for this lane's sample.
 template <int D, int NC>
-__device__ bool jacobi_rows(double2 (&xr)[D], double2 (&vr)[D], double floor2) {
+__device__ bool jacobi_rows(double2 (&xr)[D], double2 (&vr)[D], double floor2, int max_sweeps) {
   constexpr int P = NC - 1, NP = NC / 2;
   const double tol = 1e-14;
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     int rotated = 0;
 #pragma unroll
     for (int r = 0; r < P; ++r) {
@@ -811,9 +813,9 @@ __device__ bool jacobi_rows(double2 (&xr)[D], double2 (&vr)[D], double floor2) {
       }
     }
     if (!__any(rotated)) return true;
-    if (sweep == 59) return !rotated;
+    if (sweep == max_sweeps - 1) return !rotated;
   }
-  return true;
+  return false;  // a limit of 0 sweeps: nothing was verified
 }
 
 // Per step after X (rows in lanes) and V = I are formed: the Jacobi
@@ -828,9 +830,10 @@ __device__ bool jacobi_rows(double2 (&xr)[D], double2 (&vr)[D], double floor2) {
 template <int W, int NC>
 __device__ int b8_factor(double2 (&xr)[2 * W], double2 (&vr)[2 * W], double floor2, int r,
                          int XC, int cl, int cr, bool tr, bool l2r, int chi_max, double cutoff,
-                         double2* Lo, double2* Ro, int& noconv, int& over, double& dw) {
+                         double2* Lo, double2* Ro, int& noconv, int& over, double& dw,
+                         int max_sweeps) {
   constexpr int D = 2 * W, TT = W * W;
-  const bool conv = jacobi_rows<D, NC>(xr, vr, floor2);
+  const bool conv = jacobi_rows<D, NC>(xr, vr, floor2, max_sweeps);
   noconv |= conv ? 0 : 1;
   // singular values = column norms (every lane); rank descending, stable
   double S[NC], inv_S[NC];
@@ -938,7 +941,7 @@ struct B8Table {
 template <int W>
 __global__ __launch_bounds__(64) void mps_build8_kernel(B8Table tab, int nq, int n_layers,
                                                         int chi_max, int entangle,
-                                                        double cutoff) {
+                                                        double cutoff, int max_sweeps) {
   constexpr int D = 2 * W, TT = W * W, slot = 2 * TT;
   __shared__ Build8Smem<W> sm;
   int part = 0;
@@ -1089,13 +1092,13 @@ __global__ __launch_bounds__(64) void mps_build8_kernel(B8Table tab, int nq, int
       const double floor2 = 1e-30 * fro;
       int keep;
       if (nc <= 2)
-        keep = b8_factor<W, 2>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over, disc);
+        keep = b8_factor<W, 2>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over, disc, max_sweeps);
       else if (nc <= 4 || D <= 4)
-        keep = b8_factor<W, (D < 4 ? D : 4)>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over, disc);
+        keep = b8_factor<W, (D < 4 ? D : 4)>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over, disc, max_sweeps);
       else if (nc <= 6 || D <= 6)
-        keep = b8_factor<W, (D < 6 ? D : 6)>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over, disc);
+        keep = b8_factor<W, (D < 6 ? D : 6)>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over, disc, max_sweeps);
       else
-        keep = b8_factor<W, D>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over, disc);
+        keep = b8_factor<W, D>(xr, vr, floor2, r, XC, cl, cr, tr, l2r, chi_max, cutoff, Lo, Ro, noconv, over, disc, max_sweeps);
       if (keep > chi_seen) chi_seen = keep;
       wave_lds_sync();
       // The finished site goes to memory (the carried one too on the layer's
@@ -1178,11 +1181,13 @@ __global__ void pack32_kernel(const double2* __restrict__ a, float* __restrict__
 hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
                            int n_layers, int chi_max, int entangle,
                            double cutoff, int chi_ws, int T, double2* t64,
-                           int32_t* chi, int32_t* status, double* disc, hipStream_t s) {
+                           int32_t* chi, int32_t* status, double* disc, int max_sweeps,
+                           hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (nq >= 2 && (T == 1 || T == 2 || T == 4)) {
     const QkBuildPart part{x, ld_x, n, t64, chi, status, disc};
-    return qk_launch_build_many(&part, 1, nq, n_layers, chi_max, entangle, cutoff, chi_ws, T, s);
+    return qk_launch_build_many(&part, 1, nq, n_layers, chi_max, entangle, cutoff, chi_ws, T,
+                                max_sweeps, s);
   }
   // bond bounds of 32 and 64: one workgroup per sample, Theta of each
   // sample in a stream-ordered global workspace for the duration of the build
@@ -1194,11 +1199,11 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
     if (T == 32)
       hipLaunchKernelGGL(mps_build_wg_kernel<32>, dim3((unsigned)n),
                          dim3(BuildWgShape<32>::kThreads), 0, s, x, ld_x, n, nq, n_layers,
-                         chi_max, entangle, cutoff, t64, chi, status, ws, disc);
+                         chi_max, entangle, cutoff, t64, chi, status, ws, disc, max_sweeps);
     else
       hipLaunchKernelGGL(mps_build_wg_kernel<64>, dim3((unsigned)n),
                          dim3(BuildWgShape<64>::kThreads), 0, s, x, ld_x, n, nq, n_layers,
-                         chi_max, entangle, cutoff, t64, chi, status, ws, disc);
+                         chi_max, entangle, cutoff, t64, chi, status, ws, disc, max_sweeps);
     const hipError_t e = hipGetLastError();
     (void)hipFreeAsync(ws, s);  // stream-ordered: after the build
     return e;
@@ -1208,7 +1213,7 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
   case WV:                                                                    \
     hipLaunchKernelGGL(mps_build_kernel<WV>, grid, block, 0, s, x, ld_x, n,   \
                        nq, n_layers, chi_max, entangle, cutoff, t64, chi,     \
-                       status, disc);                                         \
+                       status, disc, max_sweeps);                             \
     break;
   switch (T) {
     QK_BUILD_CASE(1)  // a single qubit (every multi-qubit bound <= 4 takes the 8-sample kernel)
@@ -1223,14 +1228,15 @@ hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
 
 hipError_t qk_launch_build_many(const QkBuildPart* parts, int n_parts, int nq, int n_layers,
                                 int chi_max, int entangle, double cutoff, int chi_ws, int T,
-                                hipStream_t s) {
+                                int max_sweeps, hipStream_t s) {
   if (n_parts < 1 || n_parts > QK_MAX_BUILD_PARTS) return hipErrorInvalidValue;
   if (nq < 2 || !(T == 1 || T == 2 || T == 4)) {
     // one launch per part with the one-sample-per-wave kernel
     for (int k = 0; k < n_parts; ++k) {
       const QkBuildPart& p = parts[k];
       const hipError_t e = qk_launch_build(p.x, p.ld_x, p.n, nq, n_layers, chi_max, entangle,
-                                           cutoff, chi_ws, T, p.t64, p.chi, p.status, p.disc, s);
+                                           cutoff, chi_ws, T, p.t64, p.chi, p.status, p.disc,
+                                           max_sweeps, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1251,13 +1257,13 @@ hipError_t qk_launch_build_many(const QkBuildPart* parts, int n_parts, int nq, i
   const dim3 grid8((unsigned)wg), block8(64);
   switch (T) {
     case 1:
-      hipLaunchKernelGGL(mps_build8_kernel<1>, grid8, block8, 0, s, tab, nq, n_layers, chi_max, entangle, cutoff);
+      hipLaunchKernelGGL(mps_build8_kernel<1>, grid8, block8, 0, s, tab, nq, n_layers, chi_max, entangle, cutoff, max_sweeps);
       break;
     case 2:
-      hipLaunchKernelGGL(mps_build8_kernel<2>, grid8, block8, 0, s, tab, nq, n_layers, chi_max, entangle, cutoff);
+      hipLaunchKernelGGL(mps_build8_kernel<2>, grid8, block8, 0, s, tab, nq, n_layers, chi_max, entangle, cutoff, max_sweeps);
       break;
     default:
-      hipLaunchKernelGGL(mps_build8_kernel<4>, grid8, block8, 0, s, tab, nq, n_layers, chi_max, entangle, cutoff);
+      hipLaunchKernelGGL(mps_build8_kernel<4>, grid8, block8, 0, s, tab, nq, n_layers, chi_max, entangle, cutoff, max_sweeps);
       break;
   }
   (void)chi_ws;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstdint>
 #include <cmath>
@@ -210,21 +211,6 @@ qk_status fill_task(QkTask& t, const qk_mps_batch* rows, const qk_mps_batch* col
   return QK_OK;
 }
 
-// The matrix-core sweep for padded bonds 8..64 (sweep_wide.hip) is off by
-// default: a GPU memory fault or hung queue ended a run of the whole GPU
-// test suite plus the benchmark in which it ran, and no cause has been shown
-// (each of its tests had passed when run on their own, and a later fault
-// came without it). FP32 MFMA at bonds above 4 reports QK_ERR_UNSUPPORTED,
-// and complex FP64 serves those bonds, unless the process sets
-// QK_ENABLE_WIDE_MFMA=1 (read once).
-bool wide_mfma_enabled() {
-  static const bool on = [] {
-    const char* e = std::getenv("QK_ENABLE_WIDE_MFMA");
-    return e && e[0] == '1' && e[1] == '\0';
-  }();
-  return on;
-}
-
 bool supported_T(qk_precision p, int T) {
   switch (p) {
     case QK_PREC_FP64:
@@ -232,7 +218,7 @@ bool supported_T(qk_precision p, int T) {
     case QK_PREC_FP32:
       return T == 1 || T == 2 || T == 4;
     case QK_PREC_FP32_MFMA:
-      return qk_mfma_supports(p, T) || (wide_mfma_enabled() && qk_sweep_wide_supports(T));
+      return qk_mfma_supports(p, T) || qk_sweep_wide_supports(T);
     default:
       return qk_mfma_supports(p, T);
   }
@@ -369,6 +355,21 @@ int tile_for(qk_precision p) {
 
 qk_status qk_fail(qk_status s, const std::string& msg) { return fail(s, msg); }
 
+std::string qk_flag_text(int32_t flags) {
+  if (!flags) return "";
+  std::string m = "build latched:";
+  if (flags & QK_FLAG_NONFINITE) m += " non-finite feature;";
+  if (flags & QK_FLAG_CHI_OVER) m += " bond above the padded bound;";
+  if (flags & QK_FLAG_NOCONV) m += " Jacobi SVD sweep limit reached;";
+  return m;
+}
+
+namespace {
+std::atomic<int> g_svd_sweeps{kQkDefaultSvdSweeps};
+}  // namespace
+
+int qk_svd_sweep_limit() { return g_svd_sweeps.load(std::memory_order_relaxed); }
+
 void qk_mps_release_nosync(qk_mps_batch* b, hipStream_t s) {
   if (!b) return;
   free_batch_memory(b, s);
@@ -441,7 +442,7 @@ qk_status qk_mps_build(const qk_circuit_desc* c, const double* x_dev,
   b->chi_ws = ws;
   hipError_t e = qk_launch_build(x_dev, ld_x, n_samples, c->n_qubits, c->n_layers,
                                  c->chi_max, c->entangle, c->cutoff_rel, ws, T,
-                                 b->t64, b->chi, b->status, b->disc, s);
+                                 b->t64, b->chi, b->status, b->disc, qk_svd_sweep_limit(), s);
   if (e != hipSuccess) {
     qk_mps_release(b);
     return hip_fail(e, "build launch");
@@ -493,7 +494,7 @@ qk_status qk_mps_build_many(const qk_circuit_desc* c, int32_t n_inputs,
                            b[k]->disc};
   }
   hipError_t e = qk_launch_build_many(parts, n_inputs, c->n_qubits, c->n_layers, c->chi_max,
-                                      c->entangle, c->cutoff_rel, ws, T, s);
+                                      c->entangle, c->cutoff_rel, ws, T, qk_svd_sweep_limit(), s);
   if (e != hipSuccess) {
     release_all();
     return hip_fail(e, "build launch");
@@ -568,13 +569,7 @@ qk_status qk_mps_info(const qk_mps_batch* b, int64_t* n_samples, int32_t* n_qubi
   if (chi_pad) *chi_pad = b->T;
   if (chi_realized_max) *chi_realized_max = st[1];
   if (device_bytes) *device_bytes = b->bytes;
-  if (st[0]) {
-    std::string m = "build latched:";
-    if (st[0] & QK_FLAG_NONFINITE) m += " non-finite feature;";
-    if (st[0] & QK_FLAG_CHI_OVER) m += " bond above the padded bound;";
-    if (st[0] & QK_FLAG_NOCONV) m += " Jacobi SVD sweep limit reached;";
-    return fail(QK_ERR_DEVICE, m);
-  }
+  if (st[0]) return fail(QK_ERR_DEVICE, qk_flag_text(st[0]));
   return QK_OK;
 }
 
@@ -775,6 +770,13 @@ qk_status qk_tune_import(const char* text) {
   return QK_OK;
 }
 
+qk_status qk_set_svd_sweep_limit(int32_t sweeps) {
+  if (sweeps < 0 || sweeps > kQkMaxSvdSweeps)
+    return fail(QK_ERR_INVALID_ARG, "sweep limit must be in [0, 1000]");
+  g_svd_sweeps.store(sweeps, std::memory_order_relaxed);
+  return QK_OK;
+}
+
 qk_status qk_set_refine_threshold(qk_precision prec, double tau) {
   if (prec <= QK_PREC_FP64 || prec > QK_PREC_FP32_MFMA || prec == QK_PREC_AUTO)
     return fail(QK_ERR_INVALID_ARG, "refinement applies to the reduced-precision forms");
@@ -850,7 +852,8 @@ qk_status qk_pathsum_gram(const double* x_rows_dev, int64_t m, int64_t ld_xr,
     f.ld_xr = ld_xr;
     f.x_cols_dev = x_cols_dev;
     f.ld_xc = ld_xc;
-    if (!std::isfinite(f.gamma)) return fail(QK_ERR_INVALID_ARG, "gamma must be finite");
+    if (!(f.gamma >= 0.0) || !std::isfinite(f.gamma))
+      return fail(QK_ERR_INVALID_ARG, "gamma must be finite and >= 0");
     if (!f.w_rows_dev && !(f.w >= 0.0 && f.w <= 1.0))
       return fail(QK_ERR_INVALID_ARG, "w must be in [0, 1]");
     if ((f.kc_dev && f.ld_kc < n) || (f.k_dev && f.ld_k < n))

@@ -43,11 +43,23 @@ qk_status qk_fail(qk_status s, const std::string& msg);
 // enqueued work still reads it. Memory returns to the pool in stream order.
 void qk_mps_release_nosync(qk_mps_batch* b, hipStream_t s);
 
-// Kernel launchers (build.hip).
+// Jacobi sweeps a two-site SVD of the build may take before it latches
+// QK_FLAG_NOCONV (default), and the largest limit the setter accepts.
+constexpr int kQkDefaultSvdSweeps = 60;
+constexpr int kQkMaxSvdSweeps = 1000;
+
+// Text of the build's status flag bits ("" when none is set).
+std::string qk_flag_text(int32_t flags);
+// Jacobi sweep limit of the build's two-site SVDs (qk_set_svd_sweep_limit).
+int qk_svd_sweep_limit();
+
+// Kernel launchers (build.hip). A two-site SVD that has not converged after
+// max_sweeps Jacobi sweeps latches QK_FLAG_NOCONV.
 hipError_t qk_launch_build(const double* x, int64_t ld_x, int64_t n, int nq,
                            int n_layers, int chi_max, int entangle,
                            double cutoff, int chi_ws, int T, double2* t64,
-                           int32_t* chi, int32_t* status, double* disc, hipStream_t s);
+                           int32_t* chi, int32_t* status, double* disc, int max_sweeps,
+                           hipStream_t s);
 // Several feature matrices of one circuit built in one launch (bond bound
 // up to 4): one part per batch.
 struct QkBuildPart {
@@ -62,7 +74,7 @@ struct QkBuildPart {
 constexpr int QK_MAX_BUILD_PARTS = 8;
 hipError_t qk_launch_build_many(const QkBuildPart* parts, int n_parts, int nq, int n_layers,
                                 int chi_max, int entangle, double cutoff, int chi_ws, int T,
-                                hipStream_t s);
+                                int max_sweeps, hipStream_t s);
 hipError_t qk_launch_pack32(const double2* t64, float* t32, int64_t count,
                             hipStream_t s);
 

@@ -11,7 +11,9 @@
 //      ONE multi-task sweep launch (one task per d) with the fused RBF and
 //      per-row mix; where the support set carries a trained SVM, the decision
 //      values of the new rows follow on the same stream; copy each request's
-//      rows (and decision values) to pinned host memory.
+//      rows (and decision values) and each build's status words to pinned
+//      host memory. A request whose build latched a device check retires as
+//      FAILED with the check's text.
 // Submissions only touch host memory and the queue, so they never wait for
 // the GPU.
 #include <hip/hip_runtime.h>
@@ -58,6 +60,9 @@ struct Request {
   int64_t bytes = 0;           // budget reservation while admitted
   double* out_host = nullptr;  // pinned n_rows x n_support, filled by the D2H copy
   double* f_host = nullptr;    // pinned n_rows decision values (admitted with a model)
+  bool want_ln = false;        // also return ln K_q rows
+  double* ln_host = nullptr;   // pinned n_rows x n_support ln K_q (want_ln)
+  int group = -1;              // the iteration's d group (index of its build's status words)
 };
 
 struct Iteration {
@@ -68,6 +73,7 @@ struct Iteration {
   std::vector<qk_mps_batch*> batches;
   std::vector<void*> dev;     // stream-ordered device buffers
   std::vector<void*> pinned;  // host staging of features and weights
+  int32_t* status_host = nullptr;  // pinned: each d group's build status words (2 int32)
 };
 
 }  // namespace
@@ -106,14 +112,17 @@ int64_t request_bytes(const Request& r, const Support& sup) {
          + rows * d * 8 + rows * 8                                            // features, w
          + rows * ns * 8                                                      // K rows
          + tiles * 32                                                         // refinement masks
-         + (sup.coef ? rows * 8 : 0);                                         // decision values
+         + (sup.coef ? rows * 8 : 0)                                          // decision values
+         + (r.want_ln ? rows * ns * 8 : 0);                                   // ln K_q rows
 }
 
 void free_host(Request* r) {
   if (r->out_host) (void)hipHostFree(r->out_host);
   if (r->f_host) (void)hipHostFree(r->f_host);
+  if (r->ln_host) (void)hipHostFree(r->ln_host);
   r->out_host = nullptr;
   r->f_host = nullptr;
+  r->ln_host = nullptr;
 }
 
 void finish(qk_server* s, Request* r, int32_t state, const std::string& err = "") {
@@ -130,9 +139,16 @@ void retire(qk_server* s, Iteration* it) {
   for (Request* r : it->reqs) {
     s->budget_used -= r->bytes;
     r->bytes = 0;
+    // the build of the request's rows latched a device check (sweep limit,
+    // bond bound, non-finite input): its rows are not valid kernel values
+    const int32_t flags =
+        (it->status_host && r->group >= 0) ? it->status_host[2 * r->group] : 0;
     if (r->cancel) {
       free_host(r);
       finish(s, r, QK_REQ_CANCELLED);
+    } else if (flags) {
+      free_host(r);
+      finish(s, r, QK_REQ_FAILED, qk_flag_text(flags));
     } else {
       finish(s, r, QK_REQ_DONE);
     }
@@ -141,6 +157,7 @@ void retire(qk_server* s, Iteration* it) {
   for (qk_mps_batch* b : it->batches) qk_mps_release_nosync(b, st);
   for (void* p : it->dev) (void)hipFreeAsync(p, st);
   for (void* p : it->pinned) (void)hipHostFree(p);
+  if (it->status_host) (void)hipHostFree(it->status_host);
   (void)hipEventDestroy(it->done);
   s->slot_busy[it->slot] = false;
   delete it;
@@ -156,7 +173,8 @@ std::string launch(qk_server* s, Iteration* it) {
   struct Out {
     Request* r;
     double* k;
-    double* f;  // decision values of the d group, or NULL
+    double* f;   // decision values of the d group, or NULL
+    double* ln;  // ln K_q rows of the d group, or NULL
     int64_t row0;
   };
   struct Decision {
@@ -168,12 +186,20 @@ std::string launch(qk_server* s, Iteration* it) {
   };
   std::vector<Decision> decisions;
   std::vector<Out> outs;
+  if (hipHostMalloc((void**)&it->status_host, 2 * by_d.size() * sizeof(int32_t), 0) != hipSuccess)
+    return "pinned status allocation failed";
+  int group = 0;
   for (auto& kv : by_d) {
     const Support& sup = it->sups.at(kv.first);
     const int32_t d = kv.first;
     int64_t rows = 0;
-    for (Request* r : kv.second) rows += r->n_rows;
+    bool any_ln = false;
+    for (Request* r : kv.second) {
+      rows += r->n_rows;
+      any_ln = any_ln || r->want_ln;
+    }
     double *hx = nullptr, *hw = nullptr, *dx = nullptr, *dw = nullptr, *dk = nullptr;
+    double* dln = nullptr;
     if (hipHostMalloc((void**)&hx, rows * d * sizeof(double), 0) != hipSuccess ||
         hipHostMalloc((void**)&hw, rows * sizeof(double), 0) != hipSuccess)
       return "pinned staging allocation failed";
@@ -192,6 +218,11 @@ std::string launch(qk_server* s, Iteration* it) {
     it->dev.push_back(dx);
     it->dev.push_back(dw);
     it->dev.push_back(dk);
+    if (any_ln) {
+      if (hipMallocAsync((void**)&dln, rows * sup.n * sizeof(double), st) != hipSuccess)
+        return "device allocation for an iteration failed";
+      it->dev.push_back(dln);
+    }
     if (hipMemcpyAsync(dx, hx, rows * d * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(dw, hw, rows * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
       return "feature upload failed";
@@ -204,6 +235,8 @@ std::string launch(qk_server* s, Iteration* it) {
     t.rows = mb;
     t.cols = sup.mps;
     t.symmetric = 0;
+    t.lnkq_dev = dln;
+    t.ld_ln = sup.n;
     t.use_fuse = 1;
     t.fuse.x_rows_dev = dx;
     t.fuse.ld_xr = d;
@@ -224,15 +257,22 @@ std::string launch(qk_server* s, Iteration* it) {
     }
     off = 0;
     for (Request* r : kv.second) {
-      outs.push_back({r, dk, df, off});
+      outs.push_back({r, dk, df, r->want_ln ? dln : nullptr, off});
+      r->group = group;
       off += r->n_rows;
     }
+    ++group;
   }
   qk_status gs = qk_overlap_gram_multi(tasks.data(), (int32_t)tasks.size(), s->cfg.prec, st);
   if (gs != QK_OK) return std::string("sweep launch failed: ") + qk_last_error();
   for (const Decision& dc : decisions)
     if (qk_launch_svm_decision(dc.k, dc.rows, dc.n, dc.n, dc.coef, dc.b, dc.f, st) != hipSuccess)
       return "decision launch failed";
+  // each group's build status, read at retirement (the build runs on this stream)
+  for (size_t g = 0; g < it->batches.size(); ++g)
+    if (hipMemcpyAsync(it->status_host + 2 * g, it->batches[g]->status, 2 * sizeof(int32_t),
+                       hipMemcpyDeviceToHost, st) != hipSuccess)
+      return "status download failed";
   for (const Out& o : outs) {
     const int64_t bytes = o.r->n_rows * o.r->n_support * (int64_t)sizeof(double);
     if (hipMemcpyAsync(o.r->out_host, o.k + o.row0 * o.r->n_support, bytes,
@@ -242,6 +282,9 @@ std::string launch(qk_server* s, Iteration* it) {
     if (o.f && o.r->f_host &&
         hipMemcpyAsync(o.r->f_host, o.f + o.row0, o.r->n_rows * sizeof(double),
                        hipMemcpyDeviceToHost, st) != hipSuccess)
+      return "result download failed";
+    if (o.ln && hipMemcpyAsync(o.r->ln_host, o.ln + o.row0 * o.r->n_support, bytes,
+                               hipMemcpyDeviceToHost, st) != hipSuccess)
       return "result download failed";
   }
   if (hipEventCreateWithFlags(&it->done, hipEventDisableTiming) != hipSuccess ||
@@ -299,7 +342,9 @@ void worker_main(qk_server* s) {
         if ((!r->out_host &&
              hipHostMalloc((void**)&r->out_host, r->n_rows * sup.n * sizeof(double), 0) != hipSuccess) ||
             (sup.coef && !r->f_host &&
-             hipHostMalloc((void**)&r->f_host, r->n_rows * sizeof(double), 0) != hipSuccess)) {
+             hipHostMalloc((void**)&r->f_host, r->n_rows * sizeof(double), 0) != hipSuccess) ||
+            (r->want_ln && !r->ln_host &&
+             hipHostMalloc((void**)&r->ln_host, r->n_rows * sup.n * sizeof(double), 0) != hipSuccess)) {
           free_host(r);
           s->pending.pop_front();
           finish(s, r, QK_REQ_FAILED, "pinned result allocation failed");
@@ -469,7 +514,13 @@ qk_status qk_server_set_model(qk_server* s, int32_t d, const double* coef_host, 
 
 qk_status qk_server_submit(qk_server* s, const double* x_host, int64_t n_rows, int32_t d,
                            double w, int64_t* id) {
+  return qk_server_submit_ex(s, x_host, n_rows, d, w, 0u, id);
+}
+
+qk_status qk_server_submit_ex(qk_server* s, const double* x_host, int64_t n_rows, int32_t d,
+                              double w, uint32_t outputs, int64_t* id) {
   if (!s || !x_host || !id || n_rows < 1) return qk_fail(QK_ERR_INVALID_ARG, "bad request");
+  if (outputs & ~(uint32_t)QK_OUT_LNKQ) return qk_fail(QK_ERR_INVALID_ARG, "unknown output flag");
   if (!(w >= 0.0 && w <= 1.0)) return qk_fail(QK_ERR_INVALID_ARG, "w must be in [0, 1]");
   for (int64_t k = 0; k < n_rows * (int64_t)d; ++k)
     if (!std::isfinite(x_host[k])) return qk_fail(QK_ERR_INVALID_ARG, "non-finite feature");
@@ -477,6 +528,7 @@ qk_status qk_server_submit(qk_server* s, const double* x_host, int64_t n_rows, i
   r->d = d;
   r->n_rows = n_rows;
   r->w = w;
+  r->want_ln = (outputs & QK_OUT_LNKQ) != 0;
   r->x.assign(x_host, x_host + n_rows * (int64_t)d);
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -500,6 +552,11 @@ qk_status qk_server_submit(qk_server* s, const double* x_host, int64_t n_rows, i
 
 qk_status qk_server_poll_decision(qk_server* s, int64_t id, double* rows_host, int64_t ld_rows,
                                   double* f_host, int32_t* state) {
+  return qk_server_poll_ex(s, id, rows_host, ld_rows, f_host, nullptr, 0, state);
+}
+
+qk_status qk_server_poll_ex(qk_server* s, int64_t id, double* rows_host, int64_t ld_rows,
+                            double* f_host, double* ln_host, int64_t ld_ln, int32_t* state) {
   if (!s || !state) return qk_fail(QK_ERR_INVALID_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(s->mu);
   auto f = s->reqs.find(id);
@@ -507,15 +564,23 @@ qk_status qk_server_poll_decision(qk_server* s, int64_t id, double* rows_host, i
   Request* r = f->second;
   *state = r->state;
   if (r->state == QK_REQ_FAILED) return qk_fail(QK_OK, r->err);
-  const bool fetch = rows_host || f_host;
+  const bool fetch = rows_host || f_host || ln_host;
   if (r->state == QK_REQ_DONE && fetch) {
     if (rows_host && ld_rows < r->n_support)
       return qk_fail(QK_ERR_INVALID_ARG, "ld_rows < support size");
+    if (ln_host && ld_ln < r->n_support)
+      return qk_fail(QK_ERR_INVALID_ARG, "ld_ln < support size");
     if (f_host && !r->f_host)
       return qk_fail(QK_ERR_INVALID_ARG, "the request was admitted without a model");
+    if (ln_host && !r->ln_host)
+      return qk_fail(QK_ERR_INVALID_ARG, "the request did not ask for ln K_q rows");
     if (rows_host)
       for (int64_t q = 0; q < r->n_rows; ++q)
         std::memcpy(rows_host + q * ld_rows, r->out_host + q * r->n_support,
+                    r->n_support * sizeof(double));
+    if (ln_host)
+      for (int64_t q = 0; q < r->n_rows; ++q)
+        std::memcpy(ln_host + q * ld_ln, r->ln_host + q * r->n_support,
                     r->n_support * sizeof(double));
     if (f_host) std::memcpy(f_host, r->f_host, r->n_rows * sizeof(double));
     free_host(r);

@@ -99,6 +99,8 @@ _lib.qk_svm_predict_ovo.argtypes = [_P, C.c_int64, C.c_int64, C.c_int64, _P, C.c
 _lib.qk_svm_predict_ovo.restype = C.c_int
 _lib.qk_resolve_precision.argtypes = [_P, _P, C.POINTER(C.c_int)]
 _lib.qk_set_refine_threshold.argtypes = [C.c_int, C.c_double]
+_lib.qk_set_svd_sweep_limit.argtypes = [C.c_int32]
+_lib.qk_set_svd_sweep_limit.restype = C.c_int
 _lib.qk_set_launch_timing.argtypes = [C.c_int32]
 _lib.qk_last_launch_ms.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float)]
 for _f in ("qk_set_launch_timing", "qk_last_launch_ms"):
@@ -129,6 +131,9 @@ _lib.qk_server_poll.argtypes = [_P, C.c_int64, _P, C.c_int64, C.POINTER(C.c_int3
 _lib.qk_server_set_model.argtypes = [_P, C.c_int32, _P, C.c_int64, C.c_double]
 _lib.qk_server_poll_decision.argtypes = [_P, C.c_int64, _P, C.c_int64, _P,
                                          C.POINTER(C.c_int32)]
+_lib.qk_server_submit_ex.argtypes = [_P, _P, C.c_int64, C.c_int32, C.c_double, C.c_uint32, _I64P]
+_lib.qk_server_poll_ex.argtypes = [_P, C.c_int64, _P, C.c_int64, _P, _P, C.c_int64,
+                                   C.POINTER(C.c_int32)]
 _lib.qk_server_wait.argtypes = [_P, C.c_int64, C.c_int32, C.POINTER(C.c_int32)]
 _lib.qk_server_cancel.argtypes = [_P, C.c_int64]
 _lib.qk_server_request_times.argtypes = [_P, C.c_int64, C.POINTER(C.c_double),
@@ -137,17 +142,19 @@ _lib.qk_server_stats.argtypes = [_P, _I64P, _I64P, _I64P, _I64P]
 _lib.qk_server_destroy.argtypes = [_P]
 for _f in ("qk_server_create", "qk_server_load_support", "qk_server_submit", "qk_server_poll",
            "qk_server_set_model", "qk_server_poll_decision", "qk_server_wait", "qk_server_cancel", "qk_server_request_times", "qk_server_stats",
-           "qk_server_destroy"):
+           "qk_server_destroy", "qk_server_submit_ex", "qk_server_poll_ex"):
     getattr(_lib, _f).restype = C.c_int
 
 QK_REQ_QUEUED, QK_REQ_RUNNING, QK_REQ_DONE, QK_REQ_FAILED, QK_REQ_CANCELLED = 0, 1, 2, 3, 4
+QK_OUT_LNKQ = 1
 
 EXPORTED = ["qk_server_create", "qk_server_load_support", "qk_server_submit",
+            "qk_server_submit_ex", "qk_server_poll_ex",
             "qk_server_poll", "qk_server_set_model", "qk_server_poll_decision", "qk_server_wait", "qk_server_cancel", "qk_server_request_times",
             "qk_server_stats", "qk_server_destroy",
             "qk_mps_build", "qk_mps_build_many", "qk_mps_import", "qk_mps_info", "qk_mps_chi",
             "qk_mps_discarded", "qk_mps_release", "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
-            "qk_svm_decision", "qk_pathsum_gram", "qk_svm_fit_ovo", "qk_svm_predict_ovo", "qk_resolve_precision", "qk_set_refine_threshold", "qk_autotune",
+            "qk_svm_decision", "qk_pathsum_gram", "qk_svm_fit_ovo", "qk_svm_predict_ovo", "qk_resolve_precision", "qk_set_refine_threshold", "qk_set_svd_sweep_limit", "qk_autotune",
             "qk_tune_export", "qk_tune_import", "qk_status_string",
             "qk_last_error", "qk_set_launch_timing", "qk_last_launch_ms"]
 
@@ -435,6 +442,11 @@ def qk_set_refine_threshold(prec, tau: float):
     _check(_lib.qk_set_refine_threshold(p, float(tau)))
 
 
+def qk_set_svd_sweep_limit(sweeps: int):
+    """Jacobi sweep limit of the build's two-site SVDs (default 60)."""
+    _check(_lib.qk_set_svd_sweep_limit(int(sweeps)))
+
+
 def qk_set_launch_timing(enable: bool):
     """Record HIP events around the sweep and refinement launches of later calls."""
     _check(_lib.qk_set_launch_timing(1 if enable else 0))
@@ -530,6 +542,35 @@ def qk_server_submit(server: Server, x_rows: np.ndarray, w: float) -> int:
     _check(_lib.qk_server_submit(server.handle, x.ctypes.data_as(C.c_void_p), x.shape[0],
                                  x.shape[1], float(w), C.byref(rid)))
     return rid.value
+
+
+def qk_server_submit_ex(server: Server, x_rows: np.ndarray, w: float, outputs: int = 0) -> int:
+    """As qk_server_submit; outputs = QK_OUT_LNKQ also returns ln K_q rows."""
+    x = np.ascontiguousarray(x_rows, dtype=np.float64)
+    if x.ndim != 2:
+        raise ValueError("x_rows must be 2-D")
+    rid = C.c_int64()
+    _check(_lib.qk_server_submit_ex(server.handle, x.ctypes.data_as(C.c_void_p), x.shape[0],
+                                    x.shape[1], float(w), int(outputs), C.byref(rid)))
+    return rid.value
+
+
+def qk_server_poll_ex(server: Server, rid: int, rows: np.ndarray | None = None,
+                      ln: np.ndarray | None = None, f: np.ndarray | None = None) -> int:
+    """Fetches whichever of rows (K), ln (ln K_q) and f (decision values) are
+    given, and releases the request, when it is DONE; returns the state."""
+    st = C.c_int32()
+    args = []
+    for a in (rows, ln):
+        if a is not None and (a.dtype != np.float64 or not a.flags.c_contiguous or a.ndim != 2):
+            raise TypeError("row outputs must be C-contiguous 2-D float64 arrays")
+        args += [None, 0] if a is None else [a.ctypes.data_as(C.c_void_p), a.shape[1]]
+    if f is not None and (f.dtype != np.float64 or not f.flags.c_contiguous):
+        raise TypeError("f must be a C-contiguous float64 array")
+    fp = None if f is None else f.ctypes.data_as(C.c_void_p)
+    _check(_lib.qk_server_poll_ex(server.handle, rid, args[0], args[1], fp, args[2], args[3],
+                                  C.byref(st)))
+    return st.value
 
 
 def qk_server_poll(server: Server, rid: int, out: np.ndarray | None = None):

@@ -93,3 +93,23 @@ def test_argument_checks_of_the_svm_and_path_sum_entry_points_without_gpu():
                                None) == INVALID  # symmetric with different features
     assert lib.qk_pathsum_gram(fake, 4, 7, fake, 4, 7, 8, 2, 1, 0, None, 0, ln, 4, None,
                                None) == INVALID  # leading dimension below d
+
+
+def test_pathsum_rejects_a_negative_gamma_and_sweep_limit_range():
+    """A fused path-sum call with gamma < 0 would give K_c > 1 (outside the
+    kernel range of Eq. (3)); it is rejected before any launch, as the MPS
+    route's fusion and qk_rbf_gram do. The SVD sweep limit accepts [0, 1000]."""
+    from paper_2602_01330_amd.qk import qk_fuse_desc
+    lib = ctypes.CDLL(LIB)
+    P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.qk_pathsum_gram.argtypes = [P, I64, I64, P, I64, I64, I32, I32, I32, I32, P, I64, P,
+                                    I64, ctypes.POINTER(qk_fuse_desc), P]
+    fake = P(0x1000)
+    for gamma, want in ((-0.5, -1), (float("nan"), -1), (float("inf"), -1)):
+        f = qk_fuse_desc(gamma=gamma, w=0.5, k_dev=0x3000, ld_k=4)
+        assert lib.qk_pathsum_gram(fake, 4, 8, fake, 4, 8, 8, 2, 1, 1, None, 0, None, 0,
+                                   ctypes.byref(f), None) == want
+    lib.qk_set_svd_sweep_limit.argtypes = [I32]
+    assert lib.qk_set_svd_sweep_limit(-1) == -1
+    assert lib.qk_set_svd_sweep_limit(1001) == -1
+    assert lib.qk_set_svd_sweep_limit(60) == 0

@@ -70,10 +70,6 @@ def test_c3_full_gram_sampled(prec, ln_tol):
     assert np.array_equal(np.diag(kc), np.ones(4000))
 
 
-@pytest.mark.skipif(os.environ.get("QK_ENABLE_WIDE_MFMA") != "1",
-                    reason="the matrix-core sweep for bonds above 4 is off unless "
-                           "QK_ENABLE_WIDE_MFMA=1: a GPU fault ended a whole-suite run it was "
-                           "part of and its cause has not been shown")
 def test_chi64_sweep_784_sites_sampled():
     """The sweep at the truncating regime's full shape: 784 sites with every
     interior bond at 64 (random left-canonical MPS, 4 row and 8 column

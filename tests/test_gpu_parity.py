@@ -331,17 +331,11 @@ def test_large_bond_sweep_on_oracle_mps(qk, d, L, chi_max, T):
     _, LN2 = mps.gram(mps.pad_batch(MY), mps.pad_batch(MX))
     assert np.abs(ln_s.cpu().numpy() - LN).max() < 1e-8
     assert np.abs(ln_r.cpu().numpy() - LN2).max() < 1e-8
-    for form in ("fp32", "bf16x3") + (() if WIDE_ON else ("fp32_mfma",)):
+    for form in ("fp32", "bf16x3"):
         with pytest.raises(qk.QkError):
             qk.qk_overlap_gram(bx, bx, True, form, None, ln_s)
 
 
-WIDE_ON = os.environ.get("QK_ENABLE_WIDE_MFMA") == "1"
-WIDE_OFF = ("the matrix-core sweep for bonds above 4 is off unless QK_ENABLE_WIDE_MFMA=1: a GPU "
-            "fault ended a whole-suite run it was part of and its cause has not been shown")
-
-
-@pytest.mark.skipif(not WIDE_ON, reason=WIDE_OFF)
 @pytest.mark.parametrize("d,L,chi_max,T", [(8, 3, 64, 8), (10, 4, 64, 16), (12, 5, 64, 32),
                                            (14, 8, 64, 64), (40, 8, 64, 64)])
 def test_large_bond_mfma_sweep_on_oracle_mps(qk, d, L, chi_max, T):
