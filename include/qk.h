@@ -227,6 +227,31 @@ QK_API qk_status qk_overlap_gram(const qk_mps_batch* rows, const qk_mps_batch* c
                           const qk_fuse_desc* fuse, void* hip_stream);
 
 /*
+ * qk_overlap_gram_noalloc -- qk_overlap_gram for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. Same arguments, results and errors as
+ * qk_overlap_gram (the same kernels run), but the refinement masks and pair
+ * lists live in a static device array of QK_NOALLOC_SCRATCH_BYTES per GPU
+ * (held from the first call on that GPU until the process ends) instead of
+ * stream-ordered allocations; the call makes no hipMalloc / hipFree.
+ * The scratch needed is 4 (9 t + 1) bytes for t 16 x 16 pair tiles under a
+ * reduced form at chi_pad <= 4 (t = T(T+1)/2 of T = ceil(n/16) tile rows when
+ * symmetric, else the product of the two tile counts), 8 (pairs + 1) bytes
+ * for QK_PREC_FP32_MFMA at chi_pad 8..64, none for QK_PREC_FP64. A call that
+ * needs more returns INVALID_ARG before anything is enqueued. All calls on
+ * one GPU share its array, and the scratch is fully written before it is
+ * read within a call, so calls in stream order are independent; calls that
+ * overlap on one GPU (different streams, or host threads) race on it and
+ * must be serialised by the caller. The stream must belong to the current
+ * device.
+ */
+#define QK_NOALLOC_SCRATCH_BYTES (16 << 20)
+QK_API qk_status qk_overlap_gram_noalloc(const qk_mps_batch* rows, const qk_mps_batch* cols,
+                                         int32_t symmetric, qk_precision prec, double* kq_dev,
+                                         int64_t ld_kq, double* lnkq_dev, int64_t ld_ln,
+                                         const qk_fuse_desc* fuse, void* hip_stream);
+
+/*
  * One Gram block in a ragged multi-task launch: uneven qubit counts and
  * bond dimensions share one persistent launch. Fields as in
  * qk_overlap_gram.

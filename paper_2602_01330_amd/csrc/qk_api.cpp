@@ -68,6 +68,38 @@ int device_cus() {
   return cus;
 }
 
+// Device scratch of qk_overlap_gram_noalloc: refinement masks of the tile
+// sweeps and pair lists of the large-bond sweep. Every GPU the library runs
+// on holds its own copy until the process ends. In host code the name is a
+// host-side stand-in, so launches use the address that hipGetSymbolAddress
+// reports for each device.
+constexpr int64_t kNoAllocScratchBytes = QK_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+struct ScratchAddr {
+  std::once_flag once;
+  void* ptr = nullptr;
+  hipError_t err = hipSuccess;
+};
+ScratchAddr g_scratch_addr[kMaxDevices];
+
+// The current device's copy of `scratch` (looked up once per device, with
+// that device current).
+hipError_t noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  ScratchAddr& a = g_scratch_addr[dev];
+  std::call_once(a.once, [&a] {
+    a.err = hipGetSymbolAddress(&a.ptr, HIP_SYMBOL(scratch));
+    if (a.err == hipSuccess && !a.ptr) a.err = hipErrorInvalidSymbol;
+  });
+  *out = a.ptr;
+  return a.err;
+}
+
 qk_status check_desc(const qk_circuit_desc* c) {
   if (!c) return fail(QK_ERR_INVALID_ARG, "circuit descriptor is NULL");
   if (c->n_qubits < 1) return fail(QK_ERR_INVALID_ARG, "n_qubits must be >= 1");
@@ -244,8 +276,16 @@ void timing_mark(int which, hipStream_t s) {
   if (g_timing.enabled) (void)hipEventRecord(g_timing.ev[which], s);
 }
 
+// Caller-provided device scratch (the allocation-free entry point): the
+// refinement masks and lists then live there instead of in stream-ordered
+// allocations. Launches of one call run in stream order, so they reuse it.
+struct Scratch {
+  void* ptr = nullptr;
+  int64_t bytes = 0;
+};
+
 qk_status run_tasks(std::vector<QkTask>& tasks_in, qk_precision prec, double tau, hipStream_t s,
-                    int64_t max_tiles = -1) {
+                    int64_t max_tiles = -1, const Scratch* scratch = nullptr) {
   // tasks with bonds above 4 go to the per-pair kernels (one workgroup per
   // pair: complex FP64 on VALU, or complex FP32 on the matrix cores); the
   // tile kernels take the others
@@ -270,6 +310,23 @@ qk_status run_tasks(std::vector<QkTask>& tasks_in, qk_precision prec, double tau
   g_timing.recorded = false;  // set once this call's events are all recorded
   g_timing.refined = false;
   if (acc == 0 && big.empty()) return QK_OK;
+  if (scratch) {
+    // everything this call keeps on the device, checked before any launch
+    int64_t need = 0;
+    if (prec != QK_PREC_FP64 && tau > 0.0 && acc > 0)
+      need = (acc * (kQkMaskWords + 1) + 1) * (int64_t)sizeof(uint32_t);
+    if (prec == QK_PREC_FP32_MFMA && tau > 0.0)
+      for (int T : {64, 32, 16, 8}) {
+        int64_t pairs = 0;
+        for (const QkTask& t : big)
+          if (t.T == T) pairs += t.symmetric ? t.na * (t.na + 1) / 2 : t.na * t.nb;
+        if (pairs > 0) need = std::max<int64_t>(need, (pairs + 1) * (int64_t)sizeof(int64_t));
+      }
+    if (need > scratch->bytes)
+      return fail(QK_ERR_INVALID_ARG,
+                  "the call needs " + std::to_string(need) + " bytes of refinement scratch; the "
+                  "allocation-free entry point has " + std::to_string(scratch->bytes));
+  }
   // persistent workgroups per CU: from the tuning table, else per form
   QkTuneEntry te;
   const bool tuned =
@@ -287,7 +344,8 @@ qk_status run_tasks(std::vector<QkTask>& tasks_in, qk_precision prec, double tau
              "large-bond sweep launch");
     else if (prec == QK_PREC_FP32_MFMA)
       QK_HIP(qk_launch_sweep_wide(group.data(), (int)group.size(), device_cus(),
-                                  tau > 0.0 ? std::log(tau) : 0.0, tau > 0.0, s),
+                                  tau > 0.0 ? std::log(tau) : 0.0, tau > 0.0,
+                                  scratch ? static_cast<int64_t*>(scratch->ptr) : nullptr, s),
              "large-bond matrix-core sweep launch");
     else
       return fail(QK_ERR_UNSUPPORTED, "no sweep of this form for bonds above 4");
@@ -314,8 +372,11 @@ qk_status run_tasks(std::vector<QkTask>& tasks_in, qk_precision prec, double tau
   int32_t* marked = nullptr;
   int32_t* n_marked = nullptr;
   if (refine) {
-    QK_HIP(hipMallocAsync((void**)&flags, (acc * (kQkMaskWords + 1) + 1) * sizeof(uint32_t), s),
-           "refinement mask allocation");
+    if (scratch)
+      flags = static_cast<uint32_t*>(scratch->ptr);
+    else
+      QK_HIP(hipMallocAsync((void**)&flags, (acc * (kQkMaskWords + 1) + 1) * sizeof(uint32_t), s),
+             "refinement mask allocation");
     marked = reinterpret_cast<int32_t*>(flags + acc * kQkMaskWords);
     n_marked = marked + acc;
     QK_HIP(qk_launch_zero_i32(n_marked, 1, s), "refinement counter reset");
@@ -341,7 +402,7 @@ qk_status run_tasks(std::vector<QkTask>& tasks_in, qk_precision prec, double tau
     e = qk_launch_refine_fp64(t64, grid64, flags, marked, n_marked, s);
   }
   timing_mark(2, s);
-  if (refine) (void)hipFreeAsync(flags, s);
+  if (refine && !scratch) (void)hipFreeAsync(flags, s);
   if (e != hipSuccess) return hip_fail(e, "sweep launch");
   g_timing.recorded = g_timing.enabled;
   return QK_OK;
@@ -672,6 +733,34 @@ qk_status qk_overlap_gram_multi(const qk_gram_task* tasks, int32_t n_tasks,
     QK_HIP(hipStreamWaitEvent(s, tasks[k].cols->ready, 0), "wait for column batch");
   }
   return run_tasks(tv, prec, tau, s);
+}
+
+qk_status qk_overlap_gram_noalloc(const qk_mps_batch* rows, const qk_mps_batch* cols,
+                                  int32_t symmetric, qk_precision prec, double* kq_dev,
+                                  int64_t ld_kq, double* lnkq_dev, int64_t ld_ln,
+                                  const qk_fuse_desc* fuse, void* hip_stream) {
+  if (!rows || !cols) return fail(QK_ERR_INVALID_ARG, "batch is NULL");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (prec == QK_PREC_AUTO) {
+    qk_status st = qk_resolve_precision(rows, cols, &prec);
+    if (st != QK_OK) return st;
+  }
+  if (prec < QK_PREC_FP64 || prec > QK_PREC_FP32_MFMA || prec == QK_PREC_AUTO)
+    return fail(QK_ERR_INVALID_ARG, "unknown precision");
+  std::vector<QkTask> tv(1);
+  const double tau = prec == QK_PREC_FP64 ? 0.0 : refine_tau(prec);
+  qk_status st = fill_task(tv[0], rows, cols, symmetric, prec == QK_PREC_FP64, tau > 0.0, kq_dev,
+                           ld_kq, lnkq_dev, ld_ln, fuse, tile_for(prec));
+  if (st != QK_OK) return st;
+  if (!supported_T(prec, tv[0].T))
+    return fail(QK_ERR_UNSUPPORTED, "chi_pad " + std::to_string(tv[0].T) +
+                                        " is not supported by this sweep form");
+  Scratch scr;
+  QK_HIP(noalloc_scratch(&scr.ptr), "address of the device scratch");
+  scr.bytes = kNoAllocScratchBytes;
+  QK_HIP(hipStreamWaitEvent(s, rows->ready, 0), "wait for row batch");
+  QK_HIP(hipStreamWaitEvent(s, cols->ready, 0), "wait for column batch");
+  return run_tasks(tv, prec, tau, s, -1, &scr);
 }
 
 qk_status qk_autotune(const qk_mps_batch* rows, const qk_mps_batch* cols, int32_t symmetric,

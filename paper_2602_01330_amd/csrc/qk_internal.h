@@ -186,10 +186,11 @@ hipError_t qk_launch_sweep_big_list(const QkTask* tasks, int n_tasks, const int6
 // Complex-FP32 matrix-core sweep for the same bond dimensions (sweep_wide.hip):
 // packed FP32 tensors, one launch per bond dimension, every pair. With
 // `refine`, pairs whose ln K_q >= ln_tau are then recomputed by the FP64
-// list sweep from the tasks' ta64/tb64.
+// list sweep from the tasks' ta64/tb64. The list (pairs + 1 int64 words) is
+// a stream-ordered allocation, or list_scratch when that is not NULL.
 bool qk_sweep_wide_supports(int T);
 hipError_t qk_launch_sweep_wide(const QkTask* tasks, int n_tasks, int cus, double ln_tau,
-                                bool refine, hipStream_t s);
+                                bool refine, int64_t* list_scratch, hipStream_t s);
 
 constexpr int kQkMaskWords = 8;
 hipError_t qk_launch_sweep_fp64(const QkTaskTable& tt, int grid, const uint32_t* mask_in,

@@ -279,7 +279,7 @@ hipError_t launch_wide(const QkPairTable& tab, int64_t pairs, int cus, int per_c
 bool qk_sweep_wide_supports(int T) { return T == 8 || T == 16 || T == 32 || T == 64; }
 
 hipError_t qk_launch_sweep_wide(const QkTask* tasks, int n_tasks, int cus, double ln_tau,
-                                bool refine, hipStream_t s) {
+                                bool refine, int64_t* list_scratch, hipStream_t s) {
   if (n_tasks < 1) return hipErrorInvalidValue;
   const int T = tasks[0].T;  // one launch per bond dimension
   QkPairTable tab{};
@@ -291,12 +291,16 @@ hipError_t qk_launch_sweep_wide(const QkTask* tasks, int n_tasks, int cus, doubl
   int32_t* count = nullptr;
   hipError_t e;
   if (refine) {
-    e = hipMallocAsync((void**)&list, pairs * sizeof(int64_t) + sizeof(int64_t), s);
-    if (e != hipSuccess) return e;
+    if (list_scratch) {
+      list = list_scratch;  // the caller sized it for pairs + 1 words
+    } else {
+      e = hipMallocAsync((void**)&list, pairs * sizeof(int64_t) + sizeof(int64_t), s);
+      if (e != hipSuccess) return e;
+    }
     count = reinterpret_cast<int32_t*>(list + pairs);
     e = qk_launch_zero_i32(count, 1, s);
     if (e != hipSuccess) {
-      (void)hipFreeAsync(list, s);
+      if (!list_scratch) (void)hipFreeAsync(list, s);
       return e;
     }
   }
@@ -317,6 +321,6 @@ hipError_t qk_launch_sweep_wide(const QkTask* tasks, int n_tasks, int cus, doubl
     }
     e = qk_launch_sweep_big_list(t64, n_tasks, list, count, cus, s);
   }
-  if (list) (void)hipFreeAsync(list, s);
+  if (list && !list_scratch) (void)hipFreeAsync(list, s);
   return e;
 }

@@ -81,6 +81,9 @@ _lib.qk_mps_release.argtypes = [_P]
 _lib.qk_overlap_gram.argtypes = [_P, _P, C.c_int32, C.c_int, _P, C.c_int64, _P, C.c_int64,
                                  C.POINTER(qk_fuse_desc), _P]
 _lib.qk_overlap_gram_multi.argtypes = [C.POINTER(qk_gram_task), C.c_int32, C.c_int, _P]
+_lib.qk_overlap_gram_noalloc.argtypes = [_P, _P, C.c_int32, C.c_int, _P, C.c_int64, _P,
+                                         C.c_int64, C.POINTER(qk_fuse_desc), _P]
+_lib.qk_overlap_gram_noalloc.restype = C.c_int
 _lib.qk_rbf_gram.argtypes = [_P, C.c_int64, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int32,
                              C.c_double, _P, C.c_int64, _P]
 _lib.qk_dual_mix.argtypes = [_P, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int64, C.c_double,
@@ -153,7 +156,8 @@ EXPORTED = ["qk_server_create", "qk_server_load_support", "qk_server_submit",
             "qk_server_poll", "qk_server_set_model", "qk_server_poll_decision", "qk_server_wait", "qk_server_cancel", "qk_server_request_times",
             "qk_server_stats", "qk_server_destroy",
             "qk_mps_build", "qk_mps_build_many", "qk_mps_import", "qk_mps_info", "qk_mps_chi",
-            "qk_mps_discarded", "qk_mps_release", "qk_overlap_gram", "qk_overlap_gram_multi", "qk_rbf_gram", "qk_dual_mix",
+            "qk_mps_discarded", "qk_mps_release", "qk_overlap_gram", "qk_overlap_gram_multi",
+            "qk_overlap_gram_noalloc", "qk_rbf_gram", "qk_dual_mix",
             "qk_svm_decision", "qk_pathsum_gram", "qk_svm_fit_ovo", "qk_svm_predict_ovo", "qk_resolve_precision", "qk_set_refine_threshold", "qk_set_svd_sweep_limit", "qk_autotune",
             "qk_tune_export", "qk_tune_import", "qk_status_string",
             "qk_last_error", "qk_set_launch_timing", "qk_last_launch_ms"]
@@ -318,6 +322,20 @@ def qk_overlap_gram(rows: MpsBatch, cols: MpsBatch, symmetric=False, prec="auto"
     _check(_lib.qk_overlap_gram(rows.handle, cols.handle, 1 if symmetric else 0, p, kp, ldk,
                                 lp, ldl, C.byref(f) if f is not None else None,
                                 _stream(stream)))
+    return kq, lnkq
+
+
+def qk_overlap_gram_noalloc(rows: MpsBatch, cols: MpsBatch, symmetric=False, prec="auto",
+                            kq=None, lnkq=None, fuse=None, stream=None):
+    """qk_overlap_gram on the library's static device scratch (no device
+    allocation in the call); returns (kq, lnkq)."""
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    kp, ldk = _opt(kq, "kq")
+    lp, ldl = _opt(lnkq, "lnkq")
+    f = _fuse(fuse)
+    _check(_lib.qk_overlap_gram_noalloc(rows.handle, cols.handle, 1 if symmetric else 0, p, kp,
+                                        ldk, lp, ldl, C.byref(f) if f is not None else None,
+                                        _stream(stream)))
     return kq, lnkq
 
 
