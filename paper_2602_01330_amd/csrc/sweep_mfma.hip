@@ -612,8 +612,11 @@ __device__ inline void m4_step_r_b(const float (&e)[2][4], const float3 (&wb)[2]
 }
 
 // Per-wave staging slot of the row operand: 4 rows x 32 elements (s, a, x)
-// of one site, each element padded to 16 bytes for aligned b128 reads.
-constexpr int kM4StRow = 32 * 4;  // floats per staged row
+// of one site, each element padded to 16 bytes for aligned b128 reads. Rows
+// are 64 bytes further apart than their 512 bytes, so the four rows' elements
+// that one read instruction gathers (row pp, element x, for every pp and x)
+// start on different LDS banks.
+constexpr int kM4StRow = 32 * 4 + 16;  // floats per staged row
 struct M4Smem {
   union {
     alignas(16) double xs[32 * kXStride];   // feature rows of the tile (fused RBF, after the sweep)
@@ -728,7 +731,8 @@ __device__ void run_tile_m4(const QkTask& t, int ti, int tj, M4Smem& sm, uint32_
   __builtin_amdgcn_sched_barrier(0);
   fetch_b(0);
   __builtin_amdgcn_sched_barrier(0);
-  for (int k = 0; k < nq; ++k) {
+  // one site: E <- sum_s A^{s dagger} E B^s for every pair of the wave
+  auto site = [&](int k) {
     const int kn = k + 1 < nq ? k + 1 : k;
     // this site's row operand: staged elements to the slot, the next site's
     // staging loads in flight over the whole site, the lane's 8 elements
@@ -767,37 +771,46 @@ __device__ void run_tile_m4(const QkTask& t, int ti, int tj, M4Smem& sm, uint32_
               en[y][cp] = __builtin_amdgcn_mfma_f32_4x4x1f32(g[y][s][cin][a],
                                                              lhat(va[s][a], cp, cin), en[y][cp],
                                                              0, 0, 0);
-    if ((k % kRescaleEvery) == kRescaleEvery - 1) {
-      // power-of-two rescale of each pair (a block's four lanes), at the same
-      // sites for every pair, so that a pair's result does not depend on its
-      // position in the launch (the scale is exact except for entries in the
-      // subnormal range)
-#pragma unroll
-      for (int y = 0; y < NB; ++y) {
-        float lm = 0.f;
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) lm = __builtin_elementwise_maximum(lm, fabsf(en[y][c][b]));
-        unsigned m = __float_as_uint(lm);
-        m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0xB1, 0xF, 0xF, false));
-        m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0x4E, 0xF, 0xF, false));
-        const unsigned ex = m >> 23;
-        const float sc = rescale_factor(ex);
-        expo[y] += (int)ex - 126;
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) en[y][c][b] *= sc;
-      }
-    }
 #pragma unroll
     for (int y = 0; y < NB; ++y)
 #pragma unroll
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int b = 0; b < 4; ++b) e[y][c][b] = en[y][c][b];
+  };
+  // power-of-two rescale of each pair (a block's four lanes), after every
+  // kRescaleEvery-th site and at the same sites for every pair, so that a
+  // pair's result does not depend on its position in the launch (the scale
+  // is exact except for entries in the subnormal range)
+  auto rescale = [&]() {
+#pragma unroll
+    for (int y = 0; y < NB; ++y) {
+      float lm = 0.f;
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) lm = __builtin_elementwise_maximum(lm, fabsf(e[y][c][b]));
+      unsigned m = __float_as_uint(lm);
+      m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0xB1, 0xF, 0xF, false));
+      m = max(m, (unsigned)__builtin_amdgcn_update_dpp(0, (int)m, 0x4E, 0xF, 0xF, false));
+      const unsigned ex = m >> 23;
+      const float sc = rescale_factor(ex);
+      expo[y] += (int)ex - 126;
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) e[y][c][b] *= sc;
+    }
+  };
+  // whole groups of kRescaleEvery sites, each followed by the rescale, then
+  // the remainder without it: the site body carries no VALU work (which
+  // would not overlap the matrix-core instructions of the same SIMD)
+  const int nfull = nq - nq % kRescaleEvery;
+  for (int k0 = 0; k0 < nfull; k0 += kRescaleEvery) {
+    for (int k = k0; k < k0 + kRescaleEvery; ++k) site(k);
+    rescale();
   }
+  for (int k = nfull; k < nq; ++k) site(k);
 
   // ---- epilogue: lane x = 0 of a block holds E[0][0] of its pair
   if (tid < kQkMaskWords) sm.mask[tid] = 0;
