@@ -295,11 +295,19 @@ qk_status run_tasks(std::vector<QkTask>& tasks_in, qk_precision prec, double tau
   std::stable_sort(tasks.begin(), tasks.end(), [](const QkTask& a, const QkTask& b) {
     return (double)a.nq * a.T * a.T * a.T > (double)b.nq * b.T * b.T * b.T;
   });
+  // launch shape: the tuning entry of the dominant (first) task when it was
+  // tuned for this form, else the defaults; one launch has one shape, which
+  // decides only the order and placement of tiles, never a pair's arithmetic
+  QkTuneEntry te;
+  const bool tuned =
+      !tasks.empty() && qk_tune_lookup(tasks[0].T, tasks[0].nq, &te) && te.form == prec;
+  const int band = tuned ? te.band : kQkBand;
   QkTaskTable tt;
   memset(&tt, 0, sizeof(tt));
   int64_t acc = 0;
   for (size_t k = 0; k < tasks.size(); ++k) {
     tasks[k].tile_begin = acc;
+    tasks[k].band = band;
     acc += tasks[k].n_tiles;
     tt.t[k] = tasks[k];
   }
@@ -328,9 +336,6 @@ qk_status run_tasks(std::vector<QkTask>& tasks_in, qk_precision prec, double tau
                   "allocation-free entry point has " + std::to_string(scratch->bytes));
   }
   // persistent workgroups per CU: from the tuning table, else per form
-  QkTuneEntry te;
-  const bool tuned =
-      !tasks.empty() && qk_tune_lookup(tasks[0].T, tasks[0].nq, &te) && te.form == prec;
   const int grid64 = (int)std::min<int64_t>(
       acc, (int64_t)device_cus() * (tuned && prec == QK_PREC_FP64 ? te.wg_per_cu : 2));
   timing_mark(0, s);
@@ -388,7 +393,7 @@ qk_status run_tasks(std::vector<QkTask>& tasks_in, qk_precision prec, double tau
         acc, (int64_t)device_cus() * (tuned ? te.wg_per_cu : 3));
     e = qk_launch_sweep_fp32(tt, grid, flags, ln_tau, s);
   } else {
-    e = qk_launch_sweep_mfma(tt, prec, device_cus(), flags, ln_tau, s);
+    e = qk_launch_sweep_mfma(tt, prec, device_cus(), tuned ? te.wg_per_cu : 2, flags, ln_tau, s);
   }
   timing_mark(1, s);
   if (e == hipSuccess && refine) {
@@ -767,18 +772,35 @@ qk_status qk_autotune(const qk_mps_batch* rows, const qk_mps_batch* cols, int32_
                       int32_t max_tiles, void* hip_stream, qk_precision* chosen) {
   if (!rows || !cols || max_tiles < 1) return fail(QK_ERR_INVALID_ARG, "bad autotune arguments");
   hipStream_t s = (hipStream_t)hip_stream;
+  // Candidates: the forms that meet the stated tolerance, each with the launch
+  // shapes it admits. Where the FP32 matrix-core form applies (bonds up to
+  // 4), every key of a large job resolves to it (or to BF16x3 if that were
+  // faster), so that AUTO gives all tasks of a mixed batch one form and the
+  // batch runs as one launch: the FP32 VALU form stays available by name
+  // only, and the complex-FP64 form competes only when the whole job fits
+  // in the timed slice, i.e. a small job, where the reduced forms' FP64
+  // refinement pass has a fixed cost that can exceed what they save.
   struct Cand {
     qk_precision p;
-    int wg;
+    int wg, band;
   };
   std::vector<Cand> cands;
-  if (rows->t64 && cols->t64)
-    for (int wg : {1, 2}) cands.push_back({QK_PREC_FP64, wg});
+  const bool mfma = qk_mfma_supports(QK_PREC_FP32_MFMA, rows->T);
+  int64_t job_tiles = 0;
+  {
+    const int64_t tr = (rows->n + 15) / 16, tc = (cols->n + 15) / 16;
+    job_tiles = symmetric ? tr * (tr + 1) / 2 : tr * tc;
+  }
+  const bool small_job = job_tiles <= max_tiles;
+  if (rows->t64 && cols->t64 && (!mfma || small_job || !(rows->t32 && cols->t32)))
+    for (int wg : {1, 2}) cands.push_back({QK_PREC_FP64, wg, kQkBand});
   if (rows->t32 && cols->t32) {
-    for (int wg : {2, 3, 4}) cands.push_back({QK_PREC_FP32, wg});
-    if (qk_mfma_supports(QK_PREC_FP32_MFMA, rows->T)) {
-      cands.push_back({QK_PREC_FP32_MFMA, 1});
-      cands.push_back({QK_PREC_BF16X3, 1});
+    if (mfma) {
+      for (int band : {2, 4, 8})
+        for (int wg : {2, 1}) cands.push_back({QK_PREC_FP32_MFMA, wg, band});
+      cands.push_back({QK_PREC_BF16X3, 1, kQkBand});
+    } else if (rows->T <= 4) {
+      for (int wg : {2, 3, 4}) cands.push_back({QK_PREC_FP32, wg, kQkBand});
     }
   }
   if (cands.empty()) return fail(QK_ERR_UNSUPPORTED, "no sweep form applies to these batches");
@@ -813,7 +835,7 @@ qk_status qk_autotune(const qk_mps_batch* rows, const qk_mps_batch* cols, int32_
       if (st != QK_OK) break;
     }
     tiles = std::min<int64_t>(tv[0].n_tiles, max_tiles);
-    qk_tune_store(rows->T, rows->nq, QkTuneEntry{c.p, c.wg, 0.0});
+    qk_tune_store(rows->T, rows->nq, QkTuneEntry{c.p, c.wg, c.band, 0.0});
     st = run_tasks(tv, c.p, ref ? tau : 0.0, s, max_tiles);  // warm-up
     if (st != QK_OK) break;
     float ms = 0.f;
@@ -837,7 +859,7 @@ qk_status qk_autotune(const qk_mps_batch* rows, const qk_mps_batch* cols, int32_
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != QK_OK) return st;
-  qk_tune_store(rows->T, rows->nq, QkTuneEntry{win.p, win.wg, best});
+  qk_tune_store(rows->T, rows->nq, QkTuneEntry{win.p, win.wg, win.band, best});
   if (chosen) *chosen = win.p;
   return QK_OK;
 }

@@ -99,6 +99,7 @@ struct QkTask {
   double* kc; int64_t ld_kc;
   double* k; int64_t ld_k;
   int32_t fuse;
+  int32_t band;          // tile rows per band of the tile order (0: kQkBand)
 };
 
 constexpr int QK_MAX_TASKS = 16;
@@ -116,40 +117,44 @@ __device__ inline int64_t qk_tile_of(int64_t round, int wg, int grid) {
 }
 
 // Task-local tile index -> (tile row, tile column). Tiles are enumerated in
-// bands of kQkBand tile rows: within a band column by column, within a column
-// row by row (symmetric tasks: upper triangle incl. the diagonal). A run of
-// 32 consecutive tiles -- what one XCD holds at a time under qk_tile_of --
-// then covers 4 row blocks x 8 column blocks, whose 12 sample blocks the
-// XCD's L2 serves to all 32 workgroups. Shared by every sweep kernel, so a
-// refinement pass finds the tiles its mask words were written for.
+// bands of B = t.band tile rows (kQkBand when 0): within a band column by
+// column, within a column row by row (symmetric tasks: upper triangle incl.
+// the diagonal). A run of consecutive tiles -- what one XCD holds at a time
+// under qk_tile_of -- then covers B row blocks x (run / B) column blocks,
+// whose sample blocks the XCD's L2 serves to all of its workgroups; B trades
+// row-block reuse against column-block reuse and is a tuning parameter.
+// Shared by every sweep kernel, so a refinement pass finds the tiles its
+// mask words were written for (both passes read the same task table).
 constexpr int kQkBand = 4;
 
 __device__ inline void qk_tile_coords(const QkTask& t, int64_t lt, int& ti, int& tj) {
+  const int64_t B = t.band > 0 ? t.band : kQkBand;
   const int64_t nc = t.tiles_c;
   if (!t.symmetric) {
     const int64_t nr = t.n_tiles / nc;
-    const int64_t band = lt / (kQkBand * nc);
-    const int64_t l = lt - band * (kQkBand * nc);
-    const int64_t r0 = band * kQkBand;
-    const int64_t h = nr - r0 < kQkBand ? nr - r0 : kQkBand;
+    const int64_t band = lt / (B * nc);
+    const int64_t l = lt - band * (B * nc);
+    const int64_t r0 = band * B;
+    const int64_t h = nr - r0 < B ? nr - r0 : B;
     ti = (int)(r0 + l % h);
     tj = (int)(l / h);
     return;
   }
-  // full bands before band R hold C(R) = 4 n R - 8 R^2 + 2 R tiles
+  // full bands before band R hold C(R) = B n R + B R / 2 - B^2 R^2 / 2 tiles
+  // (B (B - 1) / 2 in the band's partial first columns, B per later column)
   const int64_t n = nc;
-  const int64_t nb = (n + kQkBand - 1) / kQkBand;
-  auto before = [&](int64_t r) { return 4 * n * r - 8 * r * r + 2 * r; };
-  const double b = 4.0 * (double)n + 2.0;
-  const double disc = b * b - 32.0 * (double)lt;
-  int64_t R = (int64_t)((b - sqrt(disc > 0.0 ? disc : 0.0)) / 16.0);
+  const int64_t nb = (n + B - 1) / B;
+  auto before = [&](int64_t r) { return B * n * r + (B * r - B * B * r * r) / 2; };
+  const double bq = (double)B * (double)n + 0.5 * (double)B;
+  const double disc = bq * bq - 2.0 * (double)(B * B) * (double)lt;
+  int64_t R = (int64_t)((bq - sqrt(disc > 0.0 ? disc : 0.0)) / (double)(B * B));
   if (R < 0) R = 0;
   if (R > nb - 1) R = nb - 1;
   while (R > 0 && before(R) > lt) --R;
   while (R + 1 < nb && before(R + 1) <= lt) ++R;
   const int64_t l = lt - before(R);
-  const int64_t r0 = kQkBand * R;
-  const int64_t h = n - r0 < kQkBand ? n - r0 : kQkBand;
+  const int64_t r0 = B * R;
+  const int64_t h = n - r0 < B ? n - r0 : B;
   const int64_t part = h * (h - 1) / 2;  // the band's first h-1 columns are partial
   if (l < part) {
     int64_t c = 0;

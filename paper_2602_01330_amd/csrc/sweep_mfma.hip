@@ -890,14 +890,15 @@ __device__ void run_tile_m4(const QkTask& t, int ti, int tj, M4Smem& sm, uint32_
   if (mask && tid < kQkMaskWords) mask[tile_id * kQkMaskWords + tid] = sm.mask[tid];
 }
 
-// Pair blocks per wave of the FP32 form, and workgroups per CU (LDS holds
-// two workgroups' feature staging).
+// Pair blocks per wave of the FP32 form: a 16 x 16 tile is 8 waves, up to
+// two workgroups per CU, four waves per SIMD (the register budget of 128
+// VGPRs). (HIP's second launch bound is the minimum number of waves per SIMD)
 constexpr int kM4Blocks = 2;
-constexpr int kM4WgPerCu = 2;
 
-// (HIP's second launch bound is the minimum number of waves per SIMD)
-__global__ __launch_bounds__(kThreads / kM4Blocks, kM4WgPerCu * kWaves / kM4Blocks / 4) void sweep_m4_kernel(
-    QkTaskTable tt, uint32_t* flags, double ln_tau) {
+__global__ __launch_bounds__(kThreads / kM4Blocks, 4) void sweep_m4_kernel(QkTaskTable tt,
+                                                                            uint32_t* flags,
+                                                                            double ln_tau) {
+  constexpr int NB = kM4Blocks;
   __shared__ M4Smem sm;
   for (int64_t rnd = 0; rnd * gridDim.x < tt.total_tiles; ++rnd) {
     const int64_t q = qk_tile_of(rnd, blockIdx.x, gridDim.x);
@@ -907,9 +908,9 @@ __global__ __launch_bounds__(kThreads / kM4Blocks, kM4WgPerCu * kWaves / kM4Bloc
     const QkTask& t = tt.t[k];
     int ti, tj;
     qk_tile_coords(t, q - t.tile_begin, ti, tj);
-    if (t.T == 4) run_tile_m4<kM4Blocks, 4>(t, ti, tj, sm, flags, q, ln_tau);
-    else if (t.T == 2) run_tile_m4<kM4Blocks, 2>(t, ti, tj, sm, flags, q, ln_tau);
-    else run_tile_m4<kM4Blocks, 1>(t, ti, tj, sm, flags, q, ln_tau);
+    if (t.T == 4) run_tile_m4<NB, 4>(t, ti, tj, sm, flags, q, ln_tau);
+    else if (t.T == 2) run_tile_m4<NB, 2>(t, ti, tj, sm, flags, q, ln_tau);
+    else run_tile_m4<NB, 1>(t, ti, tj, sm, flags, q, ln_tau);
     __syncthreads();
   }
 }
@@ -923,13 +924,13 @@ bool qk_mfma_supports(qk_precision p, int T) {
 
 int qk_mfma_tile(qk_precision) { return kTile; }
 
-hipError_t qk_launch_sweep_mfma(const QkTaskTable& tt, qk_precision p, int cus,
+hipError_t qk_launch_sweep_mfma(const QkTaskTable& tt, qk_precision p, int cus, int wg_per_cu,
                                 uint32_t* flags, double ln_tau, hipStream_t s) {
   if (tt.total_tiles == 0) return hipSuccess;
   const int grid = (int)(tt.total_tiles < (int64_t)cus ? tt.total_tiles : cus);
   switch (p) {
     case QK_PREC_FP32_MFMA: {
-      const int64_t g4 = (int64_t)cus * kM4WgPerCu;
+      const int64_t g4 = (int64_t)cus * (wg_per_cu >= 2 ? 2 : 1);
       hipLaunchKernelGGL(sweep_m4_kernel, dim3((int)(tt.total_tiles < g4 ? tt.total_tiles : g4)),
                          dim3(kThreads / kM4Blocks), 0, s, tt, flags, ln_tau);
       break;

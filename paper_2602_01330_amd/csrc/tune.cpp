@@ -8,6 +8,8 @@
 #include <map>
 #include <mutex>
 #include <sstream>
+#include <string>
+#include <vector>
 
 #include "qk_tune.h"
 
@@ -41,22 +43,32 @@ std::string qk_tune_export_text() {
   o.precision(6);
   for (auto& kv : g_table)
     o << kv.first.first << " " << kv.first.second << " " << (int)kv.second.form << " "
-      << kv.second.wg_per_cu << " " << kv.second.us_per_tile << "\n";
+      << kv.second.wg_per_cu << " " << kv.second.band << " " << kv.second.us_per_tile << "\n";
   return o.str();
 }
 
+// One line per key: "T bucket form wg_per_cu band us_per_tile", or the older
+// "T bucket form wg_per_cu us_per_tile" (band 4).
 bool qk_tune_import_text(const std::string& text) {
   std::istringstream in(text);
   std::map<std::pair<int, int>, QkTuneEntry> t;
-  int T, b, f, wg;
-  double us;
-  while (in >> T >> b >> f >> wg >> us) {
+  std::string line;
+  while (std::getline(in, line)) {
+    std::istringstream ls(line);
+    std::vector<double> v;
+    double x;
+    while (ls >> x) v.push_back(x);
+    if (!ls.eof()) return false;
+    if (v.empty()) continue;
+    if (v.size() != 5 && v.size() != 6) return false;
+    const int T = (int)v[0], b = (int)v[1], f = (int)v[2], wg = (int)v[3];
+    const int band = v.size() == 6 ? (int)v[4] : 4;
+    const double us = v.back();
     if (T < 1 || b < 0 || f < QK_PREC_FP64 || f > QK_PREC_FP32_MFMA || f == QK_PREC_AUTO ||
-        wg < 1 || wg > 8)
+        wg < 1 || wg > 8 || band < 1 || band > 64)
       return false;
-    t[{T, b}] = QkTuneEntry{(qk_precision)f, wg, us};
+    t[{T, b}] = QkTuneEntry{(qk_precision)f, wg, band, us};
   }
-  if (!in.eof()) return false;
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto& kv : t) g_table[kv.first] = kv.second;
   return true;
