@@ -674,11 +674,14 @@ def pathsum_leg(args):
 def s1_leg(args):
     """The truncating regime end to end: 1000 train + 250 test images (784
     qubits), 8 layers, chi_max 64 (bonds would reach 2^8 without the cap).
-    Device build in launches of 250 samples, then the complex-FP64 sweep of
-    train x train (symmetric) and test x train in three launches of about
-    250k pairs (progress between launches). The first three train samples'
-    bond tables, discarded weights and overlaps are checked against the
-    oracle's replay (tests/golden/s1_replay_3.json)."""
+    Device build in launches of 250 samples (FP64 tensors and their packed
+    FP32 copies), then the sweep of train x train (symmetric) and test x
+    train in three calls of about 250k pairs (progress between calls), once
+    with the chosen form (complex FP32 on the matrix cores, pairs above the
+    refinement threshold redone in FP64) and once with the plain complex-FP64
+    sweep; the two are compared on every pair. The first three train
+    samples' bond tables, discarded weights and overlaps are checked against
+    the oracle's replay (tests/golden/s1_replay_3.json)."""
     import numpy as np
     import torch
 
@@ -690,58 +693,79 @@ def s1_leg(args):
     L, chi, B = 8, 64, 250
     xs = [torch.as_tensor(x_tr[k:k + B], device="cuda") for k in range(0, ntr, B)]
     xs.append(torch.as_tensor(x_te, device="cuda"))
+    forms = ["fp64"] if args.s1_plain_only else ["fp32_mfma", "fp64"]
+    store = qk.QK_STORE_FP64 if args.s1_plain_only else qk.QK_STORE_ALL
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     bs = []
     for k, xk in enumerate(xs):
-        bs.append(qk.qk_mps_build(xk, L, chi, 1e-10, store=qk.QK_STORE_FP64))
+        bs.append(qk.qk_mps_build(xk, L, chi, 1e-10, store=store))
         torch.cuda.synchronize()
         log(f"bench: s1 build {k + 1}/{len(xs)} done at {time.perf_counter() - t0:.1f} s")
     build_s = time.perf_counter() - t0
     tr, te = bs[:-1], bs[-1]
     f64 = dict(dtype=torch.float64, device="cuda")
-    ln_tr = torch.full((ntr, ntr), float("nan"), **f64)
-    ln_te = torch.full((nte, ntr), float("nan"), **f64)
-
-    calls = [[(0, 0), (0, 1), (0, 2), (0, 3), (1, 1)], [(1, 2), (1, 3), (2, 2), (2, 3), (3, 3)]]
-    t1 = time.perf_counter()
-    for n_call, blocks in enumerate(calls):
-        tasks = [{"rows": tr[a], "cols": tr[b], "symmetric": a == b, "kq": None,
-                  "lnkq": ln_tr[a * B:(a + 1) * B, b * B:(b + 1) * B]} for a, b in blocks]
-        qk.qk_overlap_gram_multi(tasks, "fp64")
-        torch.cuda.synchronize()
-        log(f"bench: s1 train sweep {n_call + 1}/2 done at {time.perf_counter() - t1:.1f} s")
-    tasks = [{"rows": te, "cols": tr[b], "symmetric": False, "kq": None,
-              "lnkq": ln_te[:, b * B:(b + 1) * B]} for b in range(len(tr))]
-    qk.qk_overlap_gram_multi(tasks, "fp64")
-    torch.cuda.synchronize()
-    sweep_s = time.perf_counter() - t1
-    log(f"bench: s1 test sweep done, sweep {sweep_s:.1f} s")
     chi_tr = np.concatenate([qk.qk_mps_chi(b) for b in tr])
     chi_te = qk.qk_mps_chi(te)
     flops = algorithmic_flops(chi_tr, chi_tr, True) + algorithmic_flops(chi_te, chi_tr, False)
     pairs = ntr * (ntr + 1) // 2 + nte * ntr
     fx = json.load(open(os.path.join(ROOT, "tests", "golden", "s1_replay_3.json")))
-    chi_ok = bool(np.array_equal(chi_tr[:3], np.array(fx["chi"], dtype=np.int32)))
-    lmax = float(np.max(np.abs(ln_tr[:3, :3].cpu().numpy() - np.array(fx["lnkq"]))))
-    ok_b = lmax <= 1e-3
-    disc = qk.qk_mps_discarded(tr[0])[:3]
-    disc_ok = bool(np.allclose(disc, fx["discarded"], rtol=1e-6, atol=1e-15))
-    ln_all = ln_tr.cpu().numpy()
     upper = np.triu_indices(ntr)
-    for b in bs:
-        b.close()
-    return {"workload": "truncating regime: 1000 train + 250 test 784-qubit images, L=8, "
-                        "chi_max=64, complex FP64 (build + sweep), inputs resident",
-            "build_s": build_s, "sweep_s": sweep_s, "job_s": build_s + sweep_s,
-            "pairs": pairs, "pairs_per_s": pairs / (build_s + sweep_s),
-            "sweep_pairs_per_s": pairs / sweep_s,
-            "sweep_tflops": flops / sweep_s / 1e12, "algorithmic_flop": flops,
-            "chi_realized_max": int(chi_tr.max()),
-            "replay_check": {"bond_tables_equal": chi_ok, "ln_gate_b": bool(ok_b),
-                             "max_abs_dlnk": float(lmax), "discarded_equal": disc_ok},
+
+    def sweep(prec):
+        ln_tr = torch.full((ntr, ntr), float("nan"), **f64)
+        ln_te = torch.full((nte, ntr), float("nan"), **f64)
+        calls = [[(0, 0), (0, 1), (0, 2), (0, 3), (1, 1)],
+                 [(1, 2), (1, 3), (2, 2), (2, 3), (3, 3)]]
+        t1 = time.perf_counter()
+        for n_call, blocks in enumerate(calls):
+            tasks = [{"rows": tr[a], "cols": tr[b], "symmetric": a == b, "kq": None,
+                      "lnkq": ln_tr[a * B:(a + 1) * B, b * B:(b + 1) * B]} for a, b in blocks]
+            qk.qk_overlap_gram_multi(tasks, prec)
+            torch.cuda.synchronize()
+            log(f"bench: s1 {prec} train sweep {n_call + 1}/2 done at "
+                f"{time.perf_counter() - t1:.1f} s")
+        tasks = [{"rows": te, "cols": tr[b], "symmetric": False, "kq": None,
+                  "lnkq": ln_te[:, b * B:(b + 1) * B]} for b in range(len(tr))]
+        qk.qk_overlap_gram_multi(tasks, prec)
+        torch.cuda.synchronize()
+        sweep_s = time.perf_counter() - t1
+        log(f"bench: s1 {prec} test sweep done, sweep {sweep_s:.1f} s")
+        ln_all = ln_tr.cpu().numpy()
+        lmax = float(np.max(np.abs(ln_all[:3, :3] - np.array(fx["lnkq"]))))
+        return ln_tr, ln_te, {
+            "sweep_s": sweep_s, "job_s": build_s + sweep_s,
+            "pairs_per_s": pairs / (build_s + sweep_s), "sweep_pairs_per_s": pairs / sweep_s,
+            "sweep_tflops": flops / sweep_s / 1e12,
+            "replay_max_abs_dlnk": lmax, "replay_ln_gate_b": bool(lmax <= 1e-3),
             "diag_max_abs_lnk": float(np.max(np.abs(np.diag(ln_all)))),
             "upper_all_finite": bool(np.isfinite(ln_all[upper]).all())}
+
+    res = {"workload": "truncating regime: 1000 train + 250 test 784-qubit images, L=8, "
+                       "chi_max=64, device build (FP64) + sweep, inputs resident",
+           "build_s": build_s, "pairs": pairs, "algorithmic_flop": flops,
+           "chi_realized_max": int(chi_tr.max())}
+    lns = {}
+    for prec in forms:
+        ln_tr, ln_te, r = sweep(prec)
+        res[prec] = r
+        lns[prec] = (ln_tr, ln_te)
+    if len(forms) == 2:
+        a, b = lns["fp32_mfma"], lns["fp64"]
+        iu = torch.triu_indices(ntr, ntr, device=a[0].device)
+        dd = torch.cat([(a[0][iu[0], iu[1]] - b[0][iu[0], iu[1]]).abs(),
+                        (a[1] - b[1]).abs().flatten()])
+        res["chosen_vs_plain_all_pairs"] = {
+            "max_abs_dlnk": float(dd.max()), "pairs_above_ln_gate_1e-3": int((dd > 1e-3).sum())}
+        res["speedup_job"] = res["fp64"]["job_s"] / res["fp32_mfma"]["job_s"]
+        res["speedup_sweep"] = res["fp64"]["sweep_s"] / res["fp32_mfma"]["sweep_s"]
+    res["replay_check"] = {
+        "bond_tables_equal": bool(np.array_equal(chi_tr[:3], np.array(fx["chi"], dtype=np.int32))),
+        "discarded_equal": bool(np.allclose(qk.qk_mps_discarded(tr[0])[:3], fx["discarded"],
+                                            rtol=1e-6, atol=1e-15))}
+    for b in bs:
+        b.close()
+    return res
 
 
 def svm_leg(args):
@@ -1040,6 +1064,8 @@ def main():
                     help="run only the path-sum leg and print its JSON")
     ap.add_argument("--s1-only", action="store_true",
                     help="run only the truncating-regime job end to end and print its JSON")
+    ap.add_argument("--s1-plain-only", action="store_true",
+                    help="truncating-regime leg: only the plain FP64 sweep")
     ap.add_argument("--svm", action="store_true",
                     help="add the SVM training / prediction leg on the 784-feature Gram")
     ap.add_argument("--svm-only", action="store_true",

@@ -73,17 +73,23 @@ enum {
 };
 
 /*
- * Encoding circuit (the benchmark instance of the block-structured feature
- * map of Section II-C, Fig. 1(B)); per layer:
+ * Encoding circuit (the block-structured feature map of Section II-C,
+ * Fig. 1(B): single-qubit encoding layers interleaved with locally
+ * restricted entangling layers); per layer:
  *   H on every qubit, RZ(2 x_k) on qubit k, then RZZ(theta_k) on (k, k+1),
- *   k = 0..n-2, theta_k = 2 (pi - x_k)(pi - x_{k+1}); repeated n_layers
- *   times with the same x. RZ(p) = exp(-i p Z/2), RZZ(t) = exp(-i t ZZ/2).
+ *   theta_k = 2 (pi - x_k)(pi - x_{k+1}), for every k = 0..n-2 whose pair
+ *   lies inside one entangler block; repeated n_layers times with the same x.
+ *   RZ(p) = exp(-i p Z/2), RZZ(t) = exp(-i t ZZ/2).
+ * Entangler blocks: entangle = 1 is one block (the open chain over all
+ * qubits); entangle = B >= 2 cuts the chain into blocks of B consecutive
+ * qubits (pairs with (k + 1) % B == 0 get no gate), a block product state;
+ * entangle = 0 drops every entangler.
  */
 typedef struct {
   int32_t n_qubits;   /* = number of features d, >= 1                      */
   int32_t n_layers;   /* L >= 1                                             */
   int32_t chi_max;    /* bond-dimension cap, >= 1                           */
-  int32_t entangle;   /* 1: RZZ chain as above; 0: all theta_k = 0          */
+  int32_t entangle;   /* 0: none; 1: open chain; B >= 2: blocks of B qubits */
   double cutoff_rel;  /* keep singular values s_j > cutoff_rel * s_0, >= 0  */
 } qk_circuit_desc;
 
@@ -99,8 +105,9 @@ typedef struct qk_mps_batch qk_mps_batch; /* opaque, device-resident, library-ow
  * chi_max, renormalise), sweeping left to right on odd and right to left on
  * even layers. Then the tensors are packed for the overlap sweep.
  *   c        circuit; the library bounds every bond by chi_ws =
- *            min(chi_max, 2^min(n_layers, floor(n_qubits/2))) (1 when
- *            entangle = 0), the exact bond bound of this circuit family;
+ *            min(chi_max, 2^min(n_layers, floor(b/2))) with b the qubits of
+ *            an entangler block (n_qubits for the open chain; chi_ws = 1
+ *            when entangle = 0), the exact bond bound of this circuit family;
  *            tensors are padded to chi_pad = the power of two >= chi_ws;
  *            chi_ws <= 64 is supported (from 32 on, the build keeps a copy
  *            of each sample's merged matrix in a temporary device
@@ -328,8 +335,8 @@ QK_API qk_status qk_svm_decision(const double* k_dev, int64_t m, int64_t n, int6
  *   x_rows_dev  m x d features (leading dimension ld_xr >= d); x_cols_dev
  *               n x d. symmetric = 1 needs the same pointer, m = n and
  *               ld_xr = ld_xc, contracts the upper triangle and mirrors it.
- *   n_layers    1, 2 or 3 (QK_ERR_UNSUPPORTED otherwise); entangle 0 drops the
- *               RZZ chain.
+ *   n_layers    1, 2 or 3 (QK_ERR_UNSUPPORTED otherwise); entangle as in
+ *               qk_circuit_desc (0 none, 1 open chain, B >= 2 blocks of B).
  *   kq_dev, lnkq_dev  optional m x n outputs (leading dimensions >= n).
  *   fuse        optional RBF (Eq. (3)) and mix (Eq. (11)) outputs as in
  *               qk_overlap_gram; its x fields are ignored (the RBF uses

@@ -9,6 +9,13 @@ entangling layers. The benchmark instance used throughout is, per layer:
 
 repeated L times with the same x. Conventions: RZ(phi) = exp(-i phi Z / 2),
 RZZ(theta) = exp(-i theta Z(x)Z / 2), basis |0> = (1, 0).
+
+Block-structured entanglers (the block product state circuits the paper
+names): the qubits are cut into blocks of B consecutive qubits and the RZZ
+chain keeps only the pairs (k, k+1) inside one block, i.e. drops the pairs
+with (k + 1) divisible by B. The argument ``entangle`` of the oracle
+functions takes False / 0 (no entanglers), True / 1 (the open chain over all
+qubits) or a block size B >= 2.
 """
 import math
 
@@ -38,3 +45,16 @@ def rzz_angles(x: np.ndarray) -> np.ndarray:
     """Entangler angles theta_k = 2 (pi - x_k)(pi - x_{k+1}), k = 0..n-2."""
     x = np.asarray(x, dtype=np.float64)
     return 2.0 * (math.pi - x[:-1]) * (math.pi - x[1:])
+
+
+def entangler_mask(n: int, entangle=True) -> np.ndarray:
+    """Boolean array of length n-1: whether RZZ acts on the pair (k, k+1)."""
+    m = max(n - 1, 0)
+    if entangle is False or entangle == 0:
+        return np.zeros(m, dtype=bool)
+    if entangle is True or entangle == 1:
+        return np.ones(m, dtype=bool)
+    B = int(entangle)
+    if B < 2:
+        raise ValueError("entangle must be False/0, True/1 or a block size >= 2")
+    return np.array([(k + 1) % B != 0 for k in range(m)], dtype=bool)

@@ -39,15 +39,18 @@ import math
 
 import numpy as np
 
-from .circuit import HADAMARD, rz, rzz_angles
+from .circuit import HADAMARD, entangler_mask, rz, rzz_angles
 
 _SIGMA = np.array([1.0, -1.0])
 
 
 def build_mps(x, n_layers: int, chi_max: int, cutoff: float = 1e-10,
-              entangle: bool = True, return_discarded: bool = False):
+              entangle=True, return_discarded: bool = False):
     """TEBD build of |psi(x)>. Returns (list of site tensors, bond dims).
 
+    ``entangle``: False, True (open chain) or an entangler block size B >= 2;
+    a pair without an entangler is still a two-site step, with no phase (its
+    merged tensor is a product across the cut, so one singular value stays).
     With ``return_discarded`` a third value is returned: the sum over all
     truncations of the discarded weight sum_{j >= keep} s_j^2 / sum_j s_j^2.
     """
@@ -58,7 +61,7 @@ def build_mps(x, n_layers: int, chi_max: int, cutoff: float = 1e-10,
         t = np.zeros((1, 2, 1), dtype=np.complex128)
         t[0, 0, 0] = 1.0
         A.append(t)
-    theta = rzz_angles(x) if (entangle and n > 1) else np.zeros(max(n - 1, 0))
+    theta = (rzz_angles(x) * entangler_mask(n, entangle)) if n > 1 else np.zeros(0)
     discarded = 0.0
     for layer in range(n_layers):
         # 1. single-qubit layer
@@ -96,7 +99,7 @@ def build_mps(x, n_layers: int, chi_max: int, cutoff: float = 1e-10,
 
 
 def build_batch(X, n_layers: int, chi_max: int, cutoff: float = 1e-10,
-                entangle: bool = True):
+                entangle=True):
     """Build every row of X; returns a list of MPS (lists of site tensors)."""
     return [build_mps(x, n_layers, chi_max, cutoff, entangle)[0] for x in X]
 

@@ -32,7 +32,7 @@ import math
 
 import numpy as np
 
-from .circuit import rzz_angles
+from .circuit import entangler_mask, rzz_angles
 
 
 def _site_tables(n_layers: int):
@@ -65,8 +65,9 @@ def _site_tables(n_layers: int):
     return su, sv, sign, pu, pv
 
 
-def overlap_pairs(X, Y, n_layers: int, pairs, entangle: bool = True):
-    """<psi(X[i])|psi(Y[j])> for (i, j) in pairs.
+def overlap_pairs(X, Y, n_layers: int, pairs, entangle=True):
+    """<psi(X[i])|psi(Y[j])> for (i, j) in pairs (``entangle``: False, True
+    for the open chain, or an entangler block size B >= 2).
 
     Returns (mant, exp2): complex mantissas and integer exponents with
     a = mant * 2**exp2.
@@ -80,9 +81,10 @@ def overlap_pairs(X, Y, n_layers: int, pairs, entangle: bool = True):
     xi = X[pairs[:, 0]]
     yj = Y[pairs[:, 1]]
     P = pairs.shape[0]
-    if entangle and n > 1:
-        tx = np.stack([rzz_angles(r) for r in xi])
-        ty = np.stack([rzz_angles(r) for r in yj])
+    if n > 1:
+        on = entangler_mask(n, entangle)
+        tx = np.stack([rzz_angles(r) for r in xi]) * on
+        ty = np.stack([rzz_angles(r) for r in yj]) * on
     else:
         tx = np.zeros((P, max(n - 1, 0)))
         ty = np.zeros((P, max(n - 1, 0)))
@@ -106,7 +108,7 @@ def overlap_pairs(X, Y, n_layers: int, pairs, entangle: bool = True):
     return a, e2
 
 
-def ln_kernel_pairs(X, Y, n_layers: int, pairs, entangle: bool = True):
+def ln_kernel_pairs(X, Y, n_layers: int, pairs, entangle=True):
     """ln K_q = 2 ln|a| for each pair (-inf where a == 0)."""
     a, e2 = overlap_pairs(X, Y, n_layers, pairs, entangle)
     with np.errstate(divide="ignore"):

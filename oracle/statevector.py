@@ -10,14 +10,17 @@ Definition of record for small qubit counts (n <= ~16):
 """
 import numpy as np
 
-from .circuit import HADAMARD, rz, rzz, rzz_angles
+from .circuit import HADAMARD, entangler_mask, rz, rzz, rzz_angles
 
 
-def gate_list(x, n_layers: int, entangle: bool = True):
-    """Ordered gates of U(x): list of (qubits, unitary)."""
+def gate_list(x, n_layers: int, entangle=True):
+    """Ordered gates of U(x): list of (qubits, unitary). ``entangle``: False
+    (none), True (open chain) or an entangler block size B >= 2 (the chain's
+    pairs inside blocks of B qubits only)."""
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
-    theta = rzz_angles(x) if entangle else np.zeros(max(n - 1, 0))
+    theta = rzz_angles(x) if n > 1 else np.zeros(0)
+    on = entangler_mask(n, entangle)
     gates = []
     for _ in range(n_layers):
         for k in range(n):
@@ -25,7 +28,8 @@ def gate_list(x, n_layers: int, entangle: bool = True):
         for k in range(n):
             gates.append(((k,), rz(2.0 * x[k])))
         for k in range(n - 1):
-            gates.append(((k, k + 1), rzz(theta[k])))
+            if on[k]:
+                gates.append(((k, k + 1), rzz(theta[k])))
     return gates
 
 
@@ -46,7 +50,7 @@ def zero_state(n: int) -> np.ndarray:
     return psi
 
 
-def state(x, n_layers: int, entangle: bool = True) -> np.ndarray:
+def state(x, n_layers: int, entangle=True) -> np.ndarray:
     """|psi(x)> as an n-axis tensor (axis k = qubit k)."""
     n = len(x)
     psi = zero_state(n)
@@ -55,13 +59,13 @@ def state(x, n_layers: int, entangle: bool = True) -> np.ndarray:
     return psi
 
 
-def kernel_overlap(x, y, n_layers: int, entangle: bool = True) -> float:
+def kernel_overlap(x, y, n_layers: int, entangle=True) -> float:
     """Eq. (7): |<psi(x)|psi(y)>|^2."""
     a = np.vdot(state(x, n_layers, entangle), state(y, n_layers, entangle))
     return float(abs(a) ** 2)
 
 
-def amplitude_compute_uncompute(x, y, n_layers: int, entangle: bool = True):
+def amplitude_compute_uncompute(x, y, n_layers: int, entangle=True):
     """Eqs. (8)-(9): <0| U^dagger(y) U(x) |0>, gate by gate."""
     n = len(x)
     psi = zero_state(n)
@@ -72,7 +76,7 @@ def amplitude_compute_uncompute(x, y, n_layers: int, entangle: bool = True):
     return complex(psi[(0,) * n])
 
 
-def gram(X, Y, n_layers: int, entangle: bool = True) -> np.ndarray:
+def gram(X, Y, n_layers: int, entangle=True) -> np.ndarray:
     """Eq. (7) for all pairs of rows of X and Y."""
     sx = [state(x, n_layers, entangle).ravel() for x in X]
     sy = [state(y, n_layers, entangle).ravel() for y in Y]

@@ -15,6 +15,13 @@
 // splits back. The site tensors live in the packed sweep layout
 // [site][sample][s][a][b] (padded to T x T, zero outside the realized block),
 // so the FP64 sweep reads the build's output directly.
+//
+// `entangle` is the entangler block size B (0: no entanglers): the chain acts
+// on the pairs (k, k + 1) inside blocks of B consecutive qubits, as in the
+// block-structured entangling layers of Section II-C; B >= n is the open
+// chain over every qubit. A step across a block boundary applies no phase,
+// so its Theta is a product across the cut and the cutoff keeps one singular
+// value there.
 #include <hip/hip_runtime.h>
 
 #include "qk_internal.h"
@@ -239,7 +246,7 @@ __global__ __launch_bounds__(64) void mps_build_kernel(
       const int k = l2r ? step : (nq - 2 - step);
       const int cl = chi[k], cm = chi[k + 1], cr = chi[k + 2];
       double theta = 0.0;
-      if (entangle) theta = 2.0 * (kPi - xi[k]) * (kPi - xi[k + 1]);
+      if (entangle && (k + 1) % entangle != 0) theta = 2.0 * (kPi - xi[k]) * (kPi - xi[k + 1]);
       // stage the two sites (realized blocks) in LDS, W x W padded
       for (int e = lane; e < 2 * W * W; e += 64) {
         int s = e / (W * W), r = e % (W * W), a = r / W, b = r % W;
@@ -477,7 +484,7 @@ __global__ __launch_bounds__(BuildWgShape<W>::kThreads) void mps_build_wg_kernel
       const int R = 2 * cl, C = 2 * cr, P = cr;  // rows, columns, column pairs
       const bool live = ps < P;
       double theta = 0.0;
-      if (entangle) theta = 2.0 * (kPi - xi[k]) * (kPi - xi[k + 1]);
+      if (entangle && (k + 1) % entangle != 0) theta = 2.0 * (kPi - xi[k]) * (kPi - xi[k + 1]);
       double sh, ch;
       sincos(0.5 * theta, &sh, &ch);
       // stage site k (realized block) in LDS, rows padded to W + 1
@@ -1034,7 +1041,8 @@ __global__ __launch_bounds__(64) void mps_build8_kernel(B8Table tab, int nq, int
     // the entangler phase of a step and the feature of its fresh site are
     // known a step ahead, so their sines and cosines overlap other work
     double sh = 0.0, ch = 1.0;
-    if (entangle) sincos((kPi - xl) * (kPi - xrr), &sh, &ch);  // theta / 2
+    if (entangle && (k0 + 1) % entangle != 0)
+      sincos((kPi - xl) * (kPi - xrr), &sh, &ch);  // theta / 2
     double xq = nq > 2 ? xi[fresh_of(k0)] : 0.0;
     wave_lds_sync();
     for (int step = 0; step < nq - 1; ++step) {
@@ -1051,7 +1059,7 @@ __global__ __launch_bounds__(64) void mps_build8_kernel(B8Table tab, int nq, int
         far_next = old_chi(l2r ? k + 3 : k - 1);
         if (step + 2 < nq - 1) xq_next = xi[fresh_of(l2r ? k + 1 : k - 1)];
         sincos(xq, &g_sn, &g_cs);
-        if (entangle) {
+        if (entangle && ((l2r ? k + 1 : k - 1) + 1) % entangle != 0) {
           const double xa = l2r ? xrr : xq, xb = l2r ? xq : xl;
           sincos((kPi - xa) * (kPi - xb), &n_sh, &n_ch);
         }

@@ -54,7 +54,7 @@ __global__ void pathsum_table_kernel(const double* __restrict__ x, int64_t n, in
   const double xk = xs[k];
   double qs, qc, ps = 0.0, pc = 1.0;
   sincos(n_layers == 2 ? 2.0 * xk : xk, &qs, &qc);
-  if (entangle && k + 1 < d) {
+  if (entangle && k + 1 < d && (k + 1) % entangle != 0) {
     const double th = 2.0 * (M_PI - xk) * (M_PI - xs[k + 1]);
     sincos(0.5 * th, &ps, &pc);
   }

@@ -105,19 +105,28 @@ qk_status check_desc(const qk_circuit_desc* c) {
   if (c->n_qubits < 1) return fail(QK_ERR_INVALID_ARG, "n_qubits must be >= 1");
   if (c->n_layers < 1) return fail(QK_ERR_INVALID_ARG, "n_layers must be >= 1");
   if (c->chi_max < 1) return fail(QK_ERR_INVALID_ARG, "chi_max must be >= 1");
-  if (c->entangle != 0 && c->entangle != 1)
-    return fail(QK_ERR_INVALID_ARG, "entangle must be 0 or 1");
+  if (c->entangle < 0)
+    return fail(QK_ERR_INVALID_ARG, "entangle must be 0 (none), 1 (chain) or a block size >= 2");
   if (!(c->cutoff_rel >= 0.0) || !std::isfinite(c->cutoff_rel))
     return fail(QK_ERR_INVALID_ARG, "cutoff_rel must be finite and >= 0");
   return QK_OK;
 }
 
+// Entangler block size the kernels take: 0 (none), the qubit count for the
+// open chain (entangle = 1), else the block size.
+int ent_block(const qk_circuit_desc* c) {
+  if (!c->entangle) return 0;
+  return c->entangle == 1 ? std::max(c->n_qubits, 1) : c->entangle;
+}
+
 // Exact bond bound of this circuit family: each layer's RZZ chain multiplies
-// the Schmidt rank across a cut by at most 2, and no cut of n qubits has
-// rank above 2^floor(n/2).
+// the Schmidt rank across a cut by at most 2, no cut of n qubits has rank
+// above 2^floor(n/2), and with entangler blocks of B qubits no cut inside a
+// block has rank above 2^floor(B/2) (and a cut between blocks has rank 1).
 int chi_bound(const qk_circuit_desc* c) {
-  if (!c->entangle || c->n_qubits == 1) return 1;
-  const int e = std::min(c->n_layers, c->n_qubits / 2);
+  const int blk = std::min(ent_block(c), c->n_qubits);
+  if (blk < 2 || c->n_qubits == 1) return 1;
+  const int e = std::min(c->n_layers, blk / 2);
   int64_t b = 1;
   for (int l = 0; l < e && b < c->chi_max; ++l) b *= 2;
   return (int)std::min<int64_t>(b, c->chi_max);
@@ -507,7 +516,7 @@ qk_status qk_mps_build(const qk_circuit_desc* c, const double* x_dev,
   if (st != QK_OK) return st;
   b->chi_ws = ws;
   hipError_t e = qk_launch_build(x_dev, ld_x, n_samples, c->n_qubits, c->n_layers,
-                                 c->chi_max, c->entangle, c->cutoff_rel, ws, T,
+                                 c->chi_max, ent_block(c), c->cutoff_rel, ws, T,
                                  b->t64, b->chi, b->status, b->disc, qk_svd_sweep_limit(), s);
   if (e != hipSuccess) {
     qk_mps_release(b);
@@ -560,7 +569,7 @@ qk_status qk_mps_build_many(const qk_circuit_desc* c, int32_t n_inputs,
                            b[k]->disc};
   }
   hipError_t e = qk_launch_build_many(parts, n_inputs, c->n_qubits, c->n_layers, c->chi_max,
-                                      c->entangle, c->cutoff_rel, ws, T, qk_svd_sweep_limit(), s);
+                                      ent_block(c), c->cutoff_rel, ws, T, qk_svd_sweep_limit(), s);
   if (e != hipSuccess) {
     release_all();
     return hip_fail(e, "build launch");
@@ -949,6 +958,8 @@ qk_status qk_pathsum_gram(const double* x_rows_dev, int64_t m, int64_t ld_xr,
   if (d < 1) return fail(QK_ERR_INVALID_ARG, "d < 1");
   if (n_layers < 1 || n_layers > 3)
     return fail(QK_ERR_UNSUPPORTED, "the path-sum evaluator covers one to three layers");
+  if (entangle < 0)
+    return fail(QK_ERR_INVALID_ARG, "entangle must be 0 (none), 1 (chain) or a block size >= 2");
   if (symmetric && (m != n || x_rows_dev != x_cols_dev || ld_xr != ld_xc))
     return fail(QK_ERR_INVALID_ARG, "symmetric mode needs the same rows and columns");
   if ((m > 0 && !x_rows_dev) || (n > 0 && !x_cols_dev))
@@ -979,9 +990,10 @@ qk_status qk_pathsum_gram(const double* x_rows_dev, int64_t m, int64_t ld_xr,
   QK_HIP(hipMallocAsync((void**)&tab, (rows_tab + cols_tab) * sizeof(double4), s),
          "path-sum table allocation");
   double4* tc = symmetric ? tab : tab + rows_tab;
-  hipError_t e = qk_launch_pathsum_table(x_rows_dev, m, ld_xr, d, n_layers, entangle, tab, s);
+  const int blk = entangle == 1 ? d : entangle;  // entangler block size (0: none)
+  hipError_t e = qk_launch_pathsum_table(x_rows_dev, m, ld_xr, d, n_layers, blk, tab, s);
   if (e == hipSuccess && !symmetric)
-    e = qk_launch_pathsum_table(x_cols_dev, n, ld_xc, d, n_layers, entangle, tc, s);
+    e = qk_launch_pathsum_table(x_cols_dev, n, ld_xc, d, n_layers, blk, tc, s);
   if (e == hipSuccess)
     e = qk_launch_pathsum(tab, m, tc, n, d, n_layers, symmetric, kq_dev, ld_kq, lnkq_dev, ld_ln,
                           fuse ? &f : nullptr, s);

@@ -218,8 +218,16 @@ class MpsBatch:
             pass
 
 
+def _ent(entangle) -> int:
+    """entangle: True (open chain) / False (none), or an int as in the C
+    descriptor (0 none, 1 chain, B >= 2 entangler blocks of B qubits)."""
+    if isinstance(entangle, bool):
+        return 1 if entangle else 0
+    return int(entangle)
+
+
 def circuit(n_qubits, n_layers, chi_max, cutoff=1e-10, entangle=True):
-    return qk_circuit_desc(int(n_qubits), int(n_layers), int(chi_max), 1 if entangle else 0,
+    return qk_circuit_desc(int(n_qubits), int(n_layers), int(chi_max), _ent(entangle),
                            float(cutoff))
 
 
@@ -353,7 +361,7 @@ def qk_pathsum_gram(x_rows, x_cols=None, n_layers=2, entangle=True, kq=None, lnk
     lp, ldl = _opt(lnkq, "lnkq")
     f = _fuse(dict(fuse, x_rows=x_rows, x_cols=xc)) if fuse is not None else None
     _check(_lib.qk_pathsum_gram(rp, x_rows.shape[0], ldr, cp, xc.shape[0], ldc, x_rows.shape[1],
-                                int(n_layers), 1 if entangle else 0, 1 if sym else 0, kp, ldk,
+                                int(n_layers), _ent(entangle), 1 if sym else 0, kp, ldk,
                                 lp, ldl, C.byref(f) if f is not None else None,
                                 _stream(stream)))
     return kq, lnkq
