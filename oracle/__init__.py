@@ -29,7 +29,9 @@ Quantum-Classical Dual Kernel"):
   sequential minimal optimisation with second-order pair selection, the
   bias of Eq. (5), and one-against-one voting -- ``svm``;
 * kernel invariants and the tolerance gates used by the parity tests --
-  ``checks``.
+  ``checks``;
+* the pre-processing of Section II-A: z-score, PCA to n components,
+  min-max scaling -- ``preprocess``.
 
 Pins (what ties each function to something other than itself) are listed in
 the test-suite docstrings. ``mps.build_mps`` in the truncating regime
@@ -37,4 +39,4 @@ the test-suite docstrings. ``mps.build_mps`` in the truncating regime
 through the discarded-weight bound; beyond that it is parity unpinned
 (its own step-by-step replay is the reference).
 """
-from . import circuit, statevector, closed_form, pathsum, mps, classical, checks, svm  # noqa: F401
+from . import circuit, statevector, closed_form, pathsum, mps, classical, checks, svm, preprocess  # noqa: F401
