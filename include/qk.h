@@ -433,6 +433,50 @@ QK_API qk_status qk_set_refine_threshold(qk_precision prec, double tau);
 QK_API qk_status qk_set_svd_sweep_limit(int32_t sweeps);
 
 /*
+ * Pre-processing of raw features (Section II-A): z-score standardisation,
+ * principal component analysis keeping the n leading components, min-max
+ * scaling of each component to [0, 1]; the statistics are fitted on training
+ * rows and applied to any rows. FP64 on the device.
+ *
+ * qk_preproc_fit -- fits on x_dev (n >= 2 training rows x d raw features,
+ * row-major, leading dim ld_x >= d, caller-owned device memory):
+ *   mu, sigma    column means and population standard deviations;
+ *   components   the eigenvectors of the sample covariance Z^T Z / (n - 1) of
+ *                the standardised rows Z for its n_components largest
+ *                eigenvalues (cyclic two-sided Jacobi, FP64; ties in the
+ *                ranking go to the smaller index), each with its entry of
+ *                largest magnitude positive;
+ *   min, max     of each projected component over the training rows.
+ * Synchronous (the eigensolver checks convergence on the host each sweep).
+ * d <= 8192, 1 <= n_components <= d. Device memory: the fitted statistics
+ * (library-owned, (2 d + n_components (d + 2) + d) doubles), plus n d +
+ * 2 d^2 + n n_components doubles of temporaries during the call.
+ * Errors: INVALID_ARG, HIP, DEVICE (eigensolver sweep limit).
+ */
+typedef struct qk_preproc qk_preproc;
+QK_API qk_status qk_preproc_fit(const double* x_dev, int64_t n, int64_t ld_x, int32_t d,
+                                int32_t n_components, void* hip_stream, qk_preproc** out);
+
+/* Applies a fit to n rows x_dev (leading dim ld_x >= d): z-score with the
+ * fitted statistics (0 for constant training columns), projection on the
+ * components, u = (y - min) / (max - min) (0 where max = min), times scale
+ * (1 for the paper's [0, 1] angles, pi for [0, pi]); writes n x n_components
+ * FP64 to out_dev (leading dim ld_out >= n_components). Rows other than the
+ * training rows may fall outside [0, scale]. Asynchronous on hip_stream;
+ * temporaries from the stream-ordered pool. Errors: INVALID_ARG, HIP. */
+QK_API qk_status qk_preproc_apply(const qk_preproc* p, const double* x_dev, int64_t n,
+                                  int64_t ld_x, double scale, double* out_dev, int64_t ld_out,
+                                  void* hip_stream);
+
+/* Sizes of a fit, the Jacobi sweeps it took, and (eigvals_host, d doubles,
+ * nullable) the covariance eigenvalues in decreasing order. */
+QK_API qk_status qk_preproc_info(const qk_preproc* p, int32_t* d, int32_t* n_components,
+                                 int32_t* sweeps, double* eigvals_host);
+
+/* Frees a fit after waiting for the device. NULL is accepted. */
+QK_API qk_status qk_preproc_release(qk_preproc* p);
+
+/*
  * qk_autotune -- times the sweep forms that meet the stated tolerance
  * (complex FP64, complex FP32 on VALU with 2..4 persistent workgroups per CU,
  * complex FP32 on MFMA, split BF16x3 on MFMA) on the first max_tiles 16 x 16

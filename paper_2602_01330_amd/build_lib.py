@@ -12,9 +12,9 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libqk.so")
 
-SOURCES = ["qk_api.cpp", "tune.cpp", "server.cpp", "build.hip", "sweep_valu.hip",
-           "sweep_mfma.hip", "sweep_big.hip", "sweep_wide.hip", "classical.hip",
-           "svm.hip", "pathsum.hip"]
+SOURCES = ["qk_api.cpp", "tune.cpp", "server.cpp", "preproc_api.cpp", "build.hip",
+           "sweep_valu.hip", "sweep_mfma.hip", "sweep_big.hip", "sweep_wide.hip",
+           "classical.hip", "svm.hip", "pathsum.hip", "preprocess.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

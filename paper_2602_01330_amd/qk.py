@@ -101,6 +101,14 @@ _lib.qk_svm_predict_ovo.argtypes = [_P, C.c_int64, C.c_int64, C.c_int64, _P, C.c
                                     C.c_int32, _P, C.c_int64, _P, _P]
 _lib.qk_svm_predict_ovo.restype = C.c_int
 _lib.qk_resolve_precision.argtypes = [_P, _P, C.POINTER(C.c_int)]
+_lib.qk_preproc_fit.argtypes = [_P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _P,
+                                C.POINTER(_P)]
+_lib.qk_preproc_apply.argtypes = [_P, _P, C.c_int64, C.c_int64, C.c_double, _P, C.c_int64, _P]
+_lib.qk_preproc_info.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32), _P]
+_lib.qk_preproc_release.argtypes = [_P]
+for _f in ("qk_preproc_fit", "qk_preproc_apply", "qk_preproc_info", "qk_preproc_release"):
+    getattr(_lib, _f).restype = C.c_int
 _lib.qk_set_refine_threshold.argtypes = [C.c_int, C.c_double]
 _lib.qk_set_svd_sweep_limit.argtypes = [C.c_int32]
 _lib.qk_set_svd_sweep_limit.restype = C.c_int
@@ -157,7 +165,8 @@ EXPORTED = ["qk_server_create", "qk_server_load_support", "qk_server_submit",
             "qk_server_stats", "qk_server_destroy",
             "qk_mps_build", "qk_mps_build_many", "qk_mps_import", "qk_mps_info", "qk_mps_chi",
             "qk_mps_discarded", "qk_mps_release", "qk_overlap_gram", "qk_overlap_gram_multi",
-            "qk_overlap_gram_noalloc", "qk_rbf_gram", "qk_dual_mix",
+            "qk_overlap_gram_noalloc", "qk_preproc_fit", "qk_preproc_apply", "qk_preproc_info",
+            "qk_preproc_release", "qk_rbf_gram", "qk_dual_mix",
             "qk_svm_decision", "qk_pathsum_gram", "qk_svm_fit_ovo", "qk_svm_predict_ovo", "qk_resolve_precision", "qk_set_refine_threshold", "qk_set_svd_sweep_limit", "qk_autotune",
             "qk_tune_export", "qk_tune_import", "qk_status_string",
             "qk_last_error", "qk_set_launch_timing", "qk_last_launch_ms"]
@@ -466,6 +475,62 @@ def qk_set_refine_threshold(prec, tau: float):
     """FP64 recomputation of tiles holding K_q > tau for a reduced form."""
     p = PREC[prec] if isinstance(prec, str) else int(prec)
     _check(_lib.qk_set_refine_threshold(p, float(tau)))
+
+
+class Preproc:
+    """Owns a qk_preproc handle (a fitted z-score / PCA / min-max)."""
+
+    def __init__(self, handle, d, k):
+        self._h, self.d, self.n_components = handle, d, k
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("fit released")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            _lib.qk_preproc_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+def qk_preproc_fit(x, n_components: int, stream=None) -> Preproc:
+    """Fit on the rows of x (float64 CUDA tensor, n x d)."""
+    xp, ld = _mat(x, "x")
+    h = C.c_void_p()
+    _check(_lib.qk_preproc_fit(xp, x.shape[0], ld, x.shape[1], int(n_components),
+                               _stream(stream), C.byref(h)))
+    return Preproc(h, x.shape[1], int(n_components))
+
+
+def qk_preproc_apply(p: Preproc, x, out, scale: float = 1.0, stream=None):
+    """Pre-process the rows of x into out (float64 CUDA tensor, n x k)."""
+    xp, ld = _mat(x, "x")
+    op, ldo = _mat(out, "out")
+    if out.shape[0] != x.shape[0] or out.shape[1] < p.n_components:
+        raise ValueError("out must be n x n_components")
+    _check(_lib.qk_preproc_apply(p.handle, xp, x.shape[0], ld, float(scale), op, ldo,
+                                 _stream(stream)))
+    return out
+
+
+def qk_preproc_info(p: Preproc) -> dict:
+    d, k, sw = C.c_int32(), C.c_int32(), C.c_int32()
+    lam = np.empty(p.d, dtype=np.float64)
+    _check(_lib.qk_preproc_info(p.handle, C.byref(d), C.byref(k), C.byref(sw),
+                                lam.ctypes.data_as(C.c_void_p)))
+    return {"d": d.value, "n_components": k.value, "sweeps": sw.value, "eigvals": lam}
+
+
+def qk_preproc_release(p: Preproc):
+    p.close()
 
 
 def qk_set_svd_sweep_limit(sweeps: int):
