@@ -99,6 +99,20 @@ qk_status qk_preproc_fit(const double* x_dev, int64_t n, int64_t ld_x, int32_t d
   PP_HIP(hipMalloc((void**)&rot, (m / 2) * sizeof(double2)), "allocation");
   PP_HIP(hipMalloc((void**)&perm, d * sizeof(int)), "allocation");
   PP_HIP(qk_launch_pp_colstats(x_dev, n, ld_x, d, p->mu, p->sigma, s), "column statistics");
+  {
+    // a non-finite feature makes a column statistic non-finite: refuse
+    std::string buf((size_t)2 * d * sizeof(double), '\0');
+    double* h = reinterpret_cast<double*>(&buf[0]);
+    PP_HIP(hipMemcpyAsync(h, p->mu, d * sizeof(double), hipMemcpyDeviceToHost, s), "read back");
+    PP_HIP(hipMemcpyAsync(h + d, p->sigma, d * sizeof(double), hipMemcpyDeviceToHost, s),
+           "read back");
+    PP_HIP(hipStreamSynchronize(s), "synchronise");
+    for (int i = 0; i < 2 * d; ++i)
+      if (!std::isfinite(h[i])) {
+        st = qk_fail(QK_ERR_INVALID_ARG, "non-finite feature in the training rows");
+        goto done;
+      }
+  }
   PP_HIP(qk_launch_pp_standardize(x_dev, n, ld_x, d, p->mu, p->sigma, z, s), "standardise");
   PP_HIP(qk_launch_pp_cov(z, n, d, c, s), "covariance");
   {

@@ -231,7 +231,9 @@ __global__ __launch_bounds__(kPpThreads) void pp_components_kernel(const double*
                                                                    double* __restrict__ w) {
   __shared__ double rv[kPpThreads / 64];
   __shared__ int ri[kPpThreads / 64];
-  const int k = blockIdx.x, col = perm[k];
+  const int k = blockIdx.x;
+  int col = perm[k];
+  col = col < 0 ? 0 : (col >= d ? d - 1 : col);  // a ranking over non-finite values
   double best = -1.0;
   int bi = d;
   for (int i = threadIdx.x; i < d; i += kPpThreads) {
@@ -364,6 +366,10 @@ hipError_t qk_launch_pp_offdiag(const double* c, int d, double* out, hipStream_t
 
 hipError_t qk_launch_pp_components(const double* c, const double* v, int d, int k, int* perm,
                                    double* lam, double* w, hipStream_t s) {
+  // every rank slot starts valid; with finite eigenvalues the ranking writes
+  // each slot exactly once
+  const hipError_t e = hipMemsetAsync(perm, 0, d * sizeof(int), s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(pp_rank_kernel, dim3(blocks_for(d, 128)), dim3(128), 0, s, c, d, perm, lam);
   hipLaunchKernelGGL(pp_components_kernel, dim3(k), dim3(kPpThreads), 0, s, v, d, perm, w);
   return hipGetLastError();
