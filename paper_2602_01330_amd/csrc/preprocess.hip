@@ -11,8 +11,10 @@
 //                        is D' - 1 rounds (D' = D rounded up to even) of D'/2
 //                        disjoint plane rotations chosen by a round-robin
 //                        tournament, applied as C <- J^T C J and V <- V J;
-//                        sweeps until the off-diagonal mass falls below
-//                        (1e-15)^2 of the total;
+//                        sweeps until the off-diagonal Frobenius mass falls
+//                        below 1e-12 of the total (or stops shrinking below
+//                        1e-10 of it, the rounding floor of degenerate
+//                        eigenvalue clusters);
 //   components           the eigenvectors of the n largest eigenvalues (ranked
 //                        on the device, ties to the smaller index), each with
 //                        its entry of largest magnitude positive;
