@@ -11,9 +11,9 @@
 //                        is D' - 1 rounds (D' = D rounded up to even) of D'/2
 //                        disjoint plane rotations chosen by a round-robin
 //                        tournament, applied as C <- J^T C J and V <- V J;
-//                        sweeps until the off-diagonal Frobenius mass falls
-//                        below 1e-12 of the total (or stops shrinking below
-//                        1e-10 of it, the rounding floor of degenerate
+//                        sweeps until the off-diagonal Frobenius norm falls
+//                        below 1e-12 of the whole (or stops shrinking below
+//                        1e-8 of it, the rounding floor of degenerate
 //                        eigenvalue clusters);
 //   components           the eigenvectors of the n largest eigenvalues (ranked
 //                        on the device, ties to the smaller index), each with
@@ -137,14 +137,17 @@ __device__ inline void rr_pair(int r, int i, int m, int& p, int& q) {
   }
 }
 
-// rotation of each pair of round r: (cos, sin) or (1, 0) when not needed
+// The rotation of each pair of round r: (cos, sin, new C_pp, new C_qq), or
+// sin = 0 when none is needed. The new diagonal uses the stable update
+// C_pp - t C_pq, C_qq + t C_pq (t = sin / cos), and the pair's own
+// off-diagonal entries are set to zero, as in exact arithmetic.
 __global__ void pp_jac_angles_kernel(const double* __restrict__ c, int d, int m, int r,
-                                     double2* __restrict__ rot) {
+                                     double4* __restrict__ rot) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m / 2) return;
   int p, q;
   rr_pair(r, i, m, p, q);
-  double cs = 1.0, sn = 0.0;
+  double cs = 1.0, sn = 0.0, na = 0.0, nb = 0.0;
   if (q < d) {  // the padding player never rotates
     const double a = c[(int64_t)p * d + p], b = c[(int64_t)q * d + q];
     const double g = c[(int64_t)p * d + q];
@@ -153,42 +156,65 @@ __global__ void pp_jac_angles_kernel(const double* __restrict__ c, int d, int m,
       const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
       cs = 1.0 / sqrt(fma(t, t, 1.0));
       sn = t * cs;
+      na = fma(-t, g, a);
+      nb = fma(t, g, b);
     }
   }
-  rot[i] = make_double2(cs, sn);
+  rot[i] = make_double4(cs, sn, na, nb);
 }
 
-// C <- J^T C: rows p, q of every pair; grid (pairs, column chunks)
+// (cp, cq) -> (cs cp - sn cq, sn cp + cs cq), one rounding order for every
+// element, so the row update of (p, j) and the column update of (j, p)
+// produce the same bits from the same inputs and C stays symmetric
+__device__ inline void rotate(double cs, double sn, double& cp, double& cq) {
+  const double u = sn * cq, v = cs * cq;
+  const double np = fma(cs, cp, -u), nq = fma(sn, cp, v);
+  cp = np;
+  cq = nq;
+}
+
+// C <- J^T C: rows p, q of every pair; grid (column chunks, pairs)
 __global__ void pp_jac_rows_kernel(double* __restrict__ c, int d, int m, int r,
-                                   const double2* __restrict__ rot) {
+                                   const double4* __restrict__ rot) {
   const int i = blockIdx.y;
-  const double2 cr = rot[i];
+  const double4 cr = rot[i];
   if (cr.y == 0.0) return;
   int p, q;
   rr_pair(r, i, m, p, q);
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= d) return;
-  const double cp = c[(int64_t)p * d + j], cq = c[(int64_t)q * d + j];
-  c[(int64_t)p * d + j] = cr.x * cp - cr.y * cq;
-  c[(int64_t)q * d + j] = cr.y * cp + cr.x * cq;
+  double cp = c[(int64_t)p * d + j], cq = c[(int64_t)q * d + j];
+  rotate(cr.x, cr.y, cp, cq);
+  c[(int64_t)p * d + j] = cp;
+  c[(int64_t)q * d + j] = cq;
 }
 
-// C <- C J and V <- V J: columns p, q of every pair
+// C <- C J and V <- V J: columns p, q of every pair; the pair's own 2 x 2
+// block takes the stable diagonal and exact zeros
 __global__ void pp_jac_cols_kernel(double* __restrict__ c, double* __restrict__ v, int d, int m,
-                                   int r, const double2* __restrict__ rot) {
+                                   int r, const double4* __restrict__ rot) {
   const int i = blockIdx.y;
-  const double2 cr = rot[i];
+  const double4 cr = rot[i];
   if (cr.y == 0.0) return;
   int p, q;
   rr_pair(r, i, m, p, q);
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= d) return;
-  const double cp = c[(int64_t)j * d + p], cq = c[(int64_t)j * d + q];
-  c[(int64_t)j * d + p] = cr.x * cp - cr.y * cq;
-  c[(int64_t)j * d + q] = cr.y * cp + cr.x * cq;
-  const double vp = v[(int64_t)j * d + p], vq = v[(int64_t)j * d + q];
-  v[(int64_t)j * d + p] = cr.x * vp - cr.y * vq;
-  v[(int64_t)j * d + q] = cr.y * vp + cr.x * vq;
+  double cp = c[(int64_t)j * d + p], cq = c[(int64_t)j * d + q];
+  rotate(cr.x, cr.y, cp, cq);
+  if (j == p) {
+    cp = cr.z;
+    cq = 0.0;
+  } else if (j == q) {
+    cp = 0.0;
+    cq = cr.w;
+  }
+  c[(int64_t)j * d + p] = cp;
+  c[(int64_t)j * d + q] = cq;
+  double vp = v[(int64_t)j * d + p], vq = v[(int64_t)j * d + q];
+  rotate(cr.x, cr.y, vp, vq);
+  v[(int64_t)j * d + p] = vp;
+  v[(int64_t)j * d + q] = vq;
 }
 
 // off-diagonal and total squared mass: out[0] = sum_{i != j} c_ij^2, out[1] = sum c_ij^2
@@ -350,7 +376,7 @@ hipError_t qk_launch_pp_project(const double* z, int64_t n, int d, const double*
   return hipGetLastError();
 }
 
-hipError_t qk_launch_pp_jacobi_round(double* c, double* v, int d, int m, int r, double2* rot,
+hipError_t qk_launch_pp_jacobi_round(double* c, double* v, int d, int m, int r, double4* rot,
                                      hipStream_t s) {
   const int pairs = m / 2;
   hipLaunchKernelGGL(pp_jac_angles_kernel, dim3(blocks_for(pairs, 128)), dim3(128), 0, s, c, d,
