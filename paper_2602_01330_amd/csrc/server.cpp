@@ -62,7 +62,6 @@ struct Request {
   double* f_host = nullptr;    // pinned n_rows decision values (admitted with a model)
   bool want_ln = false;        // also return ln K_q rows
   double* ln_host = nullptr;   // pinned n_rows x n_support ln K_q (want_ln)
-  size_t out_bytes = 0, f_bytes = 0, ln_bytes = 0;  // their pool sizes
   int group = -1;              // the iteration's d group (index of its build's status words)
 };
 
@@ -73,61 +72,8 @@ struct Iteration {
   std::map<int32_t, Support> sups;  // support sets used, copied under the lock
   std::vector<qk_mps_batch*> batches;
   std::vector<void*> dev;     // stream-ordered device buffers
-  std::vector<std::pair<void*, size_t>> pinned;  // host staging of features and weights
+  std::vector<void*> pinned;  // host staging of features and weights
   int32_t* status_host = nullptr;  // pinned: each d group's build status words (2 int32)
-  size_t status_bytes = 0;
-};
-
-// Pinned host buffers reused across requests and iterations by power-of-two
-// size class: allocating and freeing page-locked memory is slow and can
-// wait for the device, so each size is allocated once and kept (up to a
-// cap) until the server is destroyed.
-struct PinnedPool {
-  std::mutex mu;
-  std::map<size_t, std::vector<void*>> free_lists;
-  size_t cached = 0;
-  static constexpr size_t kCap = (size_t)1 << 30;
-  static size_t size_class(size_t b) {
-    size_t c = 4096;
-    while (c < b) c <<= 1;
-    return c;
-  }
-  void* get(size_t bytes) {
-    const size_t c = size_class(bytes);
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      auto& v = free_lists[c];
-      if (!v.empty()) {
-        void* p = v.back();
-        v.pop_back();
-        cached -= c;
-        return p;
-      }
-    }
-    void* p = nullptr;
-    if (hipHostMalloc(&p, c, 0) != hipSuccess) return nullptr;
-    return p;
-  }
-  void put(void* p, size_t bytes) {
-    if (!p) return;
-    const size_t c = size_class(bytes);
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      if (cached + c <= kCap) {
-        free_lists[c].push_back(p);
-        cached += c;
-        return;
-      }
-    }
-    (void)hipHostFree(p);
-  }
-  void clear() {
-    std::lock_guard<std::mutex> lk(mu);
-    for (auto& kv : free_lists)
-      for (void* p : kv.second) (void)hipHostFree(p);
-    free_lists.clear();
-    cached = 0;
-  }
 };
 
 }  // namespace
@@ -146,7 +92,6 @@ struct qk_server {
   std::vector<double*> old_coefs;  // replaced models, freed at destroy (iterations may hold them)
   std::vector<hipStream_t> streams;
   std::vector<bool> slot_busy;
-  PinnedPool pinned;
   std::deque<Iteration*> inflight;
   int64_t next_id = 1;
   int64_t budget_used = 0, peak = 0;
@@ -171,10 +116,10 @@ int64_t request_bytes(const Request& r, const Support& sup) {
          + (r.want_ln ? rows * ns * 8 : 0);                                   // ln K_q rows
 }
 
-void free_host(qk_server* s, Request* r) {
-  s->pinned.put(r->out_host, r->out_bytes);
-  s->pinned.put(r->f_host, r->f_bytes);
-  s->pinned.put(r->ln_host, r->ln_bytes);
+void free_host(Request* r) {
+  if (r->out_host) (void)hipHostFree(r->out_host);
+  if (r->f_host) (void)hipHostFree(r->f_host);
+  if (r->ln_host) (void)hipHostFree(r->ln_host);
   r->out_host = nullptr;
   r->f_host = nullptr;
   r->ln_host = nullptr;
@@ -199,10 +144,10 @@ void retire(qk_server* s, Iteration* it) {
     const int32_t flags =
         (it->status_host && r->group >= 0) ? it->status_host[2 * r->group] : 0;
     if (r->cancel) {
-      free_host(s, r);
+      free_host(r);
       finish(s, r, QK_REQ_CANCELLED);
     } else if (flags) {
-      free_host(s, r);
+      free_host(r);
       finish(s, r, QK_REQ_FAILED, qk_flag_text(flags));
     } else {
       finish(s, r, QK_REQ_DONE);
@@ -211,8 +156,8 @@ void retire(qk_server* s, Iteration* it) {
   hipStream_t st = s->streams[it->slot];
   for (qk_mps_batch* b : it->batches) qk_mps_release_nosync(b, st);
   for (void* p : it->dev) (void)hipFreeAsync(p, st);
-  for (auto& pb : it->pinned) s->pinned.put(pb.first, pb.second);
-  s->pinned.put(it->status_host, it->status_bytes);
+  for (void* p : it->pinned) (void)hipHostFree(p);
+  if (it->status_host) (void)hipHostFree(it->status_host);
   (void)hipEventDestroy(it->done);
   s->slot_busy[it->slot] = false;
   delete it;
@@ -241,9 +186,8 @@ std::string launch(qk_server* s, Iteration* it) {
   };
   std::vector<Decision> decisions;
   std::vector<Out> outs;
-  it->status_bytes = 2 * by_d.size() * sizeof(int32_t);
-  it->status_host = static_cast<int32_t*>(s->pinned.get(it->status_bytes));
-  if (!it->status_host) return "pinned status allocation failed";
+  if (hipHostMalloc((void**)&it->status_host, 2 * by_d.size() * sizeof(int32_t), 0) != hipSuccess)
+    return "pinned status allocation failed";
   int group = 0;
   for (auto& kv : by_d) {
     const Support& sup = it->sups.at(kv.first);
@@ -256,11 +200,11 @@ std::string launch(qk_server* s, Iteration* it) {
     }
     double *hx = nullptr, *hw = nullptr, *dx = nullptr, *dw = nullptr, *dk = nullptr;
     double* dln = nullptr;
-    hx = static_cast<double*>(s->pinned.get(rows * d * sizeof(double)));
-    if (hx) it->pinned.push_back({hx, rows * d * sizeof(double)});
-    hw = static_cast<double*>(s->pinned.get(rows * sizeof(double)));
-    if (hw) it->pinned.push_back({hw, rows * sizeof(double)});
-    if (!hx || !hw) return "pinned staging allocation failed";
+    if (hipHostMalloc((void**)&hx, rows * d * sizeof(double), 0) != hipSuccess ||
+        hipHostMalloc((void**)&hw, rows * sizeof(double), 0) != hipSuccess)
+      return "pinned staging allocation failed";
+    it->pinned.push_back(hx);
+    it->pinned.push_back(hw);
     int64_t off = 0;
     for (Request* r : kv.second) {
       std::memcpy(hx + off * d, r->x.data(), r->n_rows * d * sizeof(double));
@@ -395,20 +339,13 @@ void worker_main(qk_server* s) {
         if (s->budget_used + need > budget || rows + r->n_rows > max_rows) break;
         // one sweep task per d: at most QK_MAX_TASKS distinct d per iteration
         if (it && !it->sups.count(r->d) && (int)it->sups.size() >= QK_MAX_TASKS) break;
-        if (!r->out_host) {
-          r->out_bytes = r->n_rows * sup.n * sizeof(double);
-          r->out_host = static_cast<double*>(s->pinned.get(r->out_bytes));
-        }
-        if (sup.coef && !r->f_host) {
-          r->f_bytes = r->n_rows * sizeof(double);
-          r->f_host = static_cast<double*>(s->pinned.get(r->f_bytes));
-        }
-        if (r->want_ln && !r->ln_host) {
-          r->ln_bytes = r->n_rows * sup.n * sizeof(double);
-          r->ln_host = static_cast<double*>(s->pinned.get(r->ln_bytes));
-        }
-        if (!r->out_host || (sup.coef && !r->f_host) || (r->want_ln && !r->ln_host)) {
-          free_host(s, r);
+        if ((!r->out_host &&
+             hipHostMalloc((void**)&r->out_host, r->n_rows * sup.n * sizeof(double), 0) != hipSuccess) ||
+            (sup.coef && !r->f_host &&
+             hipHostMalloc((void**)&r->f_host, r->n_rows * sizeof(double), 0) != hipSuccess) ||
+            (r->want_ln && !r->ln_host &&
+             hipHostMalloc((void**)&r->ln_host, r->n_rows * sup.n * sizeof(double), 0) != hipSuccess)) {
+          free_host(r);
           s->pending.pop_front();
           finish(s, r, QK_REQ_FAILED, "pinned result allocation failed");
           s->cv_done.notify_all();
@@ -646,7 +583,7 @@ qk_status qk_server_poll_ex(qk_server* s, int64_t id, double* rows_host, int64_t
         std::memcpy(ln_host + q * ld_ln, r->ln_host + q * r->n_support,
                     r->n_support * sizeof(double));
     if (f_host) std::memcpy(f_host, r->f_host, r->n_rows * sizeof(double));
-    free_host(s, r);
+    free_host(r);
     s->reqs.erase(f);
     delete r;
   } else if (r->state == QK_REQ_CANCELLED && fetch) {
@@ -728,10 +665,9 @@ qk_status qk_server_destroy(qk_server* s) {
   if (s->worker.joinable()) s->worker.join();
   (void)hipDeviceSynchronize();
   for (auto& kv : s->reqs) {
-    free_host(s, kv.second);
+    free_host(kv.second);
     delete kv.second;
   }
-  s->pinned.clear();
   for (auto& kv : s->supports) {
     qk_mps_release(kv.second.mps);
     (void)hipFree(kv.second.x);

@@ -11,11 +11,10 @@
 // wavefront at 16 and 8. E and the intermediate G^s = E B^s sit in LDS
 // (2 T^2 complex, rows padded by one element: 130 KB at T = 64). Each thread
 // computes a KR x KC register tile of G^s and of E' (4 x 2 at T = 64, 2 x 2
-// at 32 and 16, 1 x 1 at 8), so that every operand it loads (B^s or A^s
-// elements from memory, E or G^s elements from LDS) serves several
-// products; the tile's KC columns are T / KC apart, so the lanes of a
-// wavefront read one contiguous run of a B^s or G^s row, and its tile rows
-// share the E, A^s reads.
+// at 32 and 16, 1 x 1 at 8), so that every operand it loads (a row segment
+// of B^s or A^s from memory, a column segment of E or G^s from LDS) serves
+// several products; the tile columns of a wavefront read one contiguous row
+// of B^s or G^s, and its tile rows share the E, A^s reads.
 // Every entry follows the operation order of the FP64 tile kernel (G over b
 // ascending, E' over s then a ascending).
 #include <hip/hip_runtime.h>
@@ -64,10 +63,7 @@ __device__ void sweep_pair(const QkTask& t, int64_t i, int64_t j, BigSmem<T>& sm
   constexpr int kThreads = S::kThreads;
   const int tid = threadIdx.x;
   const int r0 = (tid / S::GC) * KR;  // tile rows a (or a')
-  // tile columns b' = c0 + y GC: neighbouring lanes take neighbouring
-  // columns, so every LDS access of a wavefront covers consecutive 16-byte
-  // elements (no bank conflicts) and every B^s row load is one contiguous run
-  const int c0 = tid % S::GC;
+  const int c0 = (tid % S::GC) * KC;  // tile columns b'
   const double* ta = static_cast<const double*>(t.ta);
   const double* tb = static_cast<const double*>(t.tb);
   const int nq = t.nq;
@@ -96,7 +92,7 @@ __device__ void sweep_pair(const QkTask& t, int64_t i, int64_t j, BigSmem<T>& sm
 #pragma unroll
           for (int x = 0; x < KR; ++x) ev[x] = sm.e[(r0 + x) * P + b];
 #pragma unroll
-          for (int y = 0; y < KC; ++y) bv[y] = B[s * TT + b * T + c0 + y * S::GC];
+          for (int y = 0; y < KC; ++y) bv[y] = B[s * TT + b * T + c0 + y];
 #pragma unroll
           for (int x = 0; x < KR; ++x)
 #pragma unroll
@@ -105,8 +101,7 @@ __device__ void sweep_pair(const QkTask& t, int64_t i, int64_t j, BigSmem<T>& sm
 #pragma unroll
         for (int x = 0; x < KR; ++x)
 #pragma unroll
-          for (int y = 0; y < KC; ++y)
-            sm.g[(r0 + x) * P + c0 + y * S::GC] = make_double2(gr[x][y], gi[x][y]);
+          for (int y = 0; y < KC; ++y) sm.g[(r0 + x) * P + c0 + y] = make_double2(gr[x][y], gi[x][y]);
       }
       __syncthreads();
       // E'[a'][b'] += sum_a conj(A^s[a][a']) G^s[a][b'], a' in r0.., b' in c0..
@@ -115,7 +110,7 @@ __device__ void sweep_pair(const QkTask& t, int64_t i, int64_t j, BigSmem<T>& sm
 #pragma unroll
         for (int x = 0; x < KR; ++x) av[x] = A[s * TT + a * T + r0 + x];
 #pragma unroll
-        for (int y = 0; y < KC; ++y) gv[y] = sm.g[a * P + c0 + y * S::GC];
+        for (int y = 0; y < KC; ++y) gv[y] = sm.g[a * P + c0 + y];
 #pragma unroll
         for (int x = 0; x < KR; ++x)
 #pragma unroll
@@ -141,7 +136,7 @@ __device__ void sweep_pair(const QkTask& t, int64_t i, int64_t j, BigSmem<T>& sm
     for (int x = 0; x < KR; ++x)
 #pragma unroll
       for (int y = 0; y < KC; ++y)
-        sm.e[(r0 + x) * P + c0 + y * S::GC] = make_double2(nr[x][y] * sc, ni[x][y] * sc);
+        sm.e[(r0 + x) * P + c0 + y] = make_double2(nr[x][y] * sc, ni[x][y] * sc);
     __syncthreads();
   }
   // epilogue: ln K_q = 2 (ln|E[0][0]| + expo ln 2), K_q, fused RBF and mix

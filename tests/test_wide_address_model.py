@@ -304,18 +304,18 @@ def test_big_pair_sweep_accesses_in_bounds(T):
     assert per_cu * lds <= LDS_PER_CU
     tid = np.arange(nthr)
     r0 = (tid // GC) * KR
-    c0 = tid % GC  # tile columns c0 + y GC
+    c0 = (tid % GC) * KC
     TT = T * T
     # E and G^s: rows r0 + x < T, columns b < T or c0 + y < T, pitch P
     rows = (r0[:, None] + np.arange(KR)[None, :]).ravel()
-    cols = (c0[:, None] + GC * np.arange(KC)[None, :]).ravel()
+    cols = (c0[:, None] + np.arange(KC)[None, :]).ravel()
     assert rows.max() < T and cols.max() < T
     assert rows.max() * P + (T - 1) < T * P and (T - 1) * P + cols.max() < T * P
     # every (r0 + x, c0 + y) of E' is written by exactly one thread
     cover = np.zeros((T, T), dtype=np.int64)
     for x in range(KR):
         for y in range(KC):
-            np.add.at(cover, (r0 + x, c0 + GC * y), 1)
+            np.add.at(cover, (r0 + x, c0 + y), 1)
     assert np.all(cover == 1)
     # site reads A[s TT + a T + r0 + x], B[s TT + b T + c0 + y] inside a slot
     assert (TT + (T - 1) * T + rows.max()) < 2 * TT
