@@ -66,15 +66,33 @@ def algorithmic_flops(chi_rows, chi_cols, symmetric):
     return 16.0 * float((cu * v).sum() + (cw * z).sum())
 
 
-def traffic_for(form):
-    """Measured HBM bytes per launch, or None if the kernel changed since."""
+def traffic_for(form, shape=None):
+    """Measured HBM bytes per launch, or None if the kernel changed since or
+    (for an entry taken at one launch shape) the launch used another shape:
+    the tile order and the workgroups per CU decide how much of the operand
+    stream the L2 caches share."""
     import hashlib
     t = TRAFFIC.get(form)
     if t is None:
         return None
+    if "shape" in t and (shape is None or tuple(shape) != tuple(t["shape"])):
+        return None
     with open(os.path.join(ROOT, t["source"]), "rb") as f:
         h = hashlib.sha256(f.read()).hexdigest()
     return t["bytes"] if h.startswith(t["sha256_prefix"]) else None
+
+
+def launch_shape(tune_text, T, nq, form_code):
+    """(workgroups per CU, band height) of the tuning entry for bond bound T
+    and nq qubits when it was tuned for this form (else the library's
+    defaults, 2 and 4), from the text of qk_tune_export: one entry per line,
+    'T bucket form wg_per_cu band us_per_tile', bucket = ceil(log2 nq)."""
+    bucket = max(0, math.ceil(math.log2(nq))) if nq > 1 else 0
+    for line in (tune_text or "").splitlines():
+        f = line.split()
+        if len(f) >= 5 and int(f[0]) == T and int(f[1]) == bucket and int(f[2]) == form_code:
+            return int(f[3]), int(f[4])
+    return 2, 4
 
 
 def gpu_state_held():
@@ -950,7 +968,13 @@ def run(args):
 
     chosen = args.prec
     tune = None
-    if chosen == "auto":
+    if args.tune_table:
+        # a fixed tuning table (';' between entries) instead of the
+        # autotuner's run: profiles repeat one launch shape exactly
+        qk.qk_tune_import(args.tune_table.replace(";", "\n") + "\n")
+        tune = qk.qk_tune_export()
+        log(f"bench: tuning table imported: {tune.strip()}")
+    if chosen == "auto" and not args.tune_table:
         # the project autotuner times the eligible forms on a slice of the
         # train x train tiles; AUTO then resolves to the winner
         b = qk.qk_mps_build(xtr, 2, 64, 1e-10, store=qk.QK_STORE_ALL)
@@ -958,7 +982,12 @@ def run(args):
         tune = qk.qk_tune_export()
         b.close()
         log(f"bench: autotune chose {chosen}")
+    if chosen == "auto":
+        b = qk.qk_mps_build(xtr, 2, 64, 1e-10, store=qk.QK_STORE_ALL)
+        chosen = qk.qk_resolve_precision(b, b)
+        b.close()
     res = measure(chosen, args.steps, args.warmup)
+    shape = launch_shape(qk.qk_tune_export(), res["chi_pad"], d, qk.PREC[chosen])
     value = pairs / (res["ms_per_step"] / 1e3)
     bound, peak = PEAKS[chosen]
     achieved = res["flops"] / (res["kernel_ms"] / 1e3) / 1e12
@@ -974,7 +1003,8 @@ def run(args):
                    "chi_realized_max": res["chi_max_realized"], "chi_pad": res["chi_pad"],
                    "unique_pairs": pairs, "sweep_form": chosen, "autotune_table": tune},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic_for(chosen),
+                     "frac": achieved / peak, "traffic": traffic_for(chosen, shape),
+                     "launch_shape": {"wg_per_cu": shape[0], "band": shape[1]},
                      "kernel": "sweep (one persistent launch per step)",
                      "kernel_ms": res["kernel_ms"], "algorithmic_flop": res["flops"],
                      "gram_call_ms": res["sweep_ms"], "fp64_refine_ms": res["refine_ms"]},
@@ -1037,6 +1067,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="auto",
                     choices=["auto", "fp64", "fp32", "fp32_mfma", "bf16x2", "bf16x3"])
+    ap.add_argument("--tune-table", default=None,
+                    help="import this tuning table ('T bucket form wg band us' entries "
+                         "separated by ';') instead of running the autotuner")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

@@ -57,3 +57,33 @@ def test_pathsum_flop_count():
     assert pathsum_flops(1, 2, 10) == 420.0
     # L = 3: 80 butterflies, the phase, q^3 / r^3, 16 cross products, 32 states
     assert pathsum_flops(3, 3, 1) == 2 * (80 * 14 + 6 + 52 * 6) + 52 * 6
+
+
+def test_launch_shape_from_the_tuning_table():
+    """The headline's launch shape is read from the tuning entry of its bond
+    bound and qubit bucket (ceil(log2 784) = 10), only when that entry was
+    tuned for the form that runs; otherwise the library defaults (2, 4)."""
+    table = "2 1 5 1 4 0.07\n4 9 5 2 2 2.3\n4 10 5 1 8 3.46\n4 10 0 2 4 9.0\n"
+    assert bench.launch_shape(table, 4, 784, 5) == (1, 8)
+    assert bench.launch_shape(table, 4, 512, 5) == (2, 2)
+    assert bench.launch_shape(table, 4, 784, 1) == (2, 4)
+    assert bench.launch_shape("", 4, 784, 5) == (2, 4)
+    assert bench.launch_shape(table, 2, 2, 5) == (1, 4)
+
+
+def test_traffic_is_reported_only_for_its_source_and_launch_shape(monkeypatch, tmp_path):
+    import hashlib
+    src = tmp_path / "k.hip"
+    src.write_bytes(b"kernel")
+    h = hashlib.sha256(b"kernel").hexdigest()[:16]
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "TRAFFIC", {
+        "a": {"source": "k.hip", "sha256_prefix": h, "bytes": 5.0, "shape": (1, 8)},
+        "b": {"source": "k.hip", "sha256_prefix": h, "bytes": 7.0},
+        "c": {"source": "k.hip", "sha256_prefix": "0" * 16, "bytes": 9.0}})
+    assert bench.traffic_for("a", (1, 8)) == 5.0
+    assert bench.traffic_for("a", (2, 4)) is None
+    assert bench.traffic_for("a") is None
+    assert bench.traffic_for("b") == 7.0
+    assert bench.traffic_for("c") is None
+    assert bench.traffic_for("missing") is None
