@@ -35,8 +35,9 @@ Quantum-Classical Dual Kernel"):
 
 Pins (what ties each function to something other than itself) are listed in
 the test-suite docstrings. ``mps.build_mps`` in the truncating regime
-(chi_max below the exact bond dimension) is pinned only on <= 16 qubits
-through the discarded-weight bound; beyond that it is parity unpinned
-(its own step-by-step replay is the reference).
+(chi_max below the exact bond dimension) is pinned only on <= 20 qubits
+(including the 8-layer, chi_max 64 schedule of the truncating workload)
+through the discarded-weight bound against exact statevectors; beyond that
+it is parity unpinned (its own step-by-step replay is the reference).
 """
 from . import circuit, statevector, closed_form, pathsum, mps, classical, checks, svm, preprocess  # noqa: F401
