@@ -113,3 +113,33 @@ def test_pathsum_rejects_a_negative_gamma_and_sweep_limit_range():
     assert lib.qk_set_svd_sweep_limit(-1) == -1
     assert lib.qk_set_svd_sweep_limit(1001) == -1
     assert lib.qk_set_svd_sweep_limit(60) == 0
+
+
+def test_argument_checks_of_preprocessing_and_the_allocation_free_call_without_gpu():
+    """qk_preproc_fit / qk_preproc_apply reject bad sizes, leading dimensions,
+    component counts and scales before any allocation or launch; the
+    allocation-free Gram call rejects a NULL batch first. Pointers are never
+    dereferenced."""
+    lib = ctypes.CDLL(LIB)
+    P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.qk_preproc_fit.argtypes = [P, I64, I64, I32, I32, P, ctypes.POINTER(P)]
+    lib.qk_preproc_apply.argtypes = [P, P, I64, I64, D, P, I64, P]
+    lib.qk_overlap_gram_noalloc.argtypes = [P, P, I32, I32, P, I64, P, I64, P, P]
+    INVALID = -1
+    fake = P(0x1000)
+    out = P()
+    fit = lambda x, n, ld, d, k: lib.qk_preproc_fit(x, n, ld, d, k, None, ctypes.byref(out))
+    assert fit(None, 10, 8, 8, 2) == INVALID          # no features
+    assert fit(fake, 1, 8, 8, 2) == INVALID           # one row: no covariance
+    assert fit(fake, 10, 8, 0, 1) == INVALID          # d < 1
+    assert fit(fake, 10, 9000, 8193, 2) == INVALID    # d above 8192
+    assert fit(fake, 10, 7, 8, 2) == INVALID          # ld_x < d
+    assert fit(fake, 10, 8, 8, 0) == INVALID          # no component
+    assert fit(fake, 10, 8, 8, 9) == INVALID          # more components than features
+    assert fit(fake, 2 ** 31, 8, 8, 2) == INVALID     # rows beyond int32
+    assert lib.qk_preproc_fit(fake, 10, 8, 8, 2, None, None) == INVALID  # no out pointer
+    assert not out.value
+    # apply: NULL handle first, then the arguments
+    assert lib.qk_preproc_apply(None, fake, 4, 8, 1.0, fake, 2, None) == INVALID
+    assert lib.qk_preproc_release(None) == 0
+    assert lib.qk_overlap_gram_noalloc(None, None, 1, 5, fake, 4, None, 0, None, None) == INVALID
