@@ -87,3 +87,29 @@ def test_traffic_is_reported_only_for_its_source_and_launch_shape(monkeypatch, t
     assert bench.traffic_for("b") == 7.0
     assert bench.traffic_for("c") is None
     assert bench.traffic_for("missing") is None
+
+
+def test_all_pairs_gap_counts_unique_pairs_only():
+    """The chosen-vs-plain comparison covers the train upper triangle (with
+    the diagonal) and every test row; the lower train triangle (a mirror) is
+    ignored, and two -inf logs (an exactly zero amplitude) count as equal."""
+    torch = pytest.importorskip("torch")
+    ntr, nte = 5, 3
+    z = lambda r, c: torch.zeros((r, c), dtype=torch.float64)
+    plain = {"ln": z(ntr, ntr), "kq": z(ntr, ntr), "k": z(ntr, ntr)}
+    plain_te = {"ln": z(nte, ntr), "kq": z(nte, ntr), "k": z(nte, ntr)}
+    ch = {k: (v.clone(), plain_te[k].clone()) for k, v in plain.items()}
+    ch["ln"][0][3, 1] = 5.0          # lower triangle: not a unique pair
+    ch["ln"][0][1, 3] = 2e-3         # upper triangle
+    ch["ln"][0][2, 2] = 5e-4         # diagonal
+    ch["ln"][1][2, 4] = -3e-3        # test row
+    ch["ln"][0][0, 4] = -float("inf")
+    plain["ln"][0, 4] = -float("inf")
+    ch["kq"][1][0, 0] = 1e-7
+    ch["k"][0][4, 4] = 2e-6
+    res = bench.all_pairs_gap(ch, plain, plain_te, ntr)
+    assert res["max_abs_dln"] == pytest.approx(3e-3)
+    assert res["pairs_above_ln_gate_1e-3"] == 2
+    assert res["pairs_above_ln_1e-4"] == 3
+    assert res["max_abs_dkq"] == pytest.approx(1e-7)
+    assert res["max_abs_dk"] == pytest.approx(2e-6)
