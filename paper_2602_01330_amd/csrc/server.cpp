@@ -380,6 +380,7 @@ void worker_main(qk_server* s) {
         for (Request* r : it->reqs) {
           s->budget_used -= r->bytes;
           r->bytes = 0;
+          free_host(r);  // the stream has drained: no copy still targets them
           finish(s, r, QK_REQ_FAILED, err);
         }
         it->reqs.clear();
