@@ -22,7 +22,9 @@ The merged matrices differ from the device's by the gauge of earlier steps
 and the sweep counts close to, not equal to, the device's.
 
 Test infrastructure: run as `python -m tests.build_work_model [every]
-[build_seconds samples]` from the repository root.
+[build_seconds samples]` from the repository root for the FLOP tally, or
+with `--orderings` for the sweep counts of alternative Jacobi set-ups on
+the last layer's full-bond matrices.
 """
 import math
 import sys
@@ -54,16 +56,17 @@ def round_robin_rounds(C):
     return rounds
 
 
-def jacobi_model(X, tol=1e-14, max_sweeps=1000):
-    """One-sided Jacobi under the device's rule. Returns (singular values in
-    decreasing order, sweeps including the final one without a rotation,
-    rotations applied)."""
+def jacobi_model(X, tol=1e-14, max_sweeps=1000, floor=1e-30):
+    """One-sided Jacobi under the device's rule (tolerance 1e-14, squared
+    column-norm floor 1e-30 of the matrix's; both can be varied to study
+    the sweep count). Returns (singular values in decreasing order, sweeps
+    including the final one without a rotation, rotations applied)."""
     X = np.array(X, dtype=np.complex128, copy=True)
     R, C = X.shape
     if C % 2:
         X = np.concatenate([X, np.zeros((R, 1), X.dtype)], axis=1)
         C += 1
-    floor2 = 1e-30 * float(np.sum(np.abs(X) ** 2))
+    floor2 = floor * float(np.sum(np.abs(X) ** 2))
     rounds = round_robin_rounds(C)
     rotations = 0
     sweeps = max_sweeps
@@ -93,6 +96,56 @@ def jacobi_model(X, tol=1e-14, max_sweeps=1000):
             break
     sv = np.sort(np.sqrt(np.sum(np.abs(X) ** 2, axis=0)))[::-1]
     return sv, sweeps, rotations
+
+
+def preconditioned_jacobi(X, twice=False):
+    """The same rule on R^H after a Householder QR with column pivoting of X
+    (X P = Q R; R^H has the singular values of X, and for graded matrices
+    its columns are close to orthogonal already), optionally after a second
+    QR without pivoting (R^H = Q2 R2, Jacobi on R2^H). Returns what
+    jacobi_model returns."""
+    import scipy.linalg as sl
+    _, Rm, _ = sl.qr(np.asarray(X, dtype=np.complex128), pivoting=True, mode="economic")
+    Y = Rm.conj().T
+    if twice:
+        _, R2 = np.linalg.qr(Y)
+        Y = R2.conj().T
+    return jacobi_model(Y)
+
+
+def merged_matrices(x, n_layers, chi_max, layer, every, cutoff=1e-10, full_bond_only=True):
+    """The merged two-site matrices of one layer of the oracle's build of one
+    sample (every `every`-th step; by default only steps whose bonds are both
+    at the cap)."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    A = [np.array([[[1.0], [0.0]]], dtype=np.complex128) for _ in range(n)]
+    theta = rzz_angles(x) * entangler_mask(n, True)
+    mats = []
+    for lay in range(layer + 1):
+        for k in range(n):
+            A[k] = np.einsum("st,atb->asb", rz(2.0 * x[k]) @ HADAMARD, A[k])
+        l2r = lay % 2 == 0
+        order = range(n - 1) if l2r else range(n - 2, -1, -1)
+        for idx, k in enumerate(order):
+            chl, chr_ = A[k].shape[0], A[k + 1].shape[2]
+            th = np.tensordot(A[k], A[k + 1], axes=([2], [0]))
+            th = th * np.exp(-0.5j * theta[k] * np.outer(_SIGMA, _SIGMA))[None, :, :, None]
+            M = th.reshape(chl * 2, 2 * chr_)
+            if lay == layer and idx % every == every // 2 and (
+                    not full_bond_only or (chl == chi_max and chr_ == chi_max)):
+                mats.append(M.copy())
+            u, s, vh = np.linalg.svd(M, full_matrices=False)
+            keep = max(1, min(int(np.count_nonzero(s > cutoff * s[0])), chi_max))
+            u, s, vh = u[:, :keep], s[:keep], vh[:keep]
+            s = s / np.linalg.norm(s)
+            if l2r:
+                A[k] = u.reshape(chl, 2, keep)
+                A[k + 1] = (s[:, None] * vh).reshape(keep, 2, chr_)
+            else:
+                A[k] = (u * s[None, :]).reshape(chl, 2, keep)
+                A[k + 1] = vh.reshape(keep, 2, chr_)
+    return mats
 
 
 def step_flop(R, C, chi_m, keep, sweeps, rotations):
@@ -146,9 +199,39 @@ def work_of_sample(x, n_layers, chi_max, cutoff=1e-10, every=8):
     return out
 
 
+def compare_orderings(x, every=30):
+    """Sweeps of the device rule on the last layer's full-bond merged
+    matrices, against a looser tolerance, a column-norm floor at the
+    truncation cutoff, and QR-preconditioned Jacobi (once and twice)."""
+    mats = merged_matrices(x, 8, 64, 7, every)
+    rows = []
+    for M in mats:
+        ref = np.linalg.svd(M, compute_uv=False)
+        out = {}
+        for name, (sv, S, _) in (("device rule", jacobi_model(M)),
+                                 ("tolerance 1e-8", jacobi_model(M, tol=1e-8)),
+                                 ("floor at the cutoff", jacobi_model(M, floor=1e-20)),
+                                 ("QR with pivoting, then Jacobi on R^H", preconditioned_jacobi(M)),
+                                 ("two QRs, then Jacobi", preconditioned_jacobi(M, True))):
+            k = min(64, len(ref))
+            out[name] = (S, float(np.max(np.abs(sv[:k] - ref[:k])) / ref[0]))
+        rows.append(out)
+    return rows
+
+
 if __name__ == "__main__":
     from synthdata import config_inputs
 
+    if len(sys.argv) > 1 and sys.argv[1] == "--orderings":
+        x, _, _ = config_inputs("S1", n_train=1, n_test=0)
+        rows = compare_orderings(x[0])
+        print(f"{len(rows)} merged 128 x 128 matrices of layer 8")
+        for name in rows[0]:
+            S = [r[name][0] for r in rows]
+            e = max(r[name][1] for r in rows)
+            print(f"{name}: sweeps {min(S)}..{max(S)} (mean {np.mean(S):.1f}); "
+                  f"kept singular values within {e:.1e} s_0 of LAPACK's")
+        sys.exit(0)
     every = int(sys.argv[1]) if len(sys.argv) > 1 else 8
     x, _, _ = config_inputs("S1", n_train=1, n_test=0)
     rows = work_of_sample(x[0], 8, 64, 1e-10, every)

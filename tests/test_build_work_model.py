@@ -52,3 +52,22 @@ def test_step_flop_formula():
     R, C, m, keep, S, rot = 128, 128, 64, 64, 3, 1000
     assert step_flop(R, C, m, keep, S, rot) == (
         8 * R * C * m + S * (C * (C - 1) // 2) * 16 * R + rot * 14 * R + 8 * keep * R * C)
+
+
+def test_qr_preconditioned_jacobi_keeps_the_singular_values():
+    """Jacobi on R^H after a QR with column pivoting (once, or with a second
+    QR) has the singular values of the original matrix, and on a strongly
+    graded matrix needs fewer sweeps than Jacobi on the matrix itself."""
+    pytest.importorskip("scipy")
+    from tests.build_work_model import preconditioned_jacobi
+    rng = np.random.default_rng(11)
+    U, _ = np.linalg.qr(rng.normal(size=(48, 48)) + 1j * rng.normal(size=(48, 48)))
+    V, _ = np.linalg.qr(rng.normal(size=(48, 48)) + 1j * rng.normal(size=(48, 48)))
+    s = 10.0 ** -np.linspace(0, 10, 48)
+    X = (U * s) @ V.conj().T
+    ref = np.linalg.svd(X, compute_uv=False)
+    _, plain, _ = jacobi_model(X)
+    for twice in (False, True):
+        sv, sweeps, _ = preconditioned_jacobi(X, twice)
+        assert np.allclose(sv[:24], ref[:24], rtol=0, atol=1e-13 * ref[0])
+        assert sweeps < plain
