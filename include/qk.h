@@ -59,9 +59,9 @@ typedef enum {
 typedef enum {
   QK_PREC_FP64 = 0,      /* complex FP64 on VALU: the plain comparator     */
   QK_PREC_FP32 = 1,      /* complex FP32 on VALU                           */
-  QK_PREC_BF16X2 = 2,    /* split BF16 (hi+lo, 3 products) on MFMA, FP32 acc */
-  QK_PREC_BF16X3 = 3,    /* split BF16 (3 pieces, 6 products) on MFMA       */
-  QK_PREC_AUTO = 4,      /* fastest form that meets the stated tolerance    */
+  QK_PREC_BF16X2 = 2,    /* split BF16 (h+l, 4 products) on MFMA, FP32 acc  */
+  QK_PREC_BF16X3 = 3,    /* split BF16 (exact h+m+l, 8 products) on MFMA    */
+  QK_PREC_AUTO = 4,      /* tuned/default form at bonds <= 4; FP64 at 8..64 */
   QK_PREC_FP32_MFMA = 5  /* complex FP32 on v_mfma_f32_4x4x1_16b_f32       */
 } qk_precision;
 
@@ -211,8 +211,10 @@ typedef struct {
 /*
  * qk_overlap_gram -- K_q for every pair (row sample i, column sample j)
  * (Eq. (7)) by the transfer-matrix sweep E_{k+1} = sum_s A_k^{s dagger} E_k
- * B_k^s, E_0 = 1, with an exact power-of-two rescale of E after every site
- * and an int32 exponent; ln K_q = 2 (ln|E_n| + e ln 2) in FP64 and
+ * B_k^s, E_0 = 1, with an exact power-of-two rescale of E (after every site
+ * in the VALU forms, every 8 sites in the matrix-core forms; a power of two
+ * is exact, so the period does not change a normal value) and an int32
+ * exponent; ln K_q = 2 (ln|E_n| + e ln 2) in FP64 and
  * K_q = exp(ln K_q) (0 once below the FP64 range).
  *   rows, cols   batches with the same qubit count and chi_pad.
  *   symmetric    1: rows == cols; only j >= i is contracted and both
@@ -425,7 +427,10 @@ QK_API qk_status qk_set_refine_threshold(qk_precision prec, double tau);
  * factorisation behind the bond truncation of each two-qubit gate step). A
  * build whose SVD has not converged after `sweeps` sweeps latches the
  * non-convergence flag, which qk_mps_info reports and the server turns into
- * a failed request. Default 60 (converged builds take 2 to 4 sweeps per SVD);
+ * a failed request. Default 60 (converged builds take 2 to 4 sweeps per SVD
+ * at bond bounds <= 4; a host replay of the rotation rule on a 784-qubit,
+ * 8-layer image counts up to 38 at bond 64, where the merged matrices are
+ * strongly graded);
  * accepted range [0, 1000]; 0 makes every SVD report non-convergence.
  * Process-wide; applies to builds launched after the call.
  * Errors: INVALID_ARG.
@@ -477,23 +482,32 @@ QK_API qk_status qk_preproc_info(const qk_preproc* p, int32_t* d, int32_t* n_com
 QK_API qk_status qk_preproc_release(qk_preproc* p);
 
 /*
- * qk_autotune -- times the sweep forms that meet the stated tolerance
- * (complex FP64, complex FP32 on VALU with 2..4 persistent workgroups per CU,
- * complex FP32 on MFMA, split BF16x3 on MFMA) on the first max_tiles 16 x 16
- * tiles of rows x cols (when these are all the tiles, each reduced form
- * with its FP64 refinement pass as AUTO would run it, provided both batches
- * hold FP64 tensors; on a partial slice the sweep alone), and records the
- * fastest under the key (chi_pad, ceil(log2 n_qubits)); QK_PREC_AUTO then
- * resolves to it for every batch pair with that key. Synchronises the
- * stream. Writes the winner to *chosen (may be NULL).
+ * qk_autotune -- times the sweep forms that meet the stated tolerance, each
+ * at the launch shapes it admits, on the first max_tiles 16 x 16 tiles of
+ * rows x cols (when these are all the tiles, each reduced form with its FP64
+ * refinement pass as AUTO would run it, provided both batches hold FP64
+ * tensors; on a partial slice the sweep alone), and records the fastest
+ * (form, workgroups per CU, band height of the tile order) under the key
+ * (chi_pad, ceil(log2 n_qubits)); QK_PREC_AUTO then resolves to that form
+ * for every batch pair with that key, and launches of that form whose
+ * dominant task has the key use that shape. Candidates where complex FP32
+ * on the matrix cores applies: that form at bands of 2, 4 and 8 tile rows
+ * with one or two workgroups per CU, and split BF16x3; complex FP64 (one or
+ * two workgroups per CU) only when the slice is the whole job. Elsewhere:
+ * complex FP64, and complex FP32 on VALU with 2..4 workgroups per CU at
+ * chi_pad <= 4. The launch shape changes which workgroup computes which
+ * tile, never a result. Synchronises the stream. Writes the winner to
+ * *chosen (may be NULL).
  */
 QK_API qk_status qk_autotune(const qk_mps_batch* rows, const qk_mps_batch* cols,
                              int32_t symmetric, int32_t max_tiles, void* hip_stream,
                              qk_precision* chosen);
 
 /* Tuning table as text, one entry per line: "chi_pad bucket form wg_per_cu
- * us_per_tile". Export writes at most cap bytes (NUL-terminated) and the
- * needed size to *len; import merges a table (INVALID_ARG if malformed). */
+ * band us_per_tile" (an entry without the band, five fields, imports with
+ * band 4). Export writes at most cap bytes (NUL-terminated) and the needed
+ * size to *len; import merges a table (INVALID_ARG if malformed, or a band
+ * outside 1..64). */
 QK_API qk_status qk_tune_export(char* buf, int64_t cap, int64_t* len);
 QK_API qk_status qk_tune_import(const char* text);
 
