@@ -143,3 +143,20 @@ def test_argument_checks_of_preprocessing_and_the_allocation_free_call_without_g
     assert lib.qk_preproc_apply(None, fake, 4, 8, 1.0, fake, 2, None) == INVALID
     assert lib.qk_preproc_release(None) == 0
     assert lib.qk_overlap_gram_noalloc(None, None, 1, 5, fake, 4, None, 0, None, None) == INVALID
+
+
+def test_tuning_table_launch_shape_fields_without_gpu():
+    """Entries carry the launch shape: 'T bucket form wg_per_cu band us'.
+    A five-field entry imports with band 4; a band outside 1..64 or a
+    workgroup count below 1 is rejected; export prints six fields."""
+    import pytest
+
+    import paper_2602_01330_amd.qk as qk
+    mfma = qk.PREC["fp32_mfma"]
+    qk.qk_tune_import(f"4 9 {mfma} 1 8 2.5\n2 3 {mfma} 2 1.25\n")
+    rows = {tuple(l.split()[:2]): l.split() for l in qk.qk_tune_export().strip().splitlines()}
+    assert rows[("4", "9")][2:5] == [str(mfma), "1", "8"] and len(rows[("4", "9")]) == 6
+    assert rows[("2", "3")][2:5] == [str(mfma), "2", "4"]
+    for bad in (f"4 9 {mfma} 1 0 1.0\n", f"4 9 {mfma} 1 65 1.0\n", f"4 9 {mfma} 0 4 1.0\n"):
+        with pytest.raises(qk.QkError):
+            qk.qk_tune_import(bad)
