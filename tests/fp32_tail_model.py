@@ -64,15 +64,16 @@ if __name__ == "__main__":
     pad = mps.pad_batch(built)
     ia, jb = np.triu_indices(N, 1)
     lab = np.arange(N) % 10
-    err, drop = [], []
+    err, drop, lns = [], [], []
     for c0 in range(0, len(ia), 100000):
         sl = slice(c0, c0 + 100000)
         l64, _ = sweep(pad, ia[sl], jb[sl], np.complex128)
         l32, d32 = sweep(pad, ia[sl], jb[sl], np.complex64)
         err.append(np.abs(l32 - l64))
         drop.append(d32)
+        lns.append(l64)
         print(f"{min(c0 + 100000, len(ia))} of {len(ia)} pairs", flush=True)
-    err, drop = np.concatenate(err), np.concatenate(drop)
+    err, drop, lns = np.concatenate(err), np.concatenate(drop), np.concatenate(lns)
     same = lab[ia] == lab[jb]
     print(f"{len(err)} off-diagonal pairs: max |d ln K_q| {err.max():.3g}, "
           f"{(err > 1e-3).sum()} above 1e-3, {(err > 1e-4).sum()} above 1e-4; "
@@ -80,3 +81,5 @@ if __name__ == "__main__":
     tail = err > 1e-3
     print(f"largest 8-site exponent drop: median {np.median(drop):.0f}, max {drop.max():.0f}; "
           f"of the pairs above 1e-3: {np.sort(drop[tail]).astype(int).tolist()}")
+    print(f"ln K_q of the pairs above 1e-3: {lns[tail].min():.1f} to {lns[tail].max():.1f} "
+          f"(all pairs: {lns.min():.1f} to {lns.max():.1f})")
